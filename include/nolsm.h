@@ -1,0 +1,240 @@
+/*
+ * nolsm.h - C ABI of the MI355X (gfx950) NOLSM hot-path library, libnolsm.so.
+ *
+ * The library computes, for every column block J of two block-sparse matrices
+ * K (the Hamiltonian H_0) and S (the overlap), the owned columns of the
+ * non-orthogonal local submatrix purification of Schade et al., Sec. III-B.2
+ * (Eq. purification_submatrix):
+ *
+ *   T_J(D) = 1/2 (I - sign(T_J(S)^-1 T_J(K) - mu I)) T_J(S)^-1,
+ *
+ * with sign() by the Newton-Schulz iteration (Eq. NS1-NS2), and writes those
+ * columns back into a block-sparse D that keeps the merged pattern of K and S
+ * (Sec. III-B.2, write-back step; Fig. 2 steps b-i).
+ *
+ * Conventions for every entry point:
+ *   - All functions are extern "C", never throw, and return NOLSM_OK (0) or a
+ *     negative nolsm_error code; nolsm_strerror() gives a message (the last
+ *     HIP runtime message is appended for NOLSM_E_HIP).
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory of the current device, owned by the caller. The library
+ *     never allocates or frees device memory; the plan owns host memory only.
+ *   - `stream` is a hipStream_t passed as void*. All device work is enqueued
+ *     asynchronously on it; NULL means the legacy default stream.
+ *   - Blocks are bs x bs doubles stored row-major, bs*bs contiguous values per
+ *     block, blocks in block-CSR order (row_ptr / col_idx, columns strictly
+ *     increasing inside a row). This build supports bs = 6 (one molecule of
+ *     the water-like systems) and bs = 1..6 in general.
+ */
+#ifndef NOLSM_H
+#define NOLSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors -- */
+typedef enum {
+    NOLSM_OK = 0,
+    NOLSM_E_ARG = -1,        /* null pointer, bad size or bad option            */
+    NOLSM_E_PATTERN = -2,    /* row_ptr not monotone, column unsorted/duplicate/
+                                out of range, pattern asymmetric, diagonal block
+                                missing, or K and S disagree on nb/bs          */
+    NOLSM_E_WORKSPACE = -3,  /* workspace or metadata buffer too small          */
+    NOLSM_E_HIP = -4,        /* HIP runtime error                               */
+    NOLSM_E_STATE = -5,      /* plan not configured/bound for these options     */
+    NOLSM_E_NOT_SPD = -6,    /* some T_J(S) not positive definite (sync mode)   */
+    NOLSM_E_NOCONV = -7,     /* some sign iteration hit max_iter (sync mode)    */
+    NOLSM_E_NOMEM = -8       /* host allocation failed                          */
+} nolsm_error;
+
+/* Per-molecule status codes, in nolsm_mol_stats.status. */
+enum {
+    NOLSM_MOL_OK = 0,
+    NOLSM_MOL_NOT_SPD = 1,   /* Cholesky pivot <= 0: Dcols left at zero         */
+    NOLSM_MOL_NOCONV = 2     /* max_iter reached without meeting the stop rule  */
+};
+
+/* ------------------------------------------------------------- patterns -- */
+/* A square block-sparse pattern: nb block rows, bs x bs blocks. The arrays
+ * are host memory, read during nolsm_build_submatrices only. */
+typedef struct {
+    int32_t nb;
+    int32_t bs;
+    int64_t nnzb;
+    const int32_t *row_ptr;  /* host, [nb+1], row_ptr[0] = 0, row_ptr[nb] = nnzb */
+    const int32_t *col_idx;  /* host, [nnzb], strictly increasing within a row   */
+} nolsm_pattern;
+
+/* ------------------------------------------------------------- options -- */
+typedef enum {
+    NOLSM_FP64 = 0,          /* everything FP64 (the plain method)              */
+    NOLSM_FP32 = 1,          /* FP64 setup, FP32 Newton-Schulz GEMMs            */
+    NOLSM_FP16 = 2,          /* FP64 setup, FP16-in/FP32-accumulate MFMA GEMMs,
+                                then n_final_fp32 FP32 finishing iterations     */
+    NOLSM_BF16 = 3           /* as FP16 with bfloat16 inputs                    */
+} nolsm_prec;
+
+typedef enum {
+    NOLSM_BOUNDS_GERSHGORIN = 0,   /* c_J = 1/min(||A||_inf, ||A||_1)           */
+    NOLSM_BOUNDS_LEARNED = 1       /* c_J from the spectral-bound MLP, clamped
+                                      at the Gershgorin scale                  */
+} nolsm_bounds;
+
+typedef enum {
+    NOLSM_SCHED_GRAPH = 0,         /* whole batch captured once into a hipGraph
+                                      and launched as one graph                */
+    NOLSM_SCHED_STREAM = 1,        /* same kernels launched directly           */
+    NOLSM_SCHED_PER_BUCKET = 2     /* baseline: one launch per size bucket per
+                                      phase (buckets of 64 rows)               */
+} nolsm_sched;
+
+typedef struct {
+    int32_t prec;            /* nolsm_prec                                       */
+    int32_t n_final_fp32;    /* FP16/BF16: FP32 finishing iterations, 0..2
+                                (default 2), applied column-restricted to Y_J   */
+    double tol;              /* FP64/FP32: stop at ||X^2 - I||_F < tol
+                                (defaults 1e-10 / 1e-5)                          */
+    int32_t max_iter;        /* iteration slots per solve (default 60)           */
+    int32_t fixed_iters;     /* > 0: exactly this many low-precision updates, no
+                                residual test (the paper's fixed step count)    */
+    double switch_theta;     /* FP32/FP16/BF16: stop when r_k > theta r_{k-1}
+                                and r_k < switch_rmax (defaults 0.7, 0.5)        */
+    double switch_rmax;
+    int32_t bounds;          /* nolsm_bounds                                     */
+    const float *d_mlp;      /* device, packed MLP parameters (NOLSM_MLP_NPARAM) */
+    const float *d_mlp_norm; /* device, 24 floats: feature mean[12], std[12]     */
+    float mlp_safety;        /* c_J = 1/(safety * rho_hat); default 1.05         */
+    int32_t sched;           /* nolsm_sched                                      */
+    int32_t sync_errors;     /* != 0: synchronize and return E_NOT_SPD/E_NOCONV  */
+    float *d_features;       /* optional device [nb][12] float: features of A_J  */
+    double debug_scale_mult; /* != 0: multiply c_J (tests of the restart guard)  */
+    int32_t debug_poison_mol;/* >= 0: molecule whose S_J pivot is forced <= 0    */
+} nolsm_solve_opts;
+
+/* Fills *o with the defaults above for precision `prec`. */
+void nolsm_default_opts(nolsm_solve_opts *o, int32_t prec);
+
+/* Per-molecule statistics, written to device memory by nolsm_sign_batch. */
+typedef struct {
+    int32_t iters;           /* Newton-Schulz updates taken in the main precision */
+    int32_t iters_fp32;      /* finishing FP32 iterations (column-restricted)     */
+    int32_t fallback;        /* 1 if the Gershgorin restart was used              */
+    int32_t status;          /* NOLSM_MOL_*                                       */
+    double scale;            /* c_J used for X_0 = c_J A_J                        */
+    double resid;            /* ||X_k^2 - I||_F of the returned iterate           */
+    double trace_SD;         /* N_J = sum_c (S_J Dcols_J)[cJ_c, c]                */
+    double energy_KD;        /* E_J = sum_c (K_J Dcols_J)[cJ_c, c]                */
+} nolsm_mol_stats;
+
+typedef struct nolsm_plan nolsm_plan;
+
+typedef struct {
+    int32_t nb, bs;
+    int64_t sum_m;           /* sum_J m_J = nnzb(D) = number of Dcols blocks      */
+    int32_t m_min, m_max;    /* blocks per submatrix                              */
+    double sum_n3;           /* sum_J n_J^3 (true sizes)                          */
+    int32_t nchunks;         /* after nolsm_plan_configure, else 0                */
+    size_t meta_bytes;       /* device metadata bytes needed by nolsm_plan_bind   */
+    size_t ws_min_bytes;     /* smallest workspace that holds the largest J       */
+    size_t ws_full_bytes;    /* workspace holding the whole batch in one chunk    */
+} nolsm_plan_sizes;
+
+/* ------------------------------------------------------------- the path -- */
+
+/* Plan / index build (Sec. III-B.2 NOLSM generation step; Fig. 2 b-c).
+ * Validates both patterns, merges them (block row I is in the submatrix of
+ * column block J iff K_IJ or S_IJ is stored), and builds N(J) sorted
+ * ascending, p_J = position of J in N(J), the pattern of D (= the merged
+ * pattern) and the scatter positions. Host work only.
+ * Errors: E_ARG (null, nb<1, bs outside 1..6, K/S disagree), E_PATTERN, E_NOMEM.
+ * On success *plan is owned by the caller (nolsm_plan_destroy). */
+int nolsm_build_submatrices(const nolsm_pattern *K, const nolsm_pattern *S,
+                            int32_t flags, nolsm_plan **plan);
+
+/* Sizes of the plan; fields after sum_n3 are zero until configured. */
+int nolsm_plan_info(const nolsm_plan *plan, nolsm_plan_sizes *out);
+
+/* Copies the plan's integer arrays to host buffers (any may be NULL):
+ * sub_ptr[nb+1], sub_blk[sum_m] (N(J) lists), self_pos[nb],
+ * D_row_ptr[nb+1], D_col_idx[sum_m], scatter_pos[sum_m] (index in D's
+ * block-CSR of block (N(J)_a, J), for entry sub_ptr[J]+a). */
+int nolsm_plan_export(const nolsm_plan *plan, int32_t *sub_ptr, int32_t *sub_blk,
+                      int32_t *self_pos, int32_t *D_row_ptr, int32_t *D_col_idx,
+                      int32_t *scatter_pos);
+
+/* Chooses the schedule for `opts` and a workspace of ws_bytes: submatrices
+ * grouped into chunks that fit the workspace, tile lists per chunk. Reports
+ * the device metadata size in *meta_bytes. Host work only.
+ * Errors: E_ARG, E_WORKSPACE (the largest submatrix does not fit). */
+int nolsm_plan_configure(nolsm_plan *plan, const nolsm_solve_opts *opts,
+                         size_t ws_bytes, size_t *meta_bytes);
+
+/* Uploads the configured metadata to d_meta (device, >= meta_bytes, 256-byte
+ * aligned) on `stream` and waits for the copy. d_meta must stay allocated and
+ * unmodified while the plan is used. Errors: E_STATE (not configured),
+ * E_WORKSPACE (too small), E_HIP. */
+int nolsm_plan_bind(nolsm_plan *plan, void *d_meta, size_t meta_bytes, void *stream);
+
+/* The batched sign solve (Eq. purification_submatrix for every J; Fig. 2 e-h
+ * with the element generation replaced by a gather from K and S):
+ *   dK_val, dS_val : device, [nnzb * bs * bs] doubles in K's / S's block-CSR;
+ *   mu             : chemical potential;
+ *   d_ws, ws_bytes : device workspace (>= the size given to configure);
+ *   dDcols         : device, [sum_m * bs * bs] doubles; the rows of molecule J
+ *                    start at element bs*bs*sub_ptr[J]: an n_J x bs row-major
+ *                    block T_J(D)[:, cJ] (so each bs x bs block is contiguous);
+ *   dD_val         : device or NULL; if given, also scattered into D's
+ *                    block-CSR (the merged pattern), [sum_m * bs * bs];
+ *   dstats         : device, [nb] nolsm_mol_stats.
+ * Per-molecule numerical failures are reported in dstats[J].status, which
+ * the caller reads after synchronizing; with opts->sync_errors the call
+ * synchronizes and returns E_NOT_SPD / E_NOCONV if any molecule failed.
+ * Errors: E_ARG, E_STATE (plan not configured/bound for opts->prec,
+ * opts->sched or a larger workspace), E_WORKSPACE, E_HIP. */
+int nolsm_sign_batch(nolsm_plan *plan, const double *dK_val, const double *dS_val,
+                     double mu, const nolsm_solve_opts *opts, void *d_ws,
+                     size_t ws_bytes, double *dDcols, double *dD_val,
+                     nolsm_mol_stats *dstats, void *stream);
+
+/* Write-back (Sec. III-B.2; Fig. 2 h-i): D block (N(J)_a, J) <- rows
+ * bs*a .. bs*a+bs-1 of molecule J's Dcols. dDcols and dD_val are device
+ * arrays of sum_m*bs*bs doubles. Requires a bound plan. */
+int nolsm_assemble_D(const nolsm_plan *plan, const double *dDcols, double *dD_val,
+                     void *stream);
+
+void nolsm_plan_destroy(nolsm_plan *plan);
+const char *nolsm_strerror(int code);
+
+/* ---------------------------------------------- learned spectral bounds -- */
+/* A 12 -> 64 -> 64 -> 2 perceptron (SiLU) mapping features of A_J to the
+ * normalised extremes (lambda_min/G_lo, lambda_max/G_hi). Not in the paper:
+ * it sets the pre-scaling that the paper only requires to exist
+ * (Sec. III-B.2, after Eq. NS2). Parameters: float, packed W1[64][12], b1[64],
+ * W2[64][64], b2[64], W3[2][64], b3[2]. All pointers are device memory. */
+#define NOLSM_MLP_NFEAT 12
+#define NOLSM_MLP_NPARAM 5122
+
+/* out[B][2] = MLP((x[B][12] - mean) / std), norm = mean[12], std[12]. */
+int nolsm_mlp_forward(const float *d_params, const float *d_norm, const float *d_x,
+                      int32_t B, float *d_out, void *stream);
+
+/* Loss = mean over B rows and 2 outputs of w (pred - y)^2, w = 4 where
+ * pred < y, else 1. Writes *d_loss (1 float) and d_grad[NPARAM] (overwritten,
+ * not accumulated). d_x are raw features (normalised inside with d_norm). */
+int nolsm_mlp_loss_grad(const float *d_params, const float *d_norm, const float *d_x,
+                        const float *d_y, int32_t B, float *d_grad, float *d_loss,
+                        void *stream);
+
+/* One Adam step with bias correction (t counts from 1) on all NPARAM values. */
+int nolsm_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v,
+                   int32_t t, float lr, float beta1, float beta2, float eps,
+                   void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NOLSM_H */

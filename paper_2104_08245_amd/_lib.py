@@ -1,0 +1,120 @@
+"""ctypes binding of libnolsm.so: the same entry points as include/nolsm.h,
+argument marshalling only. Raises if the library has not been built."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnolsm.so")
+
+NOLSM_OK = 0
+E_ARG, E_PATTERN, E_WORKSPACE, E_HIP, E_STATE, E_NOT_SPD, E_NOCONV, E_NOMEM = range(-1, -9, -1)
+MOL_OK, MOL_NOT_SPD, MOL_NOCONV = 0, 1, 2
+FP64, FP32, FP16, BF16 = 0, 1, 2, 3
+PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
+BOUNDS_GERSHGORIN, BOUNDS_LEARNED = 0, 1
+SCHED_GRAPH, SCHED_STREAM, SCHED_PER_BUCKET = 0, 1, 2
+MLP_NFEAT = 12
+MLP_NPARAM = 5122
+
+
+class NolsmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"nolsm error {code}: {msg}")
+        self.code = code
+
+
+class Pattern(C.Structure):
+    _fields_ = [("nb", C.c_int32), ("bs", C.c_int32), ("nnzb", C.c_int64),
+                ("row_ptr", C.POINTER(C.c_int32)), ("col_idx", C.POINTER(C.c_int32))]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("prec", C.c_int32), ("n_final_fp32", C.c_int32), ("tol", C.c_double),
+                ("max_iter", C.c_int32), ("fixed_iters", C.c_int32),
+                ("switch_theta", C.c_double), ("switch_rmax", C.c_double),
+                ("bounds", C.c_int32), ("d_mlp", C.c_void_p), ("d_mlp_norm", C.c_void_p),
+                ("mlp_safety", C.c_float), ("sched", C.c_int32), ("sync_errors", C.c_int32),
+                ("d_features", C.c_void_p), ("debug_scale_mult", C.c_double),
+                ("debug_poison_mol", C.c_int32)]
+
+
+class MolStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("iters_fp32", C.c_int32), ("fallback", C.c_int32),
+                ("status", C.c_int32), ("scale", C.c_double), ("resid", C.c_double),
+                ("trace_SD", C.c_double), ("energy_KD", C.c_double)]
+
+
+MOLSTATS_DTYPE = [("iters", "<i4"), ("iters_fp32", "<i4"), ("fallback", "<i4"), ("status", "<i4"),
+                  ("scale", "<f8"), ("resid", "<f8"), ("trace_SD", "<f8"), ("energy_KD", "<f8")]
+
+
+class PlanSizes(C.Structure):
+    _fields_ = [("nb", C.c_int32), ("bs", C.c_int32), ("sum_m", C.c_int64),
+                ("m_min", C.c_int32), ("m_max", C.c_int32), ("sum_n3", C.c_double),
+                ("nchunks", C.c_int32), ("meta_bytes", C.c_size_t),
+                ("ws_min_bytes", C.c_size_t), ("ws_full_bytes", C.c_size_t)]
+
+
+EXPORTED = ["nolsm_default_opts", "nolsm_build_submatrices", "nolsm_plan_info", "nolsm_plan_export",
+            "nolsm_plan_configure", "nolsm_plan_bind", "nolsm_sign_batch", "nolsm_assemble_D",
+            "nolsm_plan_destroy", "nolsm_strerror", "nolsm_mlp_forward", "nolsm_mlp_loss_grad",
+            "nolsm_mlp_adam"]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2104_08245_amd/build.py "
+                          "(there is no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, sz, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t, C.c_double
+    p_i32 = C.POINTER(C.c_int32)
+    L.nolsm_default_opts.argtypes = [C.POINTER(SolveOpts), i32]
+    L.nolsm_default_opts.restype = None
+    L.nolsm_build_submatrices.argtypes = [C.POINTER(Pattern), C.POINTER(Pattern), i32, C.POINTER(vp)]
+    L.nolsm_plan_info.argtypes = [vp, C.POINTER(PlanSizes)]
+    L.nolsm_plan_export.argtypes = [vp, p_i32, p_i32, p_i32, p_i32, p_i32, p_i32]
+    L.nolsm_plan_configure.argtypes = [vp, C.POINTER(SolveOpts), sz, C.POINTER(sz)]
+    L.nolsm_plan_bind.argtypes = [vp, vp, sz, vp]
+    L.nolsm_sign_batch.argtypes = [vp, vp, vp, dbl, C.POINTER(SolveOpts), vp, sz, vp, vp, vp, vp]
+    L.nolsm_assemble_D.argtypes = [vp, vp, vp, vp]
+    L.nolsm_plan_destroy.argtypes = [vp]
+    L.nolsm_plan_destroy.restype = None
+    L.nolsm_strerror.argtypes = [C.c_int]
+    L.nolsm_strerror.restype = C.c_char_p
+    L.nolsm_mlp_forward.argtypes = [vp, vp, vp, i32, vp, vp]
+    L.nolsm_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
+    L.nolsm_mlp_adam.argtypes = [vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+    for name in EXPORTED:
+        f = getattr(L, name)
+        if f.restype is C.c_int or name not in ("nolsm_default_opts", "nolsm_plan_destroy", "nolsm_strerror"):
+            if name not in ("nolsm_default_opts", "nolsm_plan_destroy", "nolsm_strerror"):
+                f.restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(rc):
+    if rc != NOLSM_OK:
+        raise NolsmError(rc, lib().nolsm_strerror(rc).decode())
+    return rc
+
+
+def i32_ptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def default_opts(prec="fp64", **kw):
+    o = SolveOpts()
+    lib().nolsm_default_opts(C.byref(o), PREC[prec] if isinstance(prec, str) else int(prec))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o

@@ -1,0 +1,229 @@
+// Runtime entry points: bind, the batched sign solve, write-back.
+//
+// One call of nolsm_sign_batch runs, for every chunk of submatrices that fits
+// the workspace: gather -> Cholesky -> substitution -> bounds -> X_0 ->
+// max_iter Newton-Schulz iteration slots (two GEMM launches each; finished
+// submatrices drop out inside the kernels) -> finishing products ->
+// extraction / traces / write-back. With NOLSM_SCHED_GRAPH on a non-null
+// stream the whole sequence is captured once into a hipGraph and replayed by
+// later calls with the same buffers and options.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "plan.h"
+
+static int hip_fail(hipError_t e, const char *where) {
+    nolsm_set_last_error(std::string(where) + ": " + hipGetErrorString(e));
+    return NOLSM_E_HIP;
+}
+
+static void drop_graph(nolsm_plan *pl) {
+    if (pl->graph_exec) {
+        (void)hipGraphExecDestroy((hipGraphExec_t)pl->graph_exec);
+        pl->graph_exec = nullptr;
+    }
+}
+
+extern "C" int nolsm_plan_bind(nolsm_plan *pl, void *d_meta, size_t bytes, void *stream) {
+    if (!pl || !d_meta) { nolsm_set_last_error("bind: null argument"); return NOLSM_E_ARG; }
+    if (!pl->configured) { nolsm_set_last_error("bind: plan not configured"); return NOLSM_E_STATE; }
+    if (bytes < pl->image.size()) { nolsm_set_last_error("bind: metadata buffer too small"); return NOLSM_E_WORKSPACE; }
+    if (((uintptr_t)d_meta) & 255) { nolsm_set_last_error("bind: d_meta must be 256-byte aligned"); return NOLSM_E_ARG; }
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = nolsm_kernels_init();
+    if (e != hipSuccess) return hip_fail(e, "kernel attributes");
+    e = hipMemcpyAsync(d_meta, pl->image.data(), pl->image.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "metadata upload");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "metadata upload sync");
+    drop_graph(pl);
+    pl->d_meta = d_meta;
+    pl->bound = true;
+    (void)hipGetDevice(&pl->device);
+    return NOLSM_OK;
+}
+
+static ChunkDev chunk_dev(const nolsm_plan *pl, const HostChunk &ch, char *ws) {
+    const char *base = (const char *)pl->d_meta;
+    ChunkDev cd;
+    cd.meta = (const SubMeta *)(base + ch.o_meta);
+    cd.t_subst = (const uint32_t *)(base + ch.o_subst);
+    cd.t_conv = (const uint32_t *)(base + ch.o_conv);
+    cd.t_ns = (const uint32_t *)(base + ch.o_ns);
+    cd.t_rows = (const uint32_t *)(base + ch.o_rows);
+    cd.ctl = (SubCtl *)(ws + ch.off_ctl);
+    cd.nsub = (int32_t)ch.meta.size();
+    cd.n_subst = (int32_t)ch.t_subst.size();
+    cd.n_conv = (int32_t)ch.t_conv.size();
+    cd.n_ns = (int32_t)ch.t_ns.size();
+    cd.n_rows = (int32_t)ch.t_rows.size();
+    cd.max_m = ch.max_m;
+    cd.max_np = ch.max_np;
+    return cd;
+}
+
+struct BatchArgs {
+    const double *dK, *dS;
+    double mu;
+    const nolsm_solve_opts *o;
+    char *ws;
+    double *dDcols, *dD;
+    void *dstats;
+};
+
+static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st) {
+    const char *base = (const char *)pl->d_meta;
+    const nolsm_solve_opts &o = *b.o;
+    GatherArgs ga;
+    ga.Krp = (const int32_t *)(base + pl->o_Krp);
+    ga.Kci = (const int32_t *)(base + pl->o_Kci);
+    ga.Srp = (const int32_t *)(base + pl->o_Srp);
+    ga.Sci = (const int32_t *)(base + pl->o_Sci);
+    ga.sub_blk = (const int32_t *)(base + pl->o_sub_blk);
+    ga.Kval = b.dK;
+    ga.Sval = b.dS;
+    ga.bs = pl->bs;
+    ga.poison_J = o.debug_poison_mol;
+    BoundsArgs ba;
+    ba.d_mlp = o.d_mlp;
+    ba.d_norm = o.d_mlp_norm;
+    ba.d_features = o.d_features;
+    ba.safety = o.mlp_safety > 0 ? o.mlp_safety : 1.05f;
+    ba.learned = o.bounds == NOLSM_BOUNDS_LEARNED;
+    ba.scale_mult = o.debug_scale_mult;
+    NsArgs na;
+    na.prec = o.prec;
+    na.max_iter = o.max_iter;
+    na.fixed_iters = o.fixed_iters;
+    na.allow_restart = 1;
+    na.tol = o.tol;
+    na.theta = o.switch_theta > 0 ? o.switch_theta : 0.7;
+    na.rmax = o.switch_rmax > 0 ? o.switch_rmax : 0.5;
+    FinishArgs fa;
+    fa.prec = o.prec;
+    fa.nfinal = (o.prec == NOLSM_FP16 || o.prec == NOLSM_BF16) ? o.n_final_fp32 : 0;
+    ExtractArgs ea;
+    ea.Krp = ga.Krp; ea.Kci = ga.Kci; ea.Srp = ga.Srp; ea.Sci = ga.Sci;
+    ea.sub_blk = ga.sub_blk;
+    ea.scatter_pos = (const int32_t *)(base + pl->o_scatter);
+    ea.Kval = b.dK;
+    ea.Sval = b.dS;
+    ea.Dcols = b.dDcols;
+    ea.Dval = b.dD;
+    ea.stats = b.dstats;
+    ea.bs = pl->bs;
+    ea.prec = o.prec;
+    ea.nfinal = fa.nfinal;
+    for (const HostChunk &ch : pl->chunks) {
+        const ChunkDev cd = chunk_dev(pl, ch, b.ws);
+        hipError_t e = launch_setup(cd, b.ws, ga, ba, b.mu, o.prec, st);
+        if (e != hipSuccess) return hip_fail(e, "setup launch");
+        for (int it = 0; it < o.max_iter; ++it) {
+            e = launch_ns_iter(cd, b.ws, na, it, st);
+            if (e != hipSuccess) return hip_fail(e, "Newton-Schulz launch");
+        }
+        e = launch_finish(cd, b.ws, fa, st);
+        if (e != hipSuccess) return hip_fail(e, "finish launch");
+        e = launch_extract(cd, b.ws, ea, st);
+        if (e != hipSuccess) return hip_fail(e, "extract launch");
+    }
+    return NOLSM_OK;
+}
+
+static bool same_opts(const nolsm_solve_opts &a, const nolsm_solve_opts &b) {
+    return std::memcmp(&a, &b, sizeof(a)) == 0;
+}
+
+extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const double *dS_val, double mu,
+                                const nolsm_solve_opts *opts, void *d_ws, size_t ws_bytes, double *dDcols,
+                                double *dD_val, nolsm_mol_stats *dstats, void *stream) {
+    if (!pl || !dK_val || !dS_val || !opts || !d_ws || !dDcols || !dstats) {
+        nolsm_set_last_error("sign_batch: null argument");
+        return NOLSM_E_ARG;
+    }
+    if (!pl->bound) { nolsm_set_last_error("sign_batch: plan not bound"); return NOLSM_E_STATE; }
+    if (opts->prec != pl->prec || opts->max_iter != pl->max_iter ||
+        ((opts->sched == NOLSM_SCHED_PER_BUCKET) != (pl->sched == NOLSM_SCHED_PER_BUCKET))) {
+        nolsm_set_last_error("sign_batch: options differ from the configured ones");
+        return NOLSM_E_STATE;
+    }
+    if (opts->bounds == NOLSM_BOUNDS_LEARNED && (!opts->d_mlp || !opts->d_mlp_norm)) {
+        nolsm_set_last_error("sign_batch: learned bounds need d_mlp and d_mlp_norm");
+        return NOLSM_E_ARG;
+    }
+    if (opts->prec != NOLSM_FP64 && opts->prec != NOLSM_FP32 && (opts->n_final_fp32 < 0 || opts->n_final_fp32 > 2)) {
+        nolsm_set_last_error("sign_batch: n_final_fp32 must be 0..2");
+        return NOLSM_E_ARG;
+    }
+    if (ws_bytes < pl->ws_bytes) { nolsm_set_last_error("sign_batch: workspace smaller than configured"); return NOLSM_E_WORKSPACE; }
+    if (((uintptr_t)d_ws) & 255) { nolsm_set_last_error("sign_batch: workspace must be 256-byte aligned"); return NOLSM_E_ARG; }
+    hipStream_t st = (hipStream_t)stream;
+    BatchArgs b{dK_val, dS_val, mu, opts, (char *)d_ws, dDcols, dD_val, (void *)dstats};
+    int rc;
+    if (opts->sched == NOLSM_SCHED_GRAPH && st != nullptr) {
+        const void *key[6] = {dK_val, dS_val, d_ws, dDcols, dD_val, dstats};
+        bool hit = pl->graph_exec && pl->g_mu == mu && pl->g_stream == stream && same_opts(pl->g_opts, *opts);
+        for (int i = 0; i < 6 && hit; ++i) hit = pl->g_key[i] == key[i];
+        if (!hit) {
+            drop_graph(pl);
+            hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e, "graph capture begin");
+            rc = enqueue(pl, b, st);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(st, &g);
+            if (rc != NOLSM_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return hip_fail(e, "graph capture end");
+            hipGraphExec_t ex = nullptr;
+            e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+            pl->graph_exec = ex;
+            for (int i = 0; i < 6; ++i) pl->g_key[i] = key[i];
+            pl->g_mu = mu;
+            pl->g_opts = *opts;
+            pl->g_stream = stream;
+        }
+        hipError_t e = hipGraphLaunch((hipGraphExec_t)pl->graph_exec, st);
+        if (e != hipSuccess) return hip_fail(e, "graph launch");
+        rc = NOLSM_OK;
+    } else {
+        rc = enqueue(pl, b, st);
+        if (rc != NOLSM_OK) return rc;
+    }
+    if (opts->sync_errors) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "sync");
+        std::vector<nolsm_mol_stats> hs(pl->nb);
+        e = hipMemcpy(hs.data(), dstats, sizeof(nolsm_mol_stats) * pl->nb, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "stats read-back");
+        for (const auto &s : hs) {
+            if (s.status == NOLSM_MOL_NOT_SPD) { nolsm_set_last_error("molecule not SPD"); return NOLSM_E_NOT_SPD; }
+        }
+        for (const auto &s : hs) {
+            if (s.status == NOLSM_MOL_NOCONV) { nolsm_set_last_error("molecule did not converge"); return NOLSM_E_NOCONV; }
+        }
+    }
+    return NOLSM_OK;
+}
+
+extern "C" int nolsm_assemble_D(const nolsm_plan *pl, const double *dDcols, double *dD_val, void *stream) {
+    if (!pl || !dDcols || !dD_val) return NOLSM_E_ARG;
+    if (!pl->bound) return NOLSM_E_STATE;
+    const int32_t *sp = (const int32_t *)((const char *)pl->d_meta + pl->o_scatter);
+    hipError_t e = launch_assemble(dDcols, dD_val, sp, (int64_t)pl->sub_blk.size(), pl->bs, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "assemble launch");
+    return NOLSM_OK;
+}
+
+extern "C" void nolsm_plan_destroy(nolsm_plan *pl) {
+    if (!pl) return;
+    drop_graph(pl);
+    delete pl;
+}

@@ -1,0 +1,266 @@
+// Finishing iterations, extraction of the owned columns, traces, write-back.
+//
+// Only the owned columns of T_J(D) are needed (Sec. III-B.2, write-back step):
+//   T_J(D)[:, cJ] = (Y_J - sign(A_J) Y_J) / 2,   Y_J = T_J(S)^-1 E_cJ.
+// With the low-precision iterate P = X_K, f further Newton-Schulz steps
+// (Eq. NS1) applied only to the n x bs block Y_J are exact rewrites of full
+// FP32 iterations:
+//   X_{K+1} v = (3 P v - P^3 v) / 2,   X_{K+2} Y = (3 w1 - w3) / 2 with
+//   w1 = X_{K+1} Y, w3 = X_{K+1}^2 w1,
+// i.e. 3^f products of P with n x bs blocks ("column-restricted" finishing,
+// O(n^2) work instead of full GEMMs).
+#include "dev_common.h"
+#include "kernels.h"
+
+struct SkinnyArgs {
+    int32_t ina, inb;      // input vectors (index, -1 = Y_J, -2 = none)
+    double alpha, beta;    // in = alpha * ina + beta * inb
+    int32_t out;           // output vector index
+    int32_t save;          // if >= 0: also store `in` (this workgroup's rows)
+};
+
+template <typename TP> struct Dec;
+template <> struct Dec<double> { typedef double storage; static __device__ __forceinline__ double get(double x) { return x; } };
+template <> struct Dec<float> { typedef float storage; static __device__ __forceinline__ float get(float x) { return x; } };
+struct F16 {};
+struct BF16 {};
+template <> struct Dec<F16> {
+    typedef uint16_t storage;
+    static __device__ __forceinline__ float get(uint16_t x) { return (float)__builtin_bit_cast(_Float16, x); }
+};
+template <> struct Dec<BF16> {
+    typedef uint16_t storage;
+    static __device__ __forceinline__ float get(uint16_t x) { return (float)__builtin_bit_cast(__bf16, x); }
+};
+
+#define BSMAX 6
+
+template <typename TV>
+__device__ __forceinline__ TV vec_in(const SkinnyArgs &a, const SubMeta &M, const char *ws, int row, int j) {
+    const int np = M.np;
+    const TV *V = (const TV *)(ws + M.offVec);
+    const int64_t vs = (int64_t)np * 6 * 8 / sizeof(TV);   // stride between vectors
+    auto get = [&](int idx) -> TV {
+        if (idx == -1) return (TV)((const double *)(ws + M.offK))[(int64_t)row * (np + 64) + np + j];
+        return V[(int64_t)idx * vs + (int64_t)row * 6 + j];
+    };
+    TV v = (TV)a.alpha * get(a.ina);
+    if (a.inb >= -1) v += (TV)a.beta * get(a.inb);
+    return v;
+}
+
+// out = P * in for 64 rows per workgroup; wave w takes rows 16w..16w+15,
+// lanes split the columns, then a butterfly reduction across the wave.
+template <typename TP, typename TV>
+__global__ __launch_bounds__(256) void k_skinny(ChunkDev cd, char *ws, SkinnyArgs sa, int bs) {
+    typedef typename Dec<TP>::storage ST;
+    const uint32_t task = xcd_task(cd.t_rows);
+    if (task == NOLSM_TASK_NONE) return;
+    const int s = task_slot(task), rb = task_a(task);
+    const SubMeta M = cd.meta[s];
+    const SubCtl *ctl = cd.ctl + s;
+    if (ctl->status == NOLSM_MOL_NOT_SPD) return;
+    const int np = M.np;
+    const int K = ctl->iters;
+    const ST *P = (const ST *)(ws + ((K & 1) ? M.offX1 : M.offL));
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    TV acc[16][BSMAX];
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+#pragma unroll
+        for (int j = 0; j < BSMAX; ++j) acc[r][j] = 0;
+    const int rbase = rb * 64 + w * 16;
+    for (int c = l; c < np; c += 64) {
+        TV in[BSMAX];
+#pragma unroll
+        for (int j = 0; j < BSMAX; ++j) in[j] = (j < bs) ? vec_in<TV>(sa, M, ws, c, j) : (TV)0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const TV p = (TV)Dec<TP>::get(P[(int64_t)(rbase + r) * np + c]);
+#pragma unroll
+            for (int j = 0; j < BSMAX; ++j) acc[r][j] += p * in[j];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+#pragma unroll
+        for (int j = 0; j < BSMAX; ++j) {
+            TV v = acc[r][j];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            acc[r][j] = v;
+        }
+    TV *V = (TV *)(ws + M.offVec);
+    const int64_t vs = (int64_t)np * 6 * 8 / sizeof(TV);
+    if (l == 0) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+#pragma unroll
+            for (int j = 0; j < BSMAX; ++j)
+                if (j < bs) V[(int64_t)sa.out * vs + (int64_t)(rbase + r) * 6 + j] = acc[r][j];
+    }
+    if (sa.save >= 0) {
+        for (int f = threadIdx.x; f < 64 * bs; f += 256) {
+            const int r = rb * 64 + f / bs, j = f % bs;
+            V[(int64_t)sa.save * vs + (int64_t)r * 6 + j] = vec_in<TV>(sa, M, ws, r, j);
+        }
+    }
+}
+
+template <typename TP, typename TV>
+static hipError_t run_finish(const ChunkDev &cd, char *ws, int nfinal, int bs, hipStream_t st) {
+    auto L = [&](int ina, int inb, double al, double be, int out, int save) {
+        SkinnyArgs a{ina, inb, al, be, out, save};
+        hipLaunchKernelGGL((k_skinny<TP, TV>), dim3(cd.n_rows), dim3(256), 0, st, cd, ws, a, bs);
+        return hipGetLastError();
+    };
+    hipError_t e;
+    if ((e = L(-1, -2, 1.0, 0.0, 0, -1))) return e;              // u1 = P Y
+    if (nfinal == 0) return hipSuccess;
+    if ((e = L(0, -2, 1.0, 0.0, 1, -1))) return e;               // u2 = P u1
+    if ((e = L(1, -2, 1.0, 0.0, 2, -1))) return e;               // u3 = P u2
+    if (nfinal == 1) return hipSuccess;                          // w1 = (3u1 - u3)/2
+    if ((e = L(0, 2, 1.5, -0.5, 4, 3))) return e;                // p1 = P w1, save w1
+    if ((e = L(4, -2, 1.0, 0.0, 5, -1))) return e;               // p2
+    if ((e = L(5, -2, 1.0, 0.0, 6, -1))) return e;               // p3
+    if ((e = L(4, 6, 1.5, -0.5, 8, 7))) return e;                // q1 = P w2, save w2
+    if ((e = L(8, -2, 1.0, 0.0, 9, -1))) return e;               // q2
+    if ((e = L(9, -2, 1.0, 0.0, 10, -1))) return e;              // q3
+    return hipSuccess;                                           // Z = 1.5 w1 - 0.75 q1 + 0.25 q3
+}
+
+hipError_t launch_finish(const ChunkDev &cd, char *ws, const FinishArgs &fa, hipStream_t st) {
+    const int bs = 6;
+    switch (fa.prec) {
+        case NOLSM_FP64: return run_finish<double, double>(cd, ws, 0, bs, st);
+        case NOLSM_FP32: return run_finish<float, float>(cd, ws, 0, bs, st);
+        case NOLSM_FP16: return run_finish<F16, float>(cd, ws, fa.nfinal, bs, st);
+        default: return run_finish<BF16, float>(cd, ws, fa.nfinal, bs, st);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Extraction, traces and write-back, one workgroup per submatrix.
+//   Dcols_J = (Y_J - Z_J) / 2 (FP64), Z_J = X Y_J from the products above;
+//   N_J = sum_c (S_J Dcols_J)[bs p + c, c], E_J = sum_c (K_J Dcols_J)[bs p + c, c]
+// (Eq. e_elec: the energy only needs D where K is stored; row J of K / S
+// holds every block of those rows inside N(J)). FP64 accumulation.
+// ---------------------------------------------------------------------------
+struct MolStatsDev {
+    int32_t iters, iters_fp32, fallback, status;
+    double scale, resid, trace_SD, energy_KD;
+};
+
+template <typename TV>
+__global__ __launch_bounds__(256) void k_extract(ChunkDev cd, char *ws, ExtractArgs ea) {
+    extern __shared__ double smem[];
+    __shared__ double red[256];
+    const int s = blockIdx.x;
+    if (s >= cd.nsub) return;
+    const SubMeta M = cd.meta[s];
+    const SubCtl *ctl = cd.ctl + s;
+    const int bs = ea.bs, n = M.n, np = M.np, J = M.J, t = threadIdx.x;
+    double *Dc = smem;                                    // n x bs
+    int *list = (int *)(smem + (size_t)cd.max_np * bs);
+    for (int i = t; i < M.m; i += 256) list[i] = ea.sub_blk[M.sub_off + i];
+    const bool ok = ctl->status != NOLSM_MOL_NOT_SPD;
+    const double *Kb = (const double *)(ws + M.offK);
+    const TV *V = (const TV *)(ws + M.offVec);
+    const int64_t vs = (int64_t)np * 6 * 8 / sizeof(TV);
+    double *Dout = ea.Dcols + (int64_t)bs * bs * M.sub_off;
+    for (int f = t; f < n * bs; f += 256) {
+        const int r = f / bs, c = f % bs;
+        double v = 0.0;
+        if (ok) {
+            const double y = Kb[(int64_t)r * (np + 64) + np + c];
+            const int64_t o = (int64_t)r * 6 + c;
+            double z;
+            if (ea.nfinal == 0)
+                z = (double)V[o];
+            else if (ea.nfinal == 1)
+                z = 1.5 * (double)V[o] - 0.5 * (double)V[2 * vs + o];
+            else
+                z = 1.5 * (double)V[3 * vs + o] - 0.75 * (double)V[8 * vs + o] + 0.25 * (double)V[10 * vs + o];
+            v = 0.5 * (y - z);
+        }
+        Dc[f] = v;
+        Dout[f] = v;
+    }
+    __syncthreads();
+    // traces over row J of S and of K
+    double tr[2];
+    for (int which = 0; which < 2; ++which) {
+        const int *rp = which ? ea.Krp : ea.Srp;
+        const int *ci = which ? ea.Kci : ea.Sci;
+        const double *val = which ? ea.Kval : ea.Sval;
+        const int lo = rp[J], hi = rp[J + 1];
+        const int nel = (hi - lo) * bs * bs;
+        double part = 0.0;
+        for (int f = t; f < nel; f += 256) {
+            const int e = lo + f / (bs * bs), rc = f % (bs * bs);
+            const int c = rc / bs, d = rc % bs;
+            const int C = ci[e];
+            int l = 0, h = M.m - 1, b = -1;
+            while (l <= h) {
+                const int mid = (l + h) >> 1;
+                const int v = list[mid];
+                if (v == C) { b = mid; break; }
+                if (v < C) l = mid + 1; else h = mid - 1;
+            }
+            if (b >= 0) part += val[(int64_t)e * bs * bs + rc] * Dc[(b * bs + d) * bs + c];
+        }
+        tr[which] = block_sum(part, red);
+    }
+    if (ea.Dval) {
+        for (int f = t; f < M.m * bs * bs; f += 256) {
+            const int a = f / (bs * bs), rc = f % (bs * bs);
+            const int64_t pos = ea.scatter_pos[M.sub_off + a];
+            ea.Dval[pos * bs * bs + rc] = Dc[(int64_t)a * bs * bs + rc];
+        }
+    }
+    if (t == 0) {
+        MolStatsDev *st = (MolStatsDev *)ea.stats + J;
+        st->iters = ctl->iters;
+        st->iters_fp32 = (ok && (ea.prec == NOLSM_FP16 || ea.prec == NOLSM_BF16)) ? ea.nfinal : 0;
+        st->fallback = ctl->fallback;
+        st->status = ctl->status;
+        st->scale = ctl->scale;
+        st->resid = ctl->resid;
+        st->trace_SD = ok ? tr[0] : 0.0;
+        st->energy_KD = ok ? tr[1] : 0.0;
+    }
+}
+
+hipError_t launch_extract(const ChunkDev &cd, char *ws, const ExtractArgs &ea, hipStream_t st) {
+    const size_t lds = (size_t)cd.max_np * ea.bs * 8 + (size_t)cd.max_m * 4 + 16;
+    if (ea.prec == NOLSM_FP64)
+        hipLaunchKernelGGL(k_extract<double>, dim3(cd.nsub), dim3(256), lds, st, cd, ws, ea);
+    else
+        hipLaunchKernelGGL(k_extract<float>, dim3(cd.nsub), dim3(256), lds, st, cd, ws, ea);
+    return hipGetLastError();
+}
+
+__global__ void k_assemble(const double *Dcols, double *Dval, const int32_t *scatter_pos, int64_t sum_m, int bs) {
+    const int64_t total = sum_m * bs * bs;
+    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < total; f += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = f / (bs * bs), rc = f % (bs * bs);
+        Dval[(int64_t)scatter_pos[k] * bs * bs + rc] = Dcols[f];
+    }
+}
+
+hipError_t launch_assemble(const double *Dcols, double *Dval, const int32_t *scatter_pos, int64_t sum_m,
+                           int32_t bs, hipStream_t st) {
+    const int64_t total = sum_m * bs * bs;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_assemble, dim3((unsigned)blocks), dim3(256), 0, st, Dcols, Dval, scatter_pos, sum_m, bs);
+    return hipGetLastError();
+}
+
+hipError_t nolsm_finish_init() {
+    return hipFuncSetAttribute((const void *)k_extract<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) ||
+                   hipFuncSetAttribute((const void *)k_extract<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024)
+               ? hipErrorInvalidValue
+               : hipSuccess;
+}

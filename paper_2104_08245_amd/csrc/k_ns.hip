@@ -1,0 +1,372 @@
+// Newton-Schulz sign iteration on the matrix cores (Sec. III-B.2, Eq. NS1-NS2;
+// Sec. III-C.3: the iteration runs as GEMMs in mixed precision).
+//
+// One iteration is two batched GEMM launches over the tiles of every active
+// submatrix of a chunk:
+//   mode 1: T = X_k X_k; epilogue: partial sums of ||T - I||_F^2 per tile and
+//           B = 3I - T stored in the iteration precision;
+//   mode 2: every workgroup of a submatrix reads the finished residual
+//           r_k = ||X_k^2 - I||_F, takes the same stop/continue/restart
+//           decision, and if continuing writes X_{k+1} = X_k B / 2.
+// X ping-pongs between two buffers (X_k in buffer k % 2). Precisions:
+// FP64 / FP32 use 64x64 tiles on v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4;
+// FP16 / BF16 use 128x128 tiles on v_mfma_f32_32x32x16_{f16,bf16} with FP32
+// accumulation.
+#include "dev_common.h"
+#include "kernels.h"
+
+enum { ACT_STOP = 0, ACT_UPDATE = 1, ACT_RESTART = 2 };
+
+// Decision of mode 2 at iteration `it`. Computed by thread 0 of every
+// workgroup of the submatrix from data that is final before this launch
+// (the residual partials of mode 1 and rhist[0..it-1]); the tile-0
+// workgroup records it.
+__device__ int ns_decide(const NsArgs &na, const SubMeta &M, SubCtl *ctl, const char *ws, int it,
+                         int tile) {
+    const double *res = (const double *)(ws + M.offRes) + (int64_t)it * M.ntile_ns;
+    double ssum = 0.0;
+    for (int i = 0; i < M.ntile_ns; ++i) ssum += res[i];
+    const double r = sqrt(ssum);
+    const double rprev = it > 0 ? ctl->rhist[it - 1] : INFINITY;
+    bool stop;
+    if (na.fixed_iters > 0)
+        stop = it >= na.fixed_iters;
+    else if (na.prec == NOLSM_FP64)
+        stop = r < na.tol;
+    else
+        stop = (na.tol > 0.0 && r < na.tol) || (it >= 1 && r < na.rmax && r > na.theta * rprev);
+    const bool diverge = !isfinite(r) || (it >= 1 && r > 2.0 * rprev && r > 1.0);
+    const int ra = ctl->restart_at;
+    int act;
+    bool noconv = false;
+    if (diverge && na.allow_restart && (ra < 0 || ra == it + 1)) {
+        act = ACT_RESTART;
+    } else if (diverge) {
+        act = ACT_STOP;
+        noconv = true;
+    } else if (stop) {
+        act = ACT_STOP;
+    } else if (it + 1 >= na.max_iter) {
+        act = ACT_STOP;
+        noconv = na.fixed_iters <= 0;
+    } else {
+        act = ACT_UPDATE;
+    }
+    if (tile == 0) {
+        ctl->rhist[it] = r;
+        if (act == ACT_STOP) {
+            ctl->iters = it;
+            ctl->resid = r;
+            if (noconv) ctl->status = NOLSM_MOL_NOCONV;
+            ctl->done = 1;
+        } else if (act == ACT_RESTART) {
+            ctl->fallback = 1;
+            ctl->restart_at = it + 1;
+            ctl->scale = ctl->scale_g;
+        }
+    }
+    return act;
+}
+
+template <typename T> __device__ __forceinline__ T to_t(float x);
+template <> __device__ __forceinline__ double to_t<double>(float x) { return x; }
+template <> __device__ __forceinline__ float to_t<float>(float x) { return x; }
+template <typename T> __device__ __forceinline__ T to_t_d(double x) { return (T)x; }
+
+// X_{k+1} tile <- c_G A on [0,n)^2, identity on the padding (restart)
+template <typename T, typename Cvt>
+__device__ void restart_tile(const SubMeta &M, const SubCtl *ctl, const char *ws, T *Xn, int r0, int c0,
+                             int rows, int cols, Cvt cvt) {
+    const double *A = (const double *)(ws + M.offK);
+    const int64_t ldk = M.np + 64;
+    const double c = ctl->scale_g;
+    for (int f = threadIdx.x; f < rows * cols; f += blockDim.x) {
+        const int r = r0 + f / cols, q = c0 + f % cols;
+        if (r >= M.np || q >= M.np) continue;
+        const double v = (r < M.n && q < M.n) ? c * A[(int64_t)r * ldk + q] : (r == q ? 1.0 : 0.0);
+        Xn[(int64_t)r * M.np + q] = cvt(v);
+    }
+}
+
+// ------------------------------------------------------------ FP64 / FP32
+template <typename T> struct Mma16;
+template <> struct Mma16<double> {
+    typedef v4d acc_t;
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mma16<float> {
+    typedef v4f acc_t;
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void g2s_t(T (*s)[LDP], const T *g, int64_t ld) {
+    const int t = threadIdx.x;
+    const int c4 = (t & 15) * 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = i * 16 + (t >> 4);
+        const T *p = g + (int64_t)r * ld + c4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s[r][c4 + e] = p[e];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ns64(ChunkDev cd, char *ws, NsArgs na, int it, int mode) {
+    typedef typename Mma16<T>::acc_t acc_t;
+    __shared__ T sA[64][LDP];
+    __shared__ T sB[64][LDP];
+    __shared__ double red[256];
+    __shared__ int act_s;
+    const uint32_t task = xcd_task(cd.t_ns);
+    if (task == NOLSM_TASK_NONE) return;
+    const int s = task_slot(task), ti = task_a(task), tj = task_b(task);
+    const SubMeta M = cd.meta[s];
+    SubCtl *ctl = cd.ctl + s;
+    if (ctl->done) return;
+    const int np = M.np, nt = np / 64, tile = ti * nt + tj;
+    T *Xc = (T *)(ws + ((it & 1) ? M.offX1 : M.offL));
+    T *Xn = (T *)(ws + ((it & 1) ? M.offL : M.offX1));
+    T *Bb = (T *)(ws + M.offB);
+    if (mode == 2) {
+        if (threadIdx.x == 0) act_s = ns_decide(na, M, ctl, ws, it, tile);
+        __syncthreads();
+        const int act = act_s;
+        if (act == ACT_STOP) return;
+        if (act == ACT_RESTART) {
+            restart_tile(M, ctl, ws, Xn, ti * 64, tj * 64, 64, 64, [](double v) { return (T)v; });
+            return;
+        }
+    }
+    const T *Bop = (mode == 1) ? Xc : Bb;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+    const int li = l & 15, lk = l >> 4;
+    acc_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = (acc_t){0, 0, 0, 0};
+    for (int kt = 0; kt < nt; ++kt) {
+        g2s_t(sA, Xc + (int64_t)(ti * 64) * np + kt * 64, np);
+        g2s_t(sB, Bop + (int64_t)(kt * 64) * np + tj * 64, np);
+        __syncthreads();
+#pragma unroll 4
+        for (int k0 = 0; k0 < 64; k0 += 4) {
+            const int k = k0 + lk;
+            T a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = sA[r0 + i * 16 + li][k];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) b[j] = sB[k][c0 + j * 16 + li];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = Mma16<T>::mma(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+    double part = 0.0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gr = ti * 64 + r0 + i * 16 + 4 * lk + e;
+                const int gc = tj * 64 + c0 + j * 16 + li;
+                const T v = acc[i][j][e];
+                if (mode == 1) {
+                    const double d = (double)v - (gr == gc ? 1.0 : 0.0);
+                    part += d * d;
+                    Bb[(int64_t)gr * np + gc] = (gr == gc ? (T)3 : (T)0) - v;
+                } else {
+                    Xn[(int64_t)gr * np + gc] = (T)0.5 * v;
+                }
+            }
+    if (mode == 1) {
+        const double sum = block_sum(part, red);
+        if (threadIdx.x == 0) ((double *)(ws + M.offRes))[(int64_t)it * M.ntile_ns + tile] = sum;
+    }
+}
+
+// ------------------------------------------------------------ FP16 / BF16
+template <typename T> struct Lp;
+template <> struct Lp<_Float16> {
+    typedef v8h vec;
+    static __device__ __forceinline__ v16f mma(vec a, vec b, v16f c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ uint16_t enc(float x) {
+        _Float16 h = (_Float16)x;
+        return __builtin_bit_cast(uint16_t, h);
+    }
+};
+template <> struct Lp<__bf16> {
+    typedef v8bf vec;
+    static __device__ __forceinline__ v16f mma(vec a, vec b, v16f c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ uint16_t enc(float x) {
+        __bf16 h = (__bf16)x;
+        return __builtin_bit_cast(uint16_t, h);
+    }
+};
+
+#define LBM 128
+#define LBK 64
+#define LPITCH 72   // halves per LDS row (64 + 8 pad)
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ns_lp(ChunkDev cd, char *ws, NsArgs na, int it, int mode) {
+    typedef typename Lp<T>::vec vec;
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][LBM * LPITCH];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][LBM * LPITCH];
+    __shared__ double red[256];
+    __shared__ int act_s;
+    const uint32_t task = xcd_task(cd.t_ns);
+    if (task == NOLSM_TASK_NONE) return;
+    const int s = task_slot(task), ti = task_a(task), tj = task_b(task);
+    const SubMeta M = cd.meta[s];
+    SubCtl *ctl = cd.ctl + s;
+    if (ctl->done) return;
+    const int np = M.np, nt = (np + LBM - 1) / LBM, tile = ti * nt + tj;
+    uint16_t *Xc = (uint16_t *)(ws + ((it & 1) ? M.offX1 : M.offL));
+    uint16_t *Xn = (uint16_t *)(ws + ((it & 1) ? M.offL : M.offX1));
+    uint16_t *Bb = (uint16_t *)(ws + M.offB);
+    if (mode == 2) {
+        if (threadIdx.x == 0) act_s = ns_decide(na, M, ctl, ws, it, tile);
+        __syncthreads();
+        const int act = act_s;
+        if (act == ACT_STOP) return;
+        if (act == ACT_RESTART) {
+            restart_tile(M, ctl, ws, Xn, ti * LBM, tj * LBM, LBM, LBM,
+                         [](double v) { return Lp<T>::enc((float)v); });
+            return;
+        }
+    }
+    const uint16_t *Ag = Xc;
+    const uint16_t *Bg = (mode == 1) ? Xc : Bb;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int wm = w >> 1, wn = w & 1;
+    const int row0 = ti * LBM, col0 = tj * LBM;
+    // global -> register staging: A 128x64 (4 x 16 B per thread),
+    // B 64x128 as a 4(k) x 8(n) block per thread (4 x 16 B)
+    const int ac = (t & 7) * 8;
+    const int kq = t >> 4, nc = (t & 15) * 8;
+    uint4 ra[4], rb[4];
+    auto gload = [&](int k0) {
+        // rows/columns past np are loaded clamped (always in bounds) and
+        // replaced by zeros afterwards
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int gr = row0 + q * 32 + (t >> 3);
+            const int grc = gr < np ? gr : np - 1;
+            const uint4 v = *(const uint4 *)(Ag + (int64_t)grc * np + k0 + ac);
+            const uint32_t msk = gr < np ? 0xFFFFFFFFu : 0u;
+            ra[q] = make_uint4(v.x & msk, v.y & msk, v.z & msk, v.w & msk);
+        }
+        const int gc = col0 + nc;
+        const int gcc = gc < np ? gc : np - 8;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int gk = k0 + kq * 4 + r;
+            const uint4 v = *(const uint4 *)(Bg + (int64_t)gk * np + gcc);
+            const uint32_t msk = gc < np ? 0xFFFFFFFFu : 0u;
+            rb[r] = make_uint4(v.x & msk, v.y & msk, v.z & msk, v.w & msk);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *(uint4 *)&sA[buf][(q * 32 + (t >> 3)) * LPITCH + ac] = ra[q];
+        auto word = [](const uint4 &v, int i) -> uint32_t { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; };
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int wd = j >> 1;
+            const uint32_t a0 = word(rb[0], wd), a1 = word(rb[1], wd), a2 = word(rb[2], wd), a3 = word(rb[3], wd);
+            uint32_t lo, hi;
+            if ((j & 1) == 0) {
+                lo = (a0 & 0xFFFFu) | (a1 << 16);
+                hi = (a2 & 0xFFFFu) | (a3 << 16);
+            } else {
+                lo = (a0 >> 16) | (a1 & 0xFFFF0000u);
+                hi = (a2 >> 16) | (a3 & 0xFFFF0000u);
+            }
+            *(uint2 *)&sB[buf][(nc + j) * LPITCH + kq * 4] = make_uint2(lo, hi);
+        }
+    };
+    v16f acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+    const int nk = np / LBK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * LBK);
+#pragma unroll
+        for (int kk = 0; kk < LBK; kk += 16) {
+            vec a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                a[i] = *(const vec *)&sA[buf][(wm * 64 + i * 32 + (l & 31)) * LPITCH + kk + (l >> 5) * 8];
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                b[j] = *(const vec *)&sB[buf][(wn * 64 + j * 32 + (l & 31)) * LPITCH + kk + (l >> 5) * 8];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = Lp<T>::mma(a[i], b[j], acc[i][j]);
+        }
+        if (kt + 1 < nk) sstore(buf ^ 1);
+        __syncthreads();
+    }
+    double part = 0.0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int gr = row0 + wm * 64 + i * 32 + (e >> 2) * 8 + (l >> 5) * 4 + (e & 3);
+                const int gc = col0 + wn * 64 + j * 32 + (l & 31);
+                if (gr < np && gc < np) {
+                    const float v = acc[i][j][e];
+                    if (mode == 1) {
+                        const double d = (double)v - (gr == gc ? 1.0 : 0.0);
+                        part += d * d;
+                        Bb[(int64_t)gr * np + gc] = Lp<T>::enc((gr == gc ? 3.0f : 0.0f) - v);
+                    } else {
+                        Xn[(int64_t)gr * np + gc] = Lp<T>::enc(0.5f * v);
+                    }
+                }
+            }
+    if (mode == 1) {
+        const double sum = block_sum(part, red);
+        if (threadIdx.x == 0) ((double *)(ws + M.offRes))[(int64_t)it * M.ntile_ns + tile] = sum;
+    }
+}
+
+hipError_t launch_ns_iter(const ChunkDev &cd, char *ws, const NsArgs &na, int it, hipStream_t st) {
+    for (int mode = 1; mode <= 2; ++mode) {
+        switch (na.prec) {
+            case NOLSM_FP64: hipLaunchKernelGGL(k_ns64<double>, dim3(cd.n_ns), dim3(256), 0, st, cd, ws, na, it, mode); break;
+            case NOLSM_FP32: hipLaunchKernelGGL(k_ns64<float>, dim3(cd.n_ns), dim3(256), 0, st, cd, ws, na, it, mode); break;
+            case NOLSM_FP16: hipLaunchKernelGGL(k_ns_lp<_Float16>, dim3(cd.n_ns), dim3(256), 0, st, cd, ws, na, it, mode); break;
+            default: hipLaunchKernelGGL(k_ns_lp<__bf16>, dim3(cd.n_ns), dim3(256), 0, st, cd, ws, na, it, mode); break;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}

@@ -1,0 +1,488 @@
+// FP64 setup of every submatrix: gather, Cholesky, substitution, bounds, X_0.
+//
+// Sec. III-B.2 (NOLSM generation step and Eq. purification_submatrix): the
+// submatrices T_J(K), T_J(S) are dense on the index list N(J); the sign
+// iteration acts on A_J = T_J(S)^-1 T_J(K) - mu I, and the owned columns of
+// T_J(D) need Y_J = T_J(S)^-1 E_cJ. Here T_J(S)^-1 is applied through an FP64
+// Cholesky factor (the paper's inverse is iterative; the FP64 factorisation
+// is this library's choice, see the design notes).
+#include "dev_common.h"
+#include "kernels.h"
+
+// ---------------------------------------------------------------------------
+// Gather (Sec. III-B.2, submatrix construction): block row a of T_J(K) and
+// T_J(S) from the block-CSR rows of N(J)_a, absent blocks as zeros. The K
+// buffer gets 64 extra columns holding E_cJ (identity on the molecule's own
+// bs rows), which the substitution turns into Y_J. Padding rows/columns
+// n..np-1: S = I, K = 0.
+// grid (max_m, nsub), 256 threads; dynamic LDS: bs*np doubles + m ints.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArgs ga) {
+    extern __shared__ double smem[];
+    const int s = blockIdx.y, a = blockIdx.x;
+    if (s >= cd.nsub) return;
+    const SubMeta M = cd.meta[s];
+    if (a >= M.m) return;
+    const int bs = ga.bs, np = M.np, n = M.n;
+    double *stripe = smem;                                   // bs x np
+    int *list = (int *)(smem + (size_t)bs * cd.max_np);      // m
+    const int *nlist = ga.sub_blk + M.sub_off;
+    for (int i = threadIdx.x; i < M.m; i += 256) list[i] = nlist[i];
+    const int I = list[a];
+    __syncthreads();
+    for (int which = 0; which < 2; ++which) {
+        const int *rp = which ? ga.Srp : ga.Krp;
+        const int *ci = which ? ga.Sci : ga.Kci;
+        const double *val = which ? ga.Sval : ga.Kval;
+        for (int i = threadIdx.x; i < bs * np; i += 256) stripe[i] = 0.0;
+        __syncthreads();
+        const int lo = rp[I], hi = rp[I + 1];
+        const int nel = (hi - lo) * bs * bs;
+        for (int f = threadIdx.x; f < nel; f += 256) {
+            const int e = lo + f / (bs * bs);
+            const int rc = f % (bs * bs);
+            const int C = ci[e];
+            // binary search C in N(J)
+            int l = 0, h = M.m - 1, b = -1;
+            while (l <= h) {
+                const int mid = (l + h) >> 1;
+                const int v = list[mid];
+                if (v == C) { b = mid; break; }
+                if (v < C) l = mid + 1; else h = mid - 1;
+            }
+            if (b >= 0) {
+                const int r = rc / bs, c = rc % bs;
+                double v = val[(int64_t)e * bs * bs + rc];
+                if (which == 1 && M.J == ga.poison_J && a == 0 && b == 0 && r == 0 && c == 0) v = -1.0;
+                stripe[r * np + b * bs + c] = v;
+            }
+        }
+        __syncthreads();
+        double *dst = (double *)(ws + (which ? M.offL : M.offK));
+        const int64_t ld = which ? np : np + 64;
+        for (int i = threadIdx.x; i < bs * np; i += 256) {
+            const int r = i / np, c = i % np;
+            dst[(int64_t)(a * bs + r) * ld + c] = stripe[i];
+        }
+        if (which == 0) {
+            // E tile: columns np..np+63 of the K buffer
+            for (int i = threadIdx.x; i < bs * 64; i += 256) {
+                const int r = i / 64, c = i % 64;
+                dst[(int64_t)(a * bs + r) * ld + np + c] = (a == M.p && c == r) ? 1.0 : 0.0;
+            }
+        }
+        __syncthreads();
+    }
+    // padding rows (one workgroup per submatrix does it)
+    if (a == 0 && np > n) {
+        double *Ld = (double *)(ws + M.offL);
+        double *Kd = (double *)(ws + M.offK);
+        const int rows = np - n;
+        for (int i = threadIdx.x; i < rows * np; i += 256) {
+            const int r = n + i / np, c = i % np;
+            Ld[(int64_t)r * np + c] = (r == c) ? 1.0 : 0.0;
+        }
+        for (int i = threadIdx.x; i < rows * (np + 64); i += 256) {
+            const int r = n + i / (np + 64), c = i % (np + 64);
+            Kd[(int64_t)r * (np + 64) + c] = 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky S_J = L L^T, left-looking by 64-column panels, one workgroup per
+// submatrix. Also stores the inverses of the diagonal tiles (used as GEMMs
+// by the substitution). A non-positive pivot marks the molecule NOT_SPD.
+// ---------------------------------------------------------------------------
+__device__ void potrf64_lds(double (*D)[LDP], int *fail) {
+    const int t = threadIdx.x;
+    for (int c = 0; c < 64; ++c) {
+        if (t == 0) {
+            const double d = D[c][c];
+            if (!(d > 0.0)) *fail = 1;
+            D[c][c] = sqrt(fmax(d, 1e-300));
+        }
+        __syncthreads();
+        const double piv = D[c][c];
+        for (int r = c + 1 + t; r < 64; r += 256) D[r][c] /= piv;
+        __syncthreads();
+        // trailing lower update
+        const int rem = 63 - c;
+        for (int f = t; f < rem * rem; f += 256) {
+            const int r = c + 1 + f / rem, q = c + 1 + f % rem;
+            if (q <= r) D[r][q] -= D[r][c] * D[q][c];
+        }
+        __syncthreads();
+    }
+    for (int f = t; f < 64 * 64; f += 256) {
+        const int r = f >> 6, q = f & 63;
+        if (q > r) D[r][q] = 0.0;
+    }
+    __syncthreads();
+}
+
+// Dinv = L^-1 for a lower-triangular 64x64 L in LDS; thread c < 64 solves column c.
+__device__ void trinv64_lds(const double (*Lt)[LDP], double (*Di)[LDP]) {
+    const int c = threadIdx.x;
+    if (c < 64) {
+        for (int r = 0; r < c; ++r) Di[r][c] = 0.0;
+        Di[c][c] = 1.0 / Lt[c][c];
+        for (int r = c + 1; r < 64; ++r) {
+            double acc = 0.0;
+            for (int q = c; q < r; ++q) acc += Lt[r][q] * Di[q][c];
+            Di[r][c] = -acc / Lt[r][r];
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_chol(ChunkDev cd, char *ws) {
+    __shared__ double sA[64][LDP];
+    __shared__ double sB[64][LDP];
+    __shared__ double sI[64][LDP];
+    __shared__ int fail;
+    const int s = blockIdx.x;
+    if (s >= cd.nsub) return;
+    const SubMeta M = cd.meta[s];
+    double *L = (double *)(ws + M.offL);
+    double *Dinv = (double *)(ws + M.offDinv);
+    const int64_t ld = M.np;
+    const int P = M.P;
+    if (threadIdx.x == 0) fail = 0;
+    __syncthreads();
+    for (int j = 0; j < P; ++j) {
+        for (int i = j; i < P; ++i) {
+            Acc64 acc;
+            g2s_tile(sA, L + (int64_t)(i * 64) * ld + j * 64, ld);
+            __syncthreads();
+            s2acc(acc, sA);
+            __syncthreads();
+            for (int k = 0; k < j; ++k) {
+                g2s_tile(sA, L + (int64_t)(i * 64) * ld + k * 64, ld);
+                g2s_tile(sB, L + (int64_t)(j * 64) * ld + k * 64, ld);
+                __syncthreads();
+                mma64<false, true>(acc, sA, sB, -1.0);
+                __syncthreads();
+            }
+            if (i == j) {
+                acc2s(sA, acc);
+                __syncthreads();
+                potrf64_lds(sA, &fail);
+                if (fail) break;
+                trinv64_lds(sA, sI);
+                s2g_tile(L + (int64_t)(j * 64) * ld + j * 64, ld, sA);
+                s2g_tile(Dinv + (int64_t)j * 4096, 64, sI);
+                __syncthreads();
+            } else {
+                // L_ij = acc * L_jj^-T
+                acc2s(sA, acc);
+                __syncthreads();
+                Acc64 o;
+                acc_zero(o);
+                mma64<false, true>(o, sA, sI);
+                __syncthreads();
+                acc2s(sB, o);
+                __syncthreads();
+                s2g_tile(L + (int64_t)(i * 64) * ld + j * 64, ld, sB);
+                __syncthreads();
+            }
+        }
+        if (fail) break;
+    }
+    if (threadIdx.x == 0) {
+        SubCtl *c = cd.ctl + s;
+        if (fail) { c->status = NOLSM_MOL_NOT_SPD; c->done = 1; }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Substitution for one 64-column tile cc of [K | E]: W = L^-1 B (forward),
+// then [A | Y] = L^-T W (backward), in place in the K buffer; mu is taken
+// off A's diagonal. For cc < P it also emits the |A| row sums of the tile,
+// the complete |A| column sums and a partial Frobenius sum (bounds inputs).
+// Task list: (slot, cc), cc = 0..P (P is the E tile).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_subst(ChunkDev cd, char *ws, double mu) {
+    __shared__ double sA[64][LDP];
+    __shared__ double sB[64][LDP];
+    __shared__ double red[256];
+    const uint32_t task = xcd_task(cd.t_subst);
+    if (task == NOLSM_TASK_NONE) return;
+    const int s = task_slot(task), cc = task_a(task);
+    const SubMeta M = cd.meta[s];
+    if (cd.ctl[s].status != NOLSM_MOL_OK) return;
+    const int P = M.P, np = M.np, n = M.n;
+    const int64_t ldl = np, ldk = np + 64;
+    const double *L = (const double *)(ws + M.offL);
+    const double *Dinv = (const double *)(ws + M.offDinv);
+    double *Kb = (double *)(ws + M.offK);
+    const int col0 = (cc < P) ? cc * 64 : np;
+    // forward: W_i = Dinv_i (B_i - sum_{k<i} L_ik W_k)
+    for (int i = 0; i < P; ++i) {
+        Acc64 acc;
+        g2s_tile(sA, Kb + (int64_t)(i * 64) * ldk + col0, ldk);
+        __syncthreads();
+        s2acc(acc, sA);
+        __syncthreads();
+        for (int k = 0; k < i; ++k) {
+            g2s_tile(sA, L + (int64_t)(i * 64) * ldl + k * 64, ldl);
+            g2s_tile(sB, Kb + (int64_t)(k * 64) * ldk + col0, ldk);
+            __syncthreads();
+            mma64<false, false>(acc, sA, sB, -1.0);
+            __syncthreads();
+        }
+        acc2s(sB, acc);
+        g2s_tile(sA, Dinv + (int64_t)i * 4096, 64);
+        __syncthreads();
+        Acc64 o;
+        acc_zero(o);
+        mma64<false, false>(o, sA, sB);
+        __syncthreads();
+        acc2s(sB, o);
+        __syncthreads();
+        s2g_tile(Kb + (int64_t)(i * 64) * ldk + col0, ldk, sB);
+        __syncthreads();
+    }
+    // backward: A_i = Dinv_i^T (W_i - sum_{k>i} L_ki^T A_k)
+    double colsum = 0.0, frob = 0.0;
+    for (int i = P - 1; i >= 0; --i) {
+        Acc64 acc;
+        g2s_tile(sA, Kb + (int64_t)(i * 64) * ldk + col0, ldk);
+        __syncthreads();
+        s2acc(acc, sA);
+        __syncthreads();
+        for (int k = i + 1; k < P; ++k) {
+            g2s_tile(sA, L + (int64_t)(k * 64) * ldl + i * 64, ldl);
+            g2s_tile(sB, Kb + (int64_t)(k * 64) * ldk + col0, ldk);
+            __syncthreads();
+            mma64<true, false>(acc, sA, sB, -1.0);
+            __syncthreads();
+        }
+        acc2s(sB, acc);
+        g2s_tile(sA, Dinv + (int64_t)i * 4096, 64);
+        __syncthreads();
+        Acc64 o;
+        acc_zero(o);
+        mma64<true, false>(o, sA, sB);
+        __syncthreads();
+        acc2s(sB, o);
+        __syncthreads();
+        if (cc < P) {
+            if (i == cc && threadIdx.x < 64) sB[threadIdx.x][threadIdx.x] -= mu;
+            __syncthreads();
+            const int t = threadIdx.x;
+            if (t < 64) {
+                const int gr = i * 64 + t;
+                double rs = 0.0;
+                for (int c = 0; c < 64; ++c)
+                    if (cc * 64 + c < n) rs += fabs(sB[t][c]);
+                double *rowp = (double *)(ws + M.offRow);
+                rowp[(int64_t)cc * np + gr] = (gr < n) ? rs : 0.0;
+            } else if (t < 128) {
+                const int c = t - 64;
+                for (int r = 0; r < 64; ++r)
+                    if (i * 64 + r < n) colsum += fabs(sB[r][c]);
+            }
+            {
+                // Frobenius partial: 16 entries per thread
+                double fs = 0.0;
+                for (int f = t; f < 4096; f += 256) {
+                    const int r = f >> 6, c = f & 63;
+                    if (i * 64 + r < n && cc * 64 + c < n) fs += sB[r][c] * sB[r][c];
+                }
+                frob += fs;
+            }
+        }
+        s2g_tile(Kb + (int64_t)(i * 64) * ldk + col0, ldk, sB);
+        __syncthreads();
+    }
+    if (cc < P) {
+        double *colp = (double *)(ws + M.offCol);
+        const int t = threadIdx.x;
+        if (t >= 64 && t < 128) {
+            const int c = t - 64;
+            colp[cc * 64 + c] = (cc * 64 + c < n) ? colsum : 0.0;
+        }
+        const double fsum = block_sum(frob, red);
+        if (t == 0) colp[np + cc] = fsum;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Bounds and scale (one workgroup per submatrix). Row and column Gershgorin
+// intervals of A_J; their intersection [G_lo, G_hi] encloses the (real)
+// spectrum, so c_G = 1/max(|G_lo|, |G_hi|) puts it inside [-1, 1], which
+// satisfies the convergence condition of the sign iteration (Sec. III-B.2,
+// after Eq. NS2: the matrix is rescaled before the iteration). With learned
+// bounds, an MLP predicts the normalised extremes; c = 1/(safety*rho_hat),
+// never below c_G. Also writes the 12 features.
+// ---------------------------------------------------------------------------
+__device__ float silu_f(float z) { return z / (1.0f + expf(-z)); }
+
+__global__ __launch_bounds__(256) void k_bounds(ChunkDev cd, char *ws, BoundsArgs ba) {
+    __shared__ double red[256];
+    __shared__ float feat[NOLSM_NFEAT];
+    __shared__ float h1[64], h2[64], outp[2];
+    const int s = blockIdx.x;
+    if (s >= cd.nsub) return;
+    const SubMeta M = cd.meta[s];
+    SubCtl *ctl = cd.ctl + s;
+    if (ctl->status != NOLSM_MOL_OK) return;
+    const int n = M.n, np = M.np, P = M.P, t = threadIdx.x;
+    const double *Kb = (const double *)(ws + M.offK);
+    const double *rowp = (const double *)(ws + M.offRow);
+    const double *colp = (const double *)(ws + M.offCol);
+    const int64_t ldk = np + 64;
+    double dsum = 0, dsq = 0, dmin = 1e300, dmax = -1e300;
+    double rsum = 0, rmax = -1e300, rlo = 1e300, rhi = -1e300, clo = 1e300, chi = -1e300;
+    for (int r = t; r < n; r += 256) {
+        const double d = Kb[(int64_t)r * ldk + r];
+        double rs = 0;
+        for (int c = 0; c < P; ++c) rs += rowp[(int64_t)c * np + r];
+        const double R = rs - fabs(d);
+        const double C = colp[r] - fabs(d);
+        dsum += d; dsq += d * d; dmin = fmin(dmin, d); dmax = fmax(dmax, d);
+        rsum += R; rmax = fmax(rmax, R);
+        rlo = fmin(rlo, d - R); rhi = fmax(rhi, d + R);
+        clo = fmin(clo, d - C); chi = fmax(chi, d + C);
+    }
+    double fr = 0;
+    for (int c = t; c < P; c += 256) fr += colp[np + c];
+    dsum = block_sum(dsum, red);
+    dsq = block_sum(dsq, red);
+    dmin = block_min(dmin, red);
+    dmax = block_max(dmax, red);
+    rsum = block_sum(rsum, red);
+    rmax = block_max(rmax, red);
+    rlo = block_min(rlo, red);
+    rhi = block_max(rhi, red);
+    clo = block_min(clo, red);
+    chi = block_max(chi, red);
+    fr = block_sum(fr, red);
+    const double mean = dsum / n;
+    const double glo = fmax(rlo, clo), ghi = fmin(rhi, chi);
+    const double rho_g = fmax(fabs(glo), fabs(ghi));
+    const double cg = 1.0 / rho_g;
+    if (t == 0) {
+        double f[NOLSM_NFEAT] = {log((double)n), mean, sqrt(fmax(dsq / n - mean * mean, 0.0)), dmin, dmax,
+                                 rsum / n, rmax, rlo, rhi, clo, chi, sqrt(fr / n)};
+        for (int i = 0; i < NOLSM_NFEAT; ++i) feat[i] = (float)f[i];
+        if (ba.d_features)
+            for (int i = 0; i < NOLSM_NFEAT; ++i) ba.d_features[(int64_t)M.J * NOLSM_NFEAT + i] = (float)f[i];
+    }
+    __syncthreads();
+    double c = cg;
+    if (ba.learned && ba.d_mlp) {
+        // forward of the 12-64-64-2 perceptron in FP32 (weights packed [out][in])
+        const float *W1 = ba.d_mlp, *b1 = W1 + 64 * 12, *W2 = b1 + 64, *b2 = W2 + 64 * 64,
+                    *W3 = b2 + 64, *b3 = W3 + 2 * 64;
+        if (t < 64) {
+            float z = b1[t];
+            for (int i = 0; i < 12; ++i) z += W1[t * 12 + i] * ((feat[i] - ba.d_norm[i]) / ba.d_norm[12 + i]);
+            h1[t] = silu_f(z);
+        }
+        __syncthreads();
+        if (t < 64) {
+            float z = b2[t];
+            for (int i = 0; i < 64; ++i) z += W2[t * 64 + i] * h1[i];
+            h2[t] = silu_f(z);
+        }
+        __syncthreads();
+        if (t < 2) {
+            float z = b3[t];
+            for (int i = 0; i < 64; ++i) z += W3[t * 64 + i] * h2[i];
+            outp[t] = z;
+        }
+        __syncthreads();
+        const double rho_hat = fmax(fabs((double)outp[0] * glo), fabs((double)outp[1] * ghi));
+        if (rho_hat > 0 && isfinite(rho_hat)) c = fmax(1.0 / ((double)ba.safety * rho_hat), cg);
+    }
+    if (ba.scale_mult != 0.0) c *= ba.scale_mult;
+    if (t == 0) {
+        ctl->scale = c;
+        ctl->scale_g = cg;
+        ctl->restart_at = -1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// X_0 = c_J A_J in the Newton-Schulz precision, identity on the padding
+// (sign(diag(A, I)) = diag(sign(A), I): the padding never mixes with A).
+// Task list: (slot, 64x64 tile i, j).
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ T cvt(double x);
+template <> __device__ __forceinline__ double cvt<double>(double x) { return x; }
+template <> __device__ __forceinline__ float cvt<float>(double x) { return (float)x; }
+template <> __device__ __forceinline__ _Float16 cvt<_Float16>(double x) { return (_Float16)(float)x; }
+template <> __device__ __forceinline__ __bf16 cvt<__bf16>(double x) { return (__bf16)(float)x; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_convert(ChunkDev cd, char *ws, int use_scale_g) {
+    const uint32_t task = xcd_task(cd.t_conv);
+    if (task == NOLSM_TASK_NONE) return;
+    const int s = task_slot(task), ti = task_a(task), tj = task_b(task);
+    const SubMeta M = cd.meta[s];
+    const SubCtl *ctl = cd.ctl + s;
+    if (ctl->status != NOLSM_MOL_OK) return;
+    const double c = use_scale_g ? ctl->scale_g : ctl->scale;
+    const int n = M.n, np = M.np;
+    const double *A = (const double *)(ws + M.offK);
+    T *X = (T *)(ws + M.offL);
+    const int64_t ldk = np + 64;
+    for (int f = threadIdx.x; f < 4096; f += 256) {
+        const int r = ti * 64 + (f >> 6), q = tj * 64 + (f & 63);
+        const double v = (r < n && q < n) ? c * A[(int64_t)r * ldk + q] : (r == q ? 1.0 : 0.0);
+        X[(int64_t)r * np + q] = cvt<T>(v);
+    }
+}
+
+// init of the per-slot control blocks and residual partials of a chunk
+__global__ void k_init_ctl(ChunkDev cd) {
+    const int s = blockIdx.x;
+    if (s >= cd.nsub) return;
+    SubCtl *c = cd.ctl + s;
+    if (threadIdx.x == 0) {
+        c->done = 0; c->iters = 0; c->status = NOLSM_MOL_OK; c->fallback = 0; c->restart_at = -1;
+        c->scale = 0; c->scale_g = 0; c->resid = 0;
+    }
+    for (int i = threadIdx.x; i < NOLSM_MAX_ITER_CAP; i += blockDim.x) c->rhist[i] = 0.0;
+}
+
+// ----------------------------------------------------------------- launchers
+#define LAUNCH_CHECK() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
+
+hipError_t launch_setup(const ChunkDev &cd, char *ws, const GatherArgs &ga, const BoundsArgs &ba,
+                        double mu, int prec, hipStream_t st) {
+    hipLaunchKernelGGL(k_init_ctl, dim3(cd.nsub), dim3(64), 0, st, cd);
+    LAUNCH_CHECK();
+    const size_t lds = (size_t)ga.bs * cd.max_np * 8 + (size_t)cd.max_m * 4 + 16;
+    hipLaunchKernelGGL(k_gather, dim3(cd.max_m, cd.nsub), dim3(256), lds, st, cd, ws, ga);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_chol, dim3(cd.nsub), dim3(256), 0, st, cd, ws);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_subst, dim3(cd.n_subst), dim3(256), 0, st, cd, ws, mu);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_bounds, dim3(cd.nsub), dim3(256), 0, st, cd, ws, ba);
+    LAUNCH_CHECK();
+    return launch_convert(cd, ws, prec, 0, st);
+}
+
+hipError_t launch_convert(const ChunkDev &cd, char *ws, int prec, int use_scale_g, hipStream_t st) {
+    switch (prec) {
+        case 0: hipLaunchKernelGGL(k_convert<double>, dim3(cd.n_conv), dim3(256), 0, st, cd, ws, use_scale_g); break;
+        case 1: hipLaunchKernelGGL(k_convert<float>, dim3(cd.n_conv), dim3(256), 0, st, cd, ws, use_scale_g); break;
+        case 2: hipLaunchKernelGGL(k_convert<_Float16>, dim3(cd.n_conv), dim3(256), 0, st, cd, ws, use_scale_g); break;
+        default: hipLaunchKernelGGL(k_convert<__bf16>, dim3(cd.n_conv), dim3(256), 0, st, cd, ws, use_scale_g); break;
+    }
+    return hipGetLastError();
+}
+
+// Raises the dynamic-LDS limit of the kernels whose LDS grows with the
+// largest submatrix. A refusal is not an error: launches that fit the
+// default limit still work, larger ones report the launch failure.
+hipError_t nolsm_kernels_init() {
+    (void)hipFuncSetAttribute((const void *)k_gather, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)nolsm_finish_init();
+    (void)hipGetLastError();
+    return hipSuccess;
+}

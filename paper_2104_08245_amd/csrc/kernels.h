@@ -1,0 +1,58 @@
+// Launchers of the HIP kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "nolsm_internal.h"
+
+struct GatherArgs {
+    const int32_t *Krp, *Kci, *Srp, *Sci, *sub_blk;
+    const double *Kval, *Sval;
+    int32_t bs;
+    int32_t poison_J;
+};
+
+struct BoundsArgs {
+    const float *d_mlp;
+    const float *d_norm;
+    float *d_features;
+    float safety;
+    int32_t learned;
+    double scale_mult;
+};
+
+// control of the sign iteration, identical for every workgroup of a launch
+struct NsArgs {
+    int32_t prec;          // nolsm_prec
+    int32_t max_iter;
+    int32_t fixed_iters;   // > 0: stop exactly after this many updates
+    int32_t allow_restart; // Gershgorin restart on divergence
+    double tol;            // stop when r < tol (0: unused)
+    double theta, rmax;    // stagnation switch: r_k > theta r_{k-1} and r_k < rmax
+};
+
+struct FinishArgs {
+    int32_t prec;
+    int32_t nfinal;        // 0, 1, 2 column-restricted finishing iterations
+};
+
+struct ExtractArgs {
+    const int32_t *Krp, *Kci, *Srp, *Sci, *sub_blk, *scatter_pos;
+    const double *Kval, *Sval;
+    double *Dcols;         // [36 * sum_m] for bs = 6
+    double *Dval;          // optional
+    void *stats;           // nolsm_mol_stats[nb]
+    int32_t bs;
+    int32_t prec;
+    int32_t nfinal;
+};
+
+hipError_t launch_setup(const ChunkDev &cd, char *ws, const GatherArgs &ga, const BoundsArgs &ba,
+                        double mu, int prec, hipStream_t st);
+hipError_t launch_convert(const ChunkDev &cd, char *ws, int prec, int use_scale_g, hipStream_t st);
+hipError_t launch_ns_iter(const ChunkDev &cd, char *ws, const NsArgs &na, int it, hipStream_t st);
+hipError_t launch_finish(const ChunkDev &cd, char *ws, const FinishArgs &fa, hipStream_t st);
+hipError_t launch_extract(const ChunkDev &cd, char *ws, const ExtractArgs &ea, hipStream_t st);
+hipError_t launch_assemble(const double *Dcols, double *Dval, const int32_t *scatter_pos, int64_t sum_m,
+                           int32_t bs, hipStream_t st);
+hipError_t nolsm_kernels_init();
+hipError_t nolsm_finish_init();

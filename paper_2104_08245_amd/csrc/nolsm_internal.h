@@ -1,0 +1,61 @@
+// Internal layout shared by the host runtime (plan.cpp, api.cpp) and the HIP
+// kernels. Not part of the public ABI.
+#pragma once
+#include <stdint.h>
+
+#include "../../include/nolsm.h"
+
+#define NOLSM_TILE 64          // FP64 setup tile (Cholesky, substitution)
+#define NOLSM_NFEAT 12
+#define NOLSM_MAX_ITER_CAP 128
+#define NOLSM_NVEC 12          // finishing-iteration vectors per submatrix
+
+// One submatrix slot of a chunk. Byte offsets are into the workspace.
+struct SubMeta {
+    int32_t J;        // column block (molecule)
+    int32_t m;        // blocks in N(J)
+    int32_t n;        // bs * m
+    int32_t np;       // n rounded up to NOLSM_TILE
+    int32_t p;        // position of J in N(J)
+    int32_t P;        // np / NOLSM_TILE
+    int32_t sub_off;  // sub_ptr[J]
+    int32_t ntile_ns; // NS GEMM tiles of this slot (for residual partials)
+    int64_t offL;     // np*np doubles: S -> L; later X buffer 0
+    int64_t offK;     // np*(np+64) doubles: K -> W -> [A | Y]
+    int64_t offDinv;  // P*64*64 doubles: inverses of the diagonal tiles of L
+    int64_t offRow;   // (P+1)*np doubles: partial |A| row sums per column tile
+    int64_t offCol;   // np doubles col sums of |A|, then 64 more: P frob partials
+    int64_t offX1;    // np*np elements of the NS precision: X buffer 1
+    int64_t offB;     // np*np elements: B = 3I - X^2
+    int64_t offVec;   // NOLSM_NVEC * np * 6 floats/doubles: finishing vectors
+    int64_t offRes;   // max_iter * ntile_ns doubles: residual partials
+};
+
+// Per-slot control state, written by kernels only.
+struct SubCtl {
+    int32_t done;       // sign iteration finished (or failed)
+    int32_t iters;      // index K of the returned iterate X_K
+    int32_t status;     // NOLSM_MOL_*
+    int32_t fallback;   // Gershgorin restart used
+    int32_t restart_at; // iteration of the restart, -1 if none
+    int32_t pad_[3];
+    double scale;       // c_J actually used
+    double scale_g;     // Gershgorin scale 1/rho_G
+    double resid;       // residual of the returned iterate
+    double rhist[NOLSM_MAX_ITER_CAP];
+};
+
+// Packed task: slot (16 bits) | a (8 bits) | b (8 bits); 0xFFFFFFFF = no-op.
+#define NOLSM_TASK(slot, a, b) (((uint32_t)(slot) << 16) | ((uint32_t)(a) << 8) | (uint32_t)(b))
+#define NOLSM_TASK_NONE 0xFFFFFFFFu
+
+// Device addresses of one chunk's metadata and lists (inside d_meta).
+struct ChunkDev {
+    const SubMeta *meta;
+    const uint32_t *t_subst;   // (slot, column tile 0..P)
+    const uint32_t *t_conv;    // (slot, 64x64 tile i, j) for X_0
+    const uint32_t *t_ns;      // (slot, NS tile i, j)
+    const uint32_t *t_rows;    // (slot, 64-row block) for the skinny products
+    SubCtl *ctl;               // in the workspace
+    int32_t nsub, n_subst, n_conv, n_ns, n_rows, max_m, max_np;
+};

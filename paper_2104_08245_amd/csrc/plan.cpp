@@ -1,0 +1,358 @@
+// Plan / index build of the NOLSM hot path (host work).
+//
+// Sec. III-B.2 (NOLSM generation step, Fig. 2 b-c): the row indices of a
+// column's submatrix are the union of the rows where K (H_0) or S has a
+// stored block in that column. Both inputs are symmetric block patterns, so
+// the index list N(J) of column block J is the merged block row J. The result
+// matrix D keeps the merged pattern (the submatrix approximation has the
+// sparsity of its input).
+#include <algorithm>
+#include <iterator>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "plan.h"
+
+static thread_local std::string g_last_error;
+void nolsm_set_last_error(const std::string &s) { g_last_error = s; }
+
+static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int nolsm_ns_tile_for(int32_t prec) { return (prec == NOLSM_FP16 || prec == NOLSM_BF16) ? 128 : 64; }
+int nolsm_elem_for(int32_t prec) {
+    switch (prec) {
+        case NOLSM_FP64: return 8;
+        case NOLSM_FP32: return 4;
+        default: return 2;
+    }
+}
+
+size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_iter) {
+    const size_t n = (size_t)np;
+    const size_t P = n / NOLSM_TILE;
+    const size_t nt = (n + ns_tile - 1) / ns_tile;
+    size_t b = 0;
+    b += align256(n * n * 8);                 // L / X0
+    b += align256(n * (n + 64) * 8);          // K / W / A|Y
+    b += align256(P * 64 * 64 * 8);           // Dinv
+    b += align256((P + 1) * n * 8);           // row partials
+    b += align256((n + 64) * 8);              // col sums + frob partials
+    b += align256(n * n * (size_t)elem);      // X1
+    b += align256(n * n * (size_t)elem);      // B
+    b += align256((size_t)NOLSM_NVEC * n * 6 * 8);  // finishing vectors
+    b += align256((size_t)max_iter * nt * nt * 8);  // residual partials
+    return b;
+}
+
+static int validate(const nolsm_pattern *p, const char *name) {
+    if (!p || !p->row_ptr || (p->nnzb > 0 && !p->col_idx) || p->nb < 1) {
+        nolsm_set_last_error(std::string(name) + ": null or empty pattern");
+        return NOLSM_E_ARG;
+    }
+    const int32_t nb = p->nb;
+    if (p->row_ptr[0] != 0 || (int64_t)p->row_ptr[nb] != p->nnzb) {
+        nolsm_set_last_error(std::string(name) + ": row_ptr limits");
+        return NOLSM_E_PATTERN;
+    }
+    for (int32_t i = 0; i < nb; ++i) {
+        const int32_t lo = p->row_ptr[i], hi = p->row_ptr[i + 1];
+        if (hi < lo) { nolsm_set_last_error(std::string(name) + ": row_ptr not monotone"); return NOLSM_E_PATTERN; }
+        bool diag = false;
+        for (int32_t e = lo; e < hi; ++e) {
+            const int32_t c = p->col_idx[e];
+            if (c < 0 || c >= nb) { nolsm_set_last_error(std::string(name) + ": column out of range"); return NOLSM_E_PATTERN; }
+            if (e > lo && c <= p->col_idx[e - 1]) { nolsm_set_last_error(std::string(name) + ": columns not strictly increasing"); return NOLSM_E_PATTERN; }
+            if (c == i) diag = true;
+        }
+        if (!diag) { nolsm_set_last_error(std::string(name) + ": diagonal block missing"); return NOLSM_E_PATTERN; }
+    }
+    // symmetry: (i, c) stored => (c, i) stored (binary search in row c)
+    for (int32_t i = 0; i < nb; ++i) {
+        for (int32_t e = p->row_ptr[i]; e < p->row_ptr[i + 1]; ++e) {
+            const int32_t c = p->col_idx[e];
+            const int32_t *b = p->col_idx + p->row_ptr[c], *en = p->col_idx + p->row_ptr[c + 1];
+            if (!std::binary_search(b, en, i)) {
+                nolsm_set_last_error(std::string(name) + ": pattern not symmetric");
+                return NOLSM_E_PATTERN;
+            }
+        }
+    }
+    return NOLSM_OK;
+}
+
+extern "C" int nolsm_build_submatrices(const nolsm_pattern *K, const nolsm_pattern *S,
+                                       int32_t flags, nolsm_plan **out) {
+    (void)flags;
+    if (!out) { nolsm_set_last_error("plan out-pointer is null"); return NOLSM_E_ARG; }
+    *out = nullptr;
+    if (!K || !S) { nolsm_set_last_error("null pattern"); return NOLSM_E_ARG; }
+    if (K->nb != S->nb || K->bs != S->bs) { nolsm_set_last_error("K and S disagree on nb/bs"); return NOLSM_E_ARG; }
+    if (K->bs < 1 || K->bs > 6) { nolsm_set_last_error("bs must be 1..6"); return NOLSM_E_ARG; }
+    int rc = validate(K, "K");
+    if (rc) return rc;
+    rc = validate(S, "S");
+    if (rc) return rc;
+    nolsm_plan *pl = new (std::nothrow) nolsm_plan();
+    if (!pl) return NOLSM_E_NOMEM;
+    try {
+        const int32_t nb = K->nb;
+        pl->nb = nb;
+        pl->bs = K->bs;
+        pl->Krp.assign(K->row_ptr, K->row_ptr + nb + 1);
+        pl->Kci.assign(K->col_idx, K->col_idx + K->nnzb);
+        pl->Srp.assign(S->row_ptr, S->row_ptr + nb + 1);
+        pl->Sci.assign(S->col_idx, S->col_idx + S->nnzb);
+        // merged pattern: row J of pat(K) u pat(S), sorted (set union of two
+        // sorted lists)
+        pl->sub_ptr.assign(nb + 1, 0);
+        pl->sub_blk.reserve((size_t)std::max<int64_t>(K->nnzb, S->nnzb));
+        pl->self_pos.assign(nb, -1);
+        for (int32_t J = 0; J < nb; ++J) {
+            const int32_t *a = K->col_idx + K->row_ptr[J], *ae = K->col_idx + K->row_ptr[J + 1];
+            const int32_t *b = S->col_idx + S->row_ptr[J], *be = S->col_idx + S->row_ptr[J + 1];
+            const size_t start = pl->sub_blk.size();
+            std::set_union(a, ae, b, be, std::back_inserter(pl->sub_blk));
+            pl->sub_ptr[J + 1] = (int32_t)pl->sub_blk.size();
+            const int32_t *lb = pl->sub_blk.data() + start, *le = pl->sub_blk.data() + pl->sub_blk.size();
+            pl->self_pos[J] = (int32_t)(std::lower_bound(lb, le, J) - lb);
+        }
+        // D keeps the merged pattern: D_row_ptr = sub_ptr, D_col_idx = sub_blk
+        // (P is symmetric). scatter_pos: block (N(J)_a, J) lives in row
+        // I = N(J)_a at the position of J in N(I).
+        const size_t sum_m = pl->sub_blk.size();
+        pl->scatter_pos.assign(sum_m, -1);
+        pl->m_min = 1 << 30;
+        pl->m_max = 0;
+        pl->sum_n3 = 0.0;
+        for (int32_t J = 0; J < nb; ++J) {
+            const int32_t m = pl->sub_ptr[J + 1] - pl->sub_ptr[J];
+            pl->m_min = std::min(pl->m_min, m);
+            pl->m_max = std::max(pl->m_max, m);
+            const double n = (double)m * pl->bs;
+            pl->sum_n3 += n * n * n;
+            for (int32_t a = 0; a < m; ++a) {
+                const int32_t I = pl->sub_blk[pl->sub_ptr[J] + a];
+                const int32_t *lb = pl->sub_blk.data() + pl->sub_ptr[I];
+                const int32_t *le = pl->sub_blk.data() + pl->sub_ptr[I + 1];
+                const int32_t *q = std::lower_bound(lb, le, J);
+                pl->scatter_pos[pl->sub_ptr[J] + a] = (int32_t)(q - pl->sub_blk.data());
+            }
+        }
+    } catch (...) {
+        delete pl;
+        return NOLSM_E_NOMEM;
+    }
+    *out = pl;
+    return NOLSM_OK;
+}
+
+extern "C" void nolsm_default_opts(nolsm_solve_opts *o, int32_t prec) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->prec = prec;
+    o->n_final_fp32 = (prec == NOLSM_FP16 || prec == NOLSM_BF16) ? 2 : 0;
+    o->tol = (prec == NOLSM_FP64) ? 1e-10 : (prec == NOLSM_FP32 ? 1e-5 : 0.0);
+    o->max_iter = (prec == NOLSM_FP64) ? 48 : 40;
+    o->fixed_iters = 0;
+    o->switch_theta = 0.7;
+    o->switch_rmax = 0.5;
+    o->bounds = NOLSM_BOUNDS_GERSHGORIN;
+    o->mlp_safety = 1.05f;
+    o->sched = NOLSM_SCHED_GRAPH;
+    o->debug_poison_mol = -1;
+}
+
+extern "C" int nolsm_plan_info(const nolsm_plan *p, nolsm_plan_sizes *o) {
+    if (!p || !o) return NOLSM_E_ARG;
+    std::memset(o, 0, sizeof(*o));
+    o->nb = p->nb;
+    o->bs = p->bs;
+    o->sum_m = (int64_t)p->sub_blk.size();
+    o->m_min = p->m_min;
+    o->m_max = p->m_max;
+    o->sum_n3 = p->sum_n3;
+    if (p->configured) {
+        o->nchunks = (int32_t)p->chunks.size();
+        o->meta_bytes = p->image.size();
+        o->ws_min_bytes = p->ws_min;
+        o->ws_full_bytes = p->ws_full;
+    }
+    return NOLSM_OK;
+}
+
+extern "C" int nolsm_plan_export(const nolsm_plan *p, int32_t *sub_ptr, int32_t *sub_blk,
+                                 int32_t *self_pos, int32_t *D_row_ptr, int32_t *D_col_idx,
+                                 int32_t *scatter_pos) {
+    if (!p) return NOLSM_E_ARG;
+    const size_t nb = (size_t)p->nb, sm = p->sub_blk.size();
+    if (sub_ptr) std::memcpy(sub_ptr, p->sub_ptr.data(), (nb + 1) * 4);
+    if (sub_blk) std::memcpy(sub_blk, p->sub_blk.data(), sm * 4);
+    if (self_pos) std::memcpy(self_pos, p->self_pos.data(), nb * 4);
+    if (D_row_ptr) std::memcpy(D_row_ptr, p->sub_ptr.data(), (nb + 1) * 4);
+    if (D_col_idx) std::memcpy(D_col_idx, p->sub_blk.data(), sm * 4);
+    if (scatter_pos) std::memcpy(scatter_pos, p->scatter_pos.data(), sm * 4);
+    return NOLSM_OK;
+}
+
+// Append a task list padded to a multiple of 8: kernels remap workgroup b to
+// list entry (b % 8) * (G / 8) + b / 8, so that consecutive entries (the
+// tiles of one submatrix) run on the same XCD and share its L2.
+static void pad8(std::vector<uint32_t> &v) {
+    while (v.size() % 8) v.push_back(NOLSM_TASK_NONE);
+    if (v.empty()) for (int i = 0; i < 8; ++i) v.push_back(NOLSM_TASK_NONE);
+}
+
+template <class T>
+static size_t put(std::vector<char> &img, const T *src, size_t count) {
+    const size_t off = align256(img.size());
+    img.resize(off + count * sizeof(T));
+    if (count) std::memcpy(img.data() + off, src, count * sizeof(T));
+    return off;
+}
+
+extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts,
+                                    size_t ws_bytes, size_t *meta_bytes) {
+    if (!pl || !opts) { nolsm_set_last_error("configure: null argument"); return NOLSM_E_ARG; }
+    if (opts->prec < NOLSM_FP64 || opts->prec > NOLSM_BF16) { nolsm_set_last_error("bad precision"); return NOLSM_E_ARG; }
+    if (opts->max_iter < 2 || opts->max_iter > NOLSM_MAX_ITER_CAP) { nolsm_set_last_error("max_iter must be 2..128"); return NOLSM_E_ARG; }
+    if (opts->sched < NOLSM_SCHED_GRAPH || opts->sched > NOLSM_SCHED_PER_BUCKET) { nolsm_set_last_error("bad schedule"); return NOLSM_E_ARG; }
+    try {
+        pl->configured = false;
+        pl->bound = false;
+        pl->chunks.clear();
+        pl->prec = opts->prec;
+        pl->sched = opts->sched;
+        pl->max_iter = opts->max_iter;
+        pl->ns_tile = nolsm_ns_tile_for(opts->prec);
+        pl->elem = nolsm_elem_for(opts->prec);
+        const int32_t nb = pl->nb, bs = pl->bs;
+        const int32_t T = pl->ns_tile;
+        auto np_of = [&](int32_t J) {
+            const int32_t n = bs * (pl->sub_ptr[J + 1] - pl->sub_ptr[J]);
+            return (n + NOLSM_TILE - 1) / NOLSM_TILE * NOLSM_TILE;
+        };
+        // order: decreasing np (largest-first keeps the tail short), then J
+        std::vector<int32_t> order(nb);
+        for (int32_t J = 0; J < nb; ++J) order[J] = J;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return np_of(a) > np_of(b); });
+        const size_t ctl_bytes = align256(sizeof(SubCtl));
+        pl->ws_min = 0;
+        pl->ws_full = 0;
+        for (int32_t J = 0; J < nb; ++J) {
+            const size_t sb = nolsm_slot_bytes(np_of(J), T, pl->elem, pl->max_iter) + ctl_bytes;
+            pl->ws_min = std::max(pl->ws_min, sb);
+            pl->ws_full += sb;
+        }
+        pl->ws_full += 256;
+        if (ws_bytes < pl->ws_min + 256) {
+            nolsm_set_last_error("workspace smaller than the largest submatrix needs");
+            return NOLSM_E_WORKSPACE;
+        }
+        pl->ws_bytes = ws_bytes;
+        // greedy chunks; the per-bucket schedule also cuts at bucket changes
+        // (buckets of 64 rows, i.e. equal np)
+        size_t i = 0;
+        while (i < order.size()) {
+            HostChunk ch;
+            size_t used = 0;
+            std::vector<int32_t> js;
+            const int32_t bucket = np_of(order[i]);
+            while (i < order.size() && js.size() < 65535) {
+                const int32_t J = order[i];
+                if (pl->sched == NOLSM_SCHED_PER_BUCKET && np_of(J) != bucket) break;
+                const size_t sb = nolsm_slot_bytes(np_of(J), T, pl->elem, pl->max_iter) + ctl_bytes;
+                if (used + sb + 256 > ws_bytes) break;
+                used += sb;
+                js.push_back(J);
+                ++i;
+            }
+            // layout: SubCtl array first, then the slots
+            size_t off = align256(js.size() * sizeof(SubCtl));
+            ch.off_ctl = 0;
+            for (size_t s = 0; s < js.size(); ++s) {
+                const int32_t J = js[s];
+                SubMeta m;
+                std::memset(&m, 0, sizeof(m));
+                m.J = J;
+                m.m = pl->sub_ptr[J + 1] - pl->sub_ptr[J];
+                m.n = bs * m.m;
+                m.np = np_of(J);
+                m.p = pl->self_pos[J];
+                m.P = m.np / NOLSM_TILE;
+                m.sub_off = pl->sub_ptr[J];
+                const int32_t nt = (m.np + T - 1) / T;
+                m.ntile_ns = nt * nt;
+                const size_t n = (size_t)m.np;
+                m.offL = (int64_t)off; off += align256(n * n * 8);
+                m.offK = (int64_t)off; off += align256(n * (n + 64) * 8);
+                m.offDinv = (int64_t)off; off += align256((size_t)m.P * 4096 * 8);
+                m.offRow = (int64_t)off; off += align256((size_t)(m.P + 1) * n * 8);
+                m.offCol = (int64_t)off; off += align256((n + 64) * 8);
+                m.offX1 = (int64_t)off; off += align256(n * n * pl->elem);
+                m.offB = (int64_t)off; off += align256(n * n * pl->elem);
+                m.offVec = (int64_t)off; off += align256((size_t)NOLSM_NVEC * n * 6 * 8);
+                m.offRes = (int64_t)off; off += align256((size_t)pl->max_iter * m.ntile_ns * 8);
+                ch.meta.push_back(m);
+                ch.max_m = std::max(ch.max_m, m.m);
+                ch.max_np = std::max(ch.max_np, m.np);
+                for (int32_t c = 0; c <= m.P; ++c) ch.t_subst.push_back(NOLSM_TASK(s, c, 0));
+                for (int32_t a = 0; a < m.P; ++a)
+                    for (int32_t b = 0; b < m.P; ++b) ch.t_conv.push_back(NOLSM_TASK(s, a, b));
+                for (int32_t a = 0; a < nt; ++a)
+                    for (int32_t b = 0; b < nt; ++b) ch.t_ns.push_back(NOLSM_TASK(s, a, b));
+                for (int32_t a = 0; a < m.P; ++a) ch.t_rows.push_back(NOLSM_TASK(s, a, 0));
+            }
+            ch.ws_used = off;
+            pad8(ch.t_subst);
+            pad8(ch.t_conv);
+            pad8(ch.t_ns);
+            pad8(ch.t_rows);
+            pl->chunks.push_back(std::move(ch));
+        }
+        // metadata image
+        pl->image.clear();
+        pl->o_Krp = put(pl->image, pl->Krp.data(), pl->Krp.size());
+        pl->o_Kci = put(pl->image, pl->Kci.data(), pl->Kci.size());
+        pl->o_Srp = put(pl->image, pl->Srp.data(), pl->Srp.size());
+        pl->o_Sci = put(pl->image, pl->Sci.data(), pl->Sci.size());
+        pl->o_sub_ptr = put(pl->image, pl->sub_ptr.data(), pl->sub_ptr.size());
+        pl->o_sub_blk = put(pl->image, pl->sub_blk.data(), pl->sub_blk.size());
+        pl->o_self = put(pl->image, pl->self_pos.data(), pl->self_pos.size());
+        pl->o_scatter = put(pl->image, pl->scatter_pos.data(), pl->scatter_pos.size());
+        for (auto &ch : pl->chunks) {
+            ch.o_meta = put(pl->image, ch.meta.data(), ch.meta.size());
+            ch.o_subst = put(pl->image, ch.t_subst.data(), ch.t_subst.size());
+            ch.o_conv = put(pl->image, ch.t_conv.data(), ch.t_conv.size());
+            ch.o_ns = put(pl->image, ch.t_ns.data(), ch.t_ns.size());
+            ch.o_rows = put(pl->image, ch.t_rows.data(), ch.t_rows.size());
+        }
+        pl->image.resize(align256(pl->image.size()));
+        pl->configured = true;
+        if (meta_bytes) *meta_bytes = pl->image.size();
+    } catch (...) {
+        return NOLSM_E_NOMEM;
+    }
+    return NOLSM_OK;
+}
+
+extern "C" const char *nolsm_strerror(int code) {
+    static thread_local std::string msg;
+    const char *base = "unknown error";
+    switch (code) {
+        case NOLSM_OK: base = "ok"; break;
+        case NOLSM_E_ARG: base = "invalid argument"; break;
+        case NOLSM_E_PATTERN: base = "invalid block pattern"; break;
+        case NOLSM_E_WORKSPACE: base = "workspace or metadata buffer too small"; break;
+        case NOLSM_E_HIP: base = "HIP runtime error"; break;
+        case NOLSM_E_STATE: base = "plan not configured/bound for these options"; break;
+        case NOLSM_E_NOT_SPD: base = "a submatrix of S is not positive definite"; break;
+        case NOLSM_E_NOCONV: base = "a sign iteration did not converge"; break;
+        case NOLSM_E_NOMEM: base = "host allocation failed"; break;
+    }
+    msg = base;
+    if (!g_last_error.empty()) msg += std::string(": ") + g_last_error;
+    return msg.c_str();
+}

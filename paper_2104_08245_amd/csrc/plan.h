@@ -1,0 +1,52 @@
+// Host-side plan object (internal).
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/nolsm.h"
+#include "nolsm_internal.h"
+
+struct HostChunk {
+    std::vector<SubMeta> meta;
+    std::vector<uint32_t> t_subst, t_conv, t_ns, t_rows;
+    int32_t max_m = 0, max_np = 0;
+    size_t ws_used = 0;       // bytes of the workspace this chunk uses
+    size_t off_ctl = 0;       // workspace offset of the SubCtl array
+    // metadata image offsets (bytes from d_meta)
+    size_t o_meta = 0, o_subst = 0, o_conv = 0, o_ns = 0, o_rows = 0;
+};
+
+struct nolsm_plan {
+    int32_t nb = 0, bs = 0;
+    std::vector<int32_t> Krp, Kci, Srp, Sci;
+    std::vector<int32_t> sub_ptr, sub_blk, self_pos, scatter_pos;
+    int32_t m_min = 0, m_max = 0;
+    double sum_n3 = 0.0;
+
+    // configuration
+    bool configured = false;
+    bool bound = false;
+    int32_t prec = -1, sched = -1, max_iter = 0, ns_tile = 0, elem = 0;
+    size_t ws_bytes = 0, ws_min = 0, ws_full = 0;
+    std::vector<HostChunk> chunks;
+    std::vector<char> image;              // metadata image uploaded by bind
+    size_t o_Krp = 0, o_Kci = 0, o_Srp = 0, o_Sci = 0, o_sub_ptr = 0, o_sub_blk = 0,
+           o_self = 0, o_scatter = 0;
+    void *d_meta = nullptr;
+    int device = -1;
+    // graph cache
+    void *graph_exec = nullptr;
+    const void *g_key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    double g_mu = 0.0;
+    nolsm_solve_opts g_opts;
+    void *g_stream = nullptr;
+};
+
+// Internal helpers implemented in plan.cpp
+size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_iter);
+int nolsm_ns_tile_for(int32_t prec);
+int nolsm_elem_for(int32_t prec);
+void nolsm_set_last_error(const std::string &s);

@@ -1,0 +1,181 @@
+"""Python API over the C ABI. PyTorch only provides device memory and streams;
+every step of the path runs in libnolsm.so's HIP kernels."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Plan:
+    """nolsm_build_submatrices (+ configure / bind). Host arrays are int32."""
+
+    def __init__(self, nb, bs, K_row_ptr, K_col_idx, S_row_ptr=None, S_col_idx=None, flags=0):
+        lib = L.lib()
+        self._keep = [np.ascontiguousarray(K_row_ptr, np.int32), np.ascontiguousarray(K_col_idx, np.int32)]
+        if S_row_ptr is None:
+            S_row_ptr, S_col_idx = K_row_ptr, K_col_idx
+        self._keep += [np.ascontiguousarray(S_row_ptr, np.int32), np.ascontiguousarray(S_col_idx, np.int32)]
+        krp, kci, srp, sci = self._keep
+        pk = L.Pattern(nb, bs, kci.shape[0], L.i32_ptr(krp), L.i32_ptr(kci))
+        ps = L.Pattern(nb, bs, sci.shape[0], L.i32_ptr(srp), L.i32_ptr(sci))
+        h = C.c_void_p()
+        L.check(lib.nolsm_build_submatrices(C.byref(pk), C.byref(ps), flags, C.byref(h)))
+        self.h = h
+        self.nb, self.bs = nb, bs
+        self.meta = None
+        self.opts = None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            try:
+                L.lib().nolsm_plan_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    def info(self):
+        s = L.PlanSizes()
+        L.check(L.lib().nolsm_plan_info(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in L.PlanSizes._fields_}
+
+    def export(self):
+        inf = self.info()
+        nb, sm = self.nb, inf["sum_m"]
+        out = dict(sub_ptr=np.zeros(nb + 1, np.int32), sub_blk=np.zeros(sm, np.int32),
+                   self_pos=np.zeros(nb, np.int32), D_row_ptr=np.zeros(nb + 1, np.int32),
+                   D_col_idx=np.zeros(sm, np.int32), scatter_pos=np.zeros(sm, np.int32))
+        L.check(L.lib().nolsm_plan_export(self.h, *[L.i32_ptr(out[k]) for k in
+                                                    ("sub_ptr", "sub_blk", "self_pos", "D_row_ptr",
+                                                     "D_col_idx", "scatter_pos")]))
+        return out
+
+    def configure(self, opts, ws_bytes):
+        mb = C.c_size_t(0)
+        L.check(L.lib().nolsm_plan_configure(self.h, C.byref(opts), int(ws_bytes), C.byref(mb)))
+        self.opts = opts
+        return mb.value
+
+    def bind(self, meta_bytes, device, stream=None):
+        torch = _torch()
+        self.meta = torch.empty(max(int(meta_bytes), 256), dtype=torch.uint8, device=device)
+        st = stream if stream is not None else torch.cuda.current_stream(device).cuda_stream
+        L.check(L.lib().nolsm_plan_bind(self.h, C.c_void_p(self.meta.data_ptr()), self.meta.numel(),
+                                        C.c_void_p(st)))
+
+
+def _stream_ptr(stream, device):
+    torch = _torch()
+    if stream is None:
+        return torch.cuda.current_stream(device).cuda_stream
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+class Solver:
+    """One system (K, S block-CSR) on one GPU: uploads the values, owns the
+    workspace, metadata and outputs as torch tensors, runs nolsm_sign_batch."""
+
+    def __init__(self, system, prec="fp64", device="cuda:0", ws_bytes=None, ws_budget=48 << 30,
+                 **opt_kw):
+        torch = _torch()
+        K, S = system.K, system.S
+        self.device = torch.device(device)
+        self.nb, self.bs = K.nb, K.bs
+        self.plan = Plan(K.nb, K.bs, K.row_ptr, K.col_idx, S.row_ptr, S.col_idx)
+        self.opts = L.default_opts(prec, **opt_kw)
+        full = self.plan.info()
+        # first configure with the budget to learn the full size
+        budget = int(ws_bytes) if ws_bytes is not None else int(ws_budget)
+        mb = self.plan.configure(self.opts, budget)
+        inf = self.plan.info()
+        if ws_bytes is None:
+            ws_bytes = min(budget, inf["ws_full_bytes"])
+            mb = self.plan.configure(self.opts, ws_bytes)
+        self.ws_bytes = int(ws_bytes)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.plan.bind(mb, self.device)
+        self.sum_m = full["sum_m"]
+        self.sum_n3 = full["sum_n3"]
+        self.Kv = torch.from_numpy(np.ascontiguousarray(K.val).reshape(-1)).to(self.device)
+        self.Sv = torch.from_numpy(np.ascontiguousarray(S.val).reshape(-1)).to(self.device)
+        bsq = self.bs * self.bs
+        self.Dcols = torch.zeros(self.sum_m * bsq, dtype=torch.float64, device=self.device)
+        self.D = torch.zeros(self.sum_m * bsq, dtype=torch.float64, device=self.device)
+        self.stats = torch.zeros(self.nb * C.sizeof(L.MolStats), dtype=torch.uint8, device=self.device)
+        self.mu = system.mu
+        self.features = None
+
+    def set_opts(self, **kw):
+        for k, v in kw.items():
+            setattr(self.opts, k, v)
+
+    def want_features(self):
+        torch = _torch()
+        self.features = torch.zeros(self.nb * L.MLP_NFEAT, dtype=torch.float32, device=self.device)
+        self.opts.d_features = self.features.data_ptr()
+
+    def run(self, mu=None, stream=None, scatter=True):
+        mu = self.mu if mu is None else mu
+        st = _stream_ptr(stream, self.device)
+        L.check(L.lib().nolsm_sign_batch(
+            self.plan.h, C.c_void_p(self.Kv.data_ptr()), C.c_void_p(self.Sv.data_ptr()), float(mu),
+            C.byref(self.opts), C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+            C.c_void_p(self.Dcols.data_ptr()), C.c_void_p(self.D.data_ptr() if scatter else None),
+            C.c_void_p(self.stats.data_ptr()), C.c_void_p(st)))
+
+    def assemble(self, stream=None):
+        st = _stream_ptr(stream, self.device)
+        L.check(L.lib().nolsm_assemble_D(self.plan.h, C.c_void_p(self.Dcols.data_ptr()),
+                                         C.c_void_p(self.D.data_ptr()), C.c_void_p(st)))
+
+    def host_stats(self):
+        raw = self.stats.cpu().numpy()
+        return raw.view(np.dtype(L.MOLSTATS_DTYPE))
+
+    def host_dcols(self):
+        """List of (n_J, bs) arrays, one per molecule."""
+        flat = self.Dcols.cpu().numpy()
+        ex = self.plan.export()
+        sp = ex["sub_ptr"]
+        bs = self.bs
+        out = []
+        for J in range(self.nb):
+            a, b = sp[J] * bs * bs, sp[J + 1] * bs * bs
+            out.append(flat[a:b].reshape(-1, bs))
+        return out
+
+    def host_D(self):
+        return self.D.cpu().numpy().reshape(-1, self.bs, self.bs)
+
+
+def mlp_forward(params, norm, x, out, stream=None):
+    torch = _torch()
+    st = _stream_ptr(stream, x.device)
+    L.check(L.lib().nolsm_mlp_forward(C.c_void_p(params.data_ptr()), C.c_void_p(norm.data_ptr()),
+                                      C.c_void_p(x.data_ptr()), int(x.shape[0]),
+                                      C.c_void_p(out.data_ptr()), C.c_void_p(st)))
+
+
+def mlp_loss_grad(params, norm, x, y, grad, loss, stream=None):
+    st = _stream_ptr(stream, x.device)
+    L.check(L.lib().nolsm_mlp_loss_grad(C.c_void_p(params.data_ptr()), C.c_void_p(norm.data_ptr()),
+                                        C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), int(x.shape[0]),
+                                        C.c_void_p(grad.data_ptr()), C.c_void_p(loss.data_ptr()),
+                                        C.c_void_p(st)))
+
+
+def mlp_adam(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    st = _stream_ptr(stream, params.device)
+    L.check(L.lib().nolsm_mlp_adam(C.c_void_p(params.data_ptr()), C.c_void_p(grad.data_ptr()),
+                                   C.c_void_p(m.data_ptr()), C.c_void_p(v.data_ptr()), int(t), float(lr),
+                                   float(b1), float(b2), float(eps), C.c_void_p(st)))

@@ -1,0 +1,154 @@
+"""The C ABI on the CPU: the library loads, exports every declared symbol, its
+struct layouts match the binding, and the plan (pure host work) equals the
+oracle's merge exactly. No kernel is launched here."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import nolsm as o
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nolsm.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2104_08245_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libnolsm.so not built (run __graft_entry__.build())")
+    return _lib
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nolsm_[A-Za-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(L):
+    lib = L.lib()
+    names = declared_functions()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTED)
+
+
+def test_struct_layouts_match_header(L, tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "nolsm.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\n", sizeof(nolsm_pattern), sizeof(nolsm_solve_opts), sizeof(nolsm_mol_stats), sizeof(nolsm_plan_sizes));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(nolsm_solve_opts, d_mlp), offsetof(nolsm_solve_opts, sched),
+         offsetof(nolsm_solve_opts, d_features), offsetof(nolsm_solve_opts, debug_poison_mol),
+         offsetof(nolsm_plan_sizes, ws_full_bytes));
+  return 0; }
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    got = [int(x) for x in out]
+    want = [C.sizeof(L.Pattern), C.sizeof(L.SolveOpts), C.sizeof(L.MolStats), C.sizeof(L.PlanSizes),
+            L.SolveOpts.d_mlp.offset, L.SolveOpts.sched.offset, L.SolveOpts.d_features.offset,
+            L.SolveOpts.debug_poison_mol.offset, L.PlanSizes.ws_full_bytes.offset]
+    assert got == want
+    assert np.dtype(L.MOLSTATS_DTYPE).itemsize == C.sizeof(L.MolStats)
+
+
+def test_plan_equals_oracle_merge(L, config1):
+    from paper_2104_08245_amd import Plan
+    s = config1
+    p = Plan(s.K.nb, s.K.bs, s.K.row_ptr, s.K.col_idx, s.S.row_ptr, s.S.col_idx)
+    ex = p.export()
+    ref = o.plan_arrays(s.K.nb, s.K.row_ptr, s.K.col_idx, s.S.row_ptr, s.S.col_idx)
+    for k in ("sub_ptr", "sub_blk", "self_pos", "D_row_ptr", "D_col_idx", "scatter_pos"):
+        assert np.array_equal(ex[k], ref[k]), k
+    inf = p.info()
+    m = np.diff(ref["sub_ptr"])
+    assert inf["sum_m"] == m.sum() and inf["m_min"] == m.min() and inf["m_max"] == m.max()
+    assert inf["sum_n3"] == pytest.approx(((6 * m) ** 3).sum())
+
+
+def _random_pair_patterns(rng, nb, pk, ps):
+    def sym(p):
+        A = rng.random((nb, nb)) < p
+        A = A | A.T | np.eye(nb, dtype=bool)
+        rp = np.concatenate([[0], np.cumsum(A.sum(1))]).astype(np.int32)
+        ci = np.concatenate([np.nonzero(A[i])[0] for i in range(nb)]).astype(np.int32)
+        return rp, ci
+    return sym(pk), sym(ps)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_plan_merges_different_patterns(L, seed):
+    from paper_2104_08245_amd import Plan
+    rng = np.random.default_rng(seed)
+    nb = 37
+    (krp, kci), (srp, sci) = _random_pair_patterns(rng, nb, 0.08, 0.12)
+    p = Plan(nb, 6, krp, kci, srp, sci)
+    ex = p.export()
+    ref = o.plan_arrays(nb, krp, kci, srp, sci)
+    for k in ("sub_ptr", "sub_blk", "self_pos", "D_row_ptr", "D_col_idx", "scatter_pos"):
+        assert np.array_equal(ex[k], ref[k]), k
+
+
+@pytest.mark.parametrize("case", ["unsorted", "no_diag", "asym", "range", "rowptr"])
+def test_malformed_patterns_rejected(L, case):
+    from paper_2104_08245_amd import Plan, NolsmError
+    rp = np.array([0, 2, 4], np.int32)
+    ci = np.array([0, 1, 0, 1], np.int32)
+    if case == "unsorted":
+        ci = np.array([1, 0, 0, 1], np.int32)
+    elif case == "no_diag":
+        rp, ci = np.array([0, 1, 3], np.int32), np.array([1, 0, 1], np.int32)
+    elif case == "asym":
+        rp, ci = np.array([0, 2, 3], np.int32), np.array([0, 1, 1], np.int32)
+    elif case == "range":
+        ci = np.array([0, 2, 0, 1], np.int32)
+    elif case == "rowptr":
+        rp = np.array([0, 3, 4], np.int32)
+    with pytest.raises(NolsmError) as e:
+        Plan(2, 6, rp, ci)
+    assert e.value.code == L.E_PATTERN
+
+
+def test_configure_chunks_and_workspace_errors(L, config1):
+    from paper_2104_08245_amd import Plan, NolsmError
+    s = config1
+    p = Plan(s.K.nb, s.K.bs, s.K.row_ptr, s.K.col_idx)
+    opts = L.default_opts("fp16")
+    mb = p.configure(opts, 1 << 40)
+    inf = p.info()
+    assert inf["nchunks"] == 1 and mb == inf["meta_bytes"] > 0
+    full = inf["ws_full_bytes"]
+    p.configure(opts, full // 3)
+    assert p.info()["nchunks"] >= 3
+    with pytest.raises(NolsmError) as e:
+        p.configure(opts, 1024)
+    assert e.value.code == L.E_WORKSPACE
+    opts.sched = L.SCHED_PER_BUCKET
+    p.configure(opts, 1 << 40)
+    m = np.diff(s.K.row_ptr) * 6
+    buckets = len(set(((m + 63) // 64).tolist()))
+    assert p.info()["nchunks"] == buckets
+
+
+def test_bad_options_rejected(L, config1):
+    from paper_2104_08245_amd import Plan, NolsmError
+    s = config1
+    p = Plan(s.K.nb, s.K.bs, s.K.row_ptr, s.K.col_idx)
+    for kw in (dict(prec=7), dict(max_iter=1), dict(max_iter=500), dict(sched=9)):
+        opts = L.default_opts("fp64")
+        for k, v in kw.items():
+            setattr(opts, k, v)
+        with pytest.raises(NolsmError) as e:
+            p.configure(opts, 1 << 40)
+        assert e.value.code == L.E_ARG

@@ -1,0 +1,63 @@
+"""MLP kernels vs the FP64 CPU oracle: forward, loss/gradient, Adam."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def setup(torch, B, seed=0):
+    rng = np.random.default_rng(seed)
+    theta = mlp.init_params(rng)
+    x = rng.standard_normal((B, 12)) * 2 + 1
+    mean, std = x.mean(0), x.std(0) + 0.1
+    y = rng.uniform(0.3, 1.0, (B, 2))
+    dev = "cuda:0"
+    T = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
+    return theta, x, y, mean, std, T(theta), T(x), T(y), T(np.concatenate([mean, std]))
+
+
+@pytest.mark.parametrize("B", [1, 17, 256])
+def test_forward_and_grad_match_oracle(torch, B):
+    from paper_2104_08245_amd import mlp_forward, mlp_loss_grad
+    theta, x, y, mean, std, tp, tx, ty, tn = setup(torch, B)
+    xs = (x.astype(np.float32).astype(np.float64) - mean.astype(np.float32)) / std.astype(np.float32)
+    th32 = theta.astype(np.float32).astype(np.float64)
+    out = torch.zeros(B, 2, device="cuda:0")
+    mlp_forward(tp, tn, tx, out)
+    g = torch.zeros(mlp.NPARAM, device="cuda:0")
+    loss = torch.zeros(1, device="cuda:0")
+    mlp_loss_grad(tp, tn, tx, ty, g, loss)
+    torch.cuda.synchronize()
+    ref_out, _ = mlp.forward(th32, xs)
+    L, G = mlp.loss_and_grad(th32, xs, y.astype(np.float32).astype(np.float64))
+    assert np.allclose(out.cpu().numpy(), ref_out, rtol=1e-4, atol=1e-5)
+    assert abs(loss.item() - L) <= 1e-4 * max(1, L)
+    gg = g.cpu().numpy()
+    assert np.linalg.norm(gg - G) <= 1e-4 * np.linalg.norm(G)
+
+
+def test_adam_matches_oracle(torch):
+    from paper_2104_08245_amd import mlp_adam
+    rng = np.random.default_rng(3)
+    th = rng.standard_normal(mlp.NPARAM)
+    g = rng.standard_normal(mlp.NPARAM)
+    m = rng.standard_normal(mlp.NPARAM) * 0.1
+    v = rng.uniform(0, 0.1, mlp.NPARAM)
+    T = lambda a: torch.tensor(a.astype(np.float32), device="cuda:0")
+    tp, tg, tm, tv = T(th), T(g), T(m), T(v)
+    mlp_adam(tp, tg, tm, tv, 5, lr=1e-3)
+    torch.cuda.synchronize()
+    r, rm, rv = mlp.adam_step(th.astype(np.float32).astype(np.float64), g.astype(np.float32),
+                              m.astype(np.float32), v.astype(np.float32), 5, lr=1e-3)
+    assert np.allclose(tp.cpu().numpy(), r, rtol=1e-5, atol=1e-6)
+    assert np.allclose(tm.cpu().numpy(), rm, rtol=1e-5, atol=1e-7)
+    assert np.allclose(tv.cpu().numpy(), rv, rtol=1e-5, atol=1e-8)

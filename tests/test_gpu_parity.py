@@ -1,0 +1,213 @@
+"""GPU path vs the CPU oracle, through the C ABI (ctypes binding).
+
+Bars: FP64 relative Frobenius error <= 1e-10 (whole Dcols of every molecule,
+and D), traces to 1e-10; FP32 <= 1e-5 relative; FP16 / BF16 per-molecule
+band-energy error and Dcols error within the stated bounds below. Integer
+outputs (pattern, positions, statuses) are compared exactly.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import nolsm as o
+
+pytestmark = pytest.mark.gpu
+
+# stated error bounds of the mixed-precision paths vs the FP64 oracle
+MIXED = {"fp16": dict(dcols=5e-3, energy=1e-3), "bf16": dict(dcols=4e-2, energy=1e-2)}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ref1(config1):
+    return o.nolsm(config1)
+
+
+def solve(system, prec, **kw):
+    from paper_2104_08245_amd import Solver
+    import torch
+    say(f"[gpu] solve prec={prec} nmol={system.nmol} opts={kw}")
+    sv = Solver(system, prec=prec, device="cuda:0", **kw)
+    sv.run()
+    torch.cuda.synchronize()
+    return sv
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_fp64_matches_oracle_config1(torch, config1, ref1):
+    sv = solve(config1, "fp64")
+    st = sv.host_stats()
+    dc = sv.host_dcols()
+    assert np.all(st["status"] == 0)
+    worst = max(rel(dc[J], ref1.Dcols[J]) for J in range(config1.nmol))
+    say("fp64 worst per-molecule rel-F", worst)
+    assert worst <= 1e-10
+    D = sv.host_D()
+    assert rel(D, ref1.D_val) <= 1e-10
+    assert np.allclose(st["trace_SD"], ref1.N, rtol=0, atol=1e-10)
+    assert np.allclose(st["energy_KD"], ref1.E, rtol=0, atol=1e-10)
+    assert np.all(np.abs(st["iters"] - ref1.iters) <= 1)
+    assert np.all(st["resid"] < 1e-10)
+
+
+def test_fp32_matches_oracle_config1(torch, config1, ref1):
+    sv = solve(config1, "fp32")
+    st = sv.host_stats()
+    dc = sv.host_dcols()
+    assert np.all(st["status"] == 0)
+    worst = max(rel(dc[J], ref1.Dcols[J]) for J in range(config1.nmol))
+    say("fp32 worst rel-F", worst, "iters", st["iters"].min(), st["iters"].max())
+    assert worst <= 1e-5
+    assert np.abs(st["energy_KD"] - ref1.E).max() <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_mixed_within_stated_error_config1(torch, config1, ref1, prec):
+    sv = solve(config1, prec)
+    st = sv.host_stats()
+    dc = sv.host_dcols()
+    assert np.all(st["status"] == 0)
+    errs = np.array([rel(dc[J], ref1.Dcols[J]) for J in range(config1.nmol)])
+    de = np.abs(st["energy_KD"] - ref1.E)
+    say(f"{prec}: Dcols rel-F max {errs.max():.3e} mean {errs.mean():.3e}; |dE_J| max {de.max():.3e} "
+        f"mean {de.mean():.3e}; iters {st['iters'].min()}..{st['iters'].max()} fp32 {st['iters_fp32'][0]}")
+    assert errs.max() <= MIXED[prec]["dcols"]
+    assert de.max() <= MIXED[prec]["energy"]
+    assert np.all(st["iters_fp32"] == 2)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_schedules_and_replays_bit_identical(torch, config1, prec):
+    from paper_2104_08245_amd import _lib as L
+    base = solve(config1, prec, sched=L.SCHED_STREAM)
+    ref = base.Dcols.cpu().numpy()
+    pb = solve(config1, prec, sched=L.SCHED_PER_BUCKET)
+    assert np.array_equal(pb.Dcols.cpu().numpy(), ref)
+    # graph capture needs a non-default stream; replay twice with work between
+    from paper_2104_08245_amd import Solver
+    sv = Solver(config1, prec=prec, device="cuda:0", sched=L.SCHED_GRAPH)
+    s = torch.cuda.Stream()
+    for rep in range(3):
+        say(f"[gpu] graph replay {rep} prec={prec}")
+        sv.Dcols.zero_()
+        torch.cuda.synchronize()
+        sv.run(stream=s)
+        s.synchronize()
+        assert np.array_equal(sv.Dcols.cpu().numpy(), ref), rep
+    assert sv.plan is not None
+
+
+def test_chunked_equals_single_chunk(torch, config1):
+    one = solve(config1, "fp16")
+    full = one.plan.info()["ws_full_bytes"]
+    many = solve(config1, "fp16", ws_bytes=full // 4 + 4096)
+    assert many.plan.info()["nchunks"] >= 4
+    assert np.array_equal(many.Dcols.cpu().numpy(), one.Dcols.cpu().numpy())
+    assert np.array_equal(many.D.cpu().numpy(), one.D.cpu().numpy())
+
+
+def test_assemble_equals_fused_scatter(torch, config1):
+    sv = solve(config1, "fp64")
+    fused = sv.D.cpu().numpy().copy()
+    sv.D.zero_()
+    sv.assemble()
+    torch.cuda.synchronize()
+    assert np.array_equal(sv.D.cpu().numpy(), fused)
+
+
+def test_not_spd_is_flagged_per_molecule(torch, config1, ref1):
+    from paper_2104_08245_amd import _lib as L, NolsmError
+    sv = solve(config1, "fp64", debug_poison_mol=5)
+    st = sv.host_stats()
+    assert st["status"][5] == L.MOL_NOT_SPD
+    assert np.all(np.delete(st["status"], 5) == 0)
+    dc = sv.host_dcols()
+    assert np.all(dc[5] == 0)
+    assert rel(dc[6], ref1.Dcols[6]) <= 1e-10
+    sv.set_opts(sync_errors=1)
+    with pytest.raises(NolsmError) as e:
+        sv.run()
+    assert e.value.code == L.E_NOT_SPD
+
+
+def test_divergence_restarts_from_gershgorin(torch, config1, ref1):
+    sv = solve(config1, "fp64", debug_scale_mult=3.0)
+    st = sv.host_stats()
+    assert np.all(st["fallback"] == 1) and np.all(st["status"] == 0)
+    dc = sv.host_dcols()
+    worst = max(rel(dc[J], ref1.Dcols[J]) for J in range(config1.nmol))
+    assert worst <= 1e-10
+
+
+def test_noconv_flag(torch, config1):
+    from paper_2104_08245_amd import _lib as L, NolsmError
+    sv = solve(config1, "fp64", max_iter=3)
+    st = sv.host_stats()
+    assert np.all(st["status"] == L.MOL_NOCONV)
+    sv.set_opts(sync_errors=1)
+    with pytest.raises(NolsmError) as e:
+        sv.run()
+    assert e.value.code == L.E_NOCONV
+
+
+def test_mu_outside_spectrum(torch, config1):
+    # mu above the spectrum: sign = -I, Dcols = S_J^-1 columns; below: zero
+    Js = [0, 33]
+    hi = o.nolsm(config1, mu=50.0, molecules=Js)
+    sv = solve(config1, "fp64")
+    sv.run(mu=50.0)
+    torch.cuda.synchronize()
+    dc = sv.host_dcols()
+    for J in Js:
+        assert rel(dc[J], hi.Dcols[J]) <= 1e-10
+    sv.run(mu=-50.0)
+    torch.cuda.synchronize()
+    assert np.abs(sv.Dcols.cpu().numpy()).max() < 1e-12
+
+
+def test_features_match_oracle(torch, config1):
+    from oracle import mlp
+    from paper_2104_08245_amd import Solver
+    sv = Solver(config1, prec="fp64", device="cuda:0")
+    sv.want_features()
+    sv.run()
+    torch.cuda.synchronize()
+    f = sv.features.cpu().numpy().reshape(config1.nmol, 12)
+    r = o.nolsm(config1, molecules=[2, 40], keep_x=True)
+    for J in (2, 40):
+        ref = mlp.features(r.xs[J][1])
+        assert np.allclose(f[J], ref, rtol=1e-5, atol=1e-6), (J, f[J], ref)
+
+
+def test_config2_sample_fp64(torch):
+    s = synth.make_config(2)
+    rng = s.sample_rng
+    mols = sorted(rng.choice(s.nmol, 8, replace=False).tolist())
+    say("[cpu] oracle on config-2 sample", mols)
+    ref = o.nolsm(s, molecules=mols)
+    sv = solve(s, "fp64")
+    st = sv.host_stats()
+    dc = sv.host_dcols()
+    assert np.all(st["status"] == 0)
+    for J in mols:
+        assert rel(dc[J], ref.Dcols[J]) <= 1e-10, J
+        assert abs(st["energy_KD"][J] - ref.E[J]) <= 1e-10
+    # properties that hold for every molecule at full size
+    assert np.all(st["resid"] < 1e-10)
+    assert abs(st["trace_SD"].sum() / s.nmol - 4.0) < 0.05
