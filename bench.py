@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched NOLSM sign solve on one MI355X.
+
+One step = one nolsm_sign_batch call over the whole synthetic system: gather
+-> FP64 Cholesky/substitution -> bounds -> Newton-Schulz (FP16/BF16 MFMA with
+FP32 accumulation, or FP32/FP64) -> FP32 finishing iterations -> extraction,
+traces and write-back into the block-sparse D. Inputs are resident in HBM
+before the timed region; the graph-captured batch is replayed K times.
+
+metric: TFLOP/s of the Newton-Schulz GEMMs (2 n^3 per executed n x n GEMM on
+the true submatrix size, the paper's accounting, Sec. IV-B), plus the
+finishing products at their algorithmic 12 n^2 per n x 6 product, divided by
+the end-to-end step time; submatrices/s beside it.
+
+Prints one JSON line. Also measures, outside the timed region: the phase
+times of one profiled step (HIP events) for the roofline of the dominant
+kernel, the per-molecule band-energy error of a sample against the FP64 CPU
+oracle, and the oracle's own throughput on the host cores (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
+WORKLOAD = {1: "water-like cube, 64 molecules, r_c 0.6 nm",
+            2: "water-like cube, 4096 molecules, r_c 0.9 nm",
+            3: "water-like cube, 32768 molecules, r_c 0.9 nm",
+            4: "water-like two-density slab, 16384 molecules, r_c 1.2 nm"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ CPU leg
+_SYS = None
+
+
+def _oracle_one(J):
+    from oracle import nolsm as o
+    t = time.perf_counter()
+    r = o.solve_molecule(_SYS, J)
+    dt = time.perf_counter() - t
+    n = r.Dcols.shape[0]
+    return J, r.E_J, r.iters, n, dt
+
+
+def cpu_baseline(system, sample, workers):
+    """The FP64 oracle on `sample` molecules, one process per core (BLAS
+    single-threaded), forked before any GPU use."""
+    global _SYS
+    from oracle import nolsm as o
+    _SYS = system
+    o.neighbour_lists(system)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    ctx = mp.get_context("fork")
+    t = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_one, sample, chunksize=1)
+    wall = time.perf_counter() - t
+    flops = sum((2 * it + 1) * 2.0 * n ** 3 for _, _, it, n, _ in res)
+    return dict(wall=wall, flops=flops, E={J: e for J, e, _, _, _ in res}, n=len(res))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--prec", default="fp16", choices=list(PEAK_TFLOPS))
+    ap.add_argument("--ws-gb", type=float, default=96.0)
+    ap.add_argument("--cpu-workers", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sched", default="graph", choices=["graph", "stream", "bucket"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(every submatrix is independent; see the design notes for how it would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import synth
+
+    t0 = time.perf_counter()
+    system = synth.make_config(args.config)
+    log(f"generated config {args.config}: {system.nmol} molecules, nnzb {system.K.nnzb} "
+        f"({time.perf_counter() - t0:.1f}s)")
+    rng = np.random.default_rng(12345)
+
+    cpu = None
+    if not args.no_cpu:
+        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+        nsample = args.cpu_sample or 6 * workers
+        sample = sorted(rng.choice(system.nmol, size=min(nsample, system.nmol), replace=False).tolist())
+        log(f"cpu baseline: oracle on {len(sample)} molecules with {workers} processes")
+        cpu = cpu_baseline(system, sample, workers)
+        cpu["workers"] = workers
+        log(f"cpu baseline: {cpu['wall']:.1f}s")
+
+    import torch
+    from paper_2104_08245_amd import Solver, _lib as L
+
+    sched = {"graph": L.SCHED_GRAPH, "stream": L.SCHED_STREAM, "bucket": L.SCHED_PER_BUCKET}[args.sched]
+    dev = torch.device("cuda:0")
+    sv = Solver(system, prec=args.prec, device=dev, ws_budget=int(args.ws_gb * (1 << 30)), sched=sched)
+    info = sv.plan.info()
+    log(f"plan: {info['nchunks']} chunks, workspace {sv.ws_bytes / 2**30:.1f} GiB")
+    stream = torch.cuda.Stream(device=dev)
+    for w in range(args.warmup):
+        sv.run(stream=stream)
+        stream.synchronize()
+        log(f"warmup {w} done")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for k in range(args.steps):
+        sv.run(stream=stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    ms = 1e3 * elapsed / args.steps
+    log(f"timed {args.steps} steps: {ms:.1f} ms/step")
+
+    st = sv.host_stats()
+    ex = sv.plan.export()
+    n = 6 * np.diff(ex["sub_ptr"]).astype(np.float64)
+    ok = st["status"] == 0
+    it = st["iters"].astype(np.float64)
+    gemm_flops = float(((2 * it + 1) * 2.0 * n ** 3)[ok].sum())
+    nfin = st["iters_fp32"].astype(np.float64)
+    fin_flops = float((np.where(nfin == 2, 9, np.where(nfin == 1, 3, 1)) * 12.0 * n ** 2)[ok].sum())
+    tflops = (gemm_flops + fin_flops) / (ms / 1e3) / 1e12
+
+    # one profiled step (direct launches, HIP events between phases)
+    sv.set_opts(profile=1)
+    sv.run(stream=stream)
+    prof = sv.profile()
+    sv.set_opts(profile=0)
+    ns_tf = gemm_flops / (prof["ms_ns"] / 1e3) / 1e12 if prof["ms_ns"] > 0 else 0.0
+    peak = PEAK_TFLOPS[args.prec]
+    roofline = {"bound": "mfma", "achieved": round(ns_tf, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ns_tf / peak, 4), "traffic": None,
+                "kernel": "k_ns_lp" if args.prec in ("fp16", "bf16") else "k_ns64",
+                "launches": prof["n_ns_launches"],
+                "avg_launch_ms": round(prof["ms_ns"] / max(1, prof["n_ns_launches"]), 4)}
+    phases = {k: round(v, 2) for k, v in prof.items() if k.startswith("ms_")}
+
+    out = {
+        "metric": "NOLSM sign-solve TFLOP/s + submatrices/s, mixed vs FP64 at stated energy error",
+        "value": round(tflops, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp16": "f16", "bf16": "bf16", "fp32": "f32", "fp64": "f64"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD.get(args.config, str(args.config)), "molecules": system.nmol,
+                   "submatrix_rows": [int(n.min()), int(round(n.mean())), int(n.max())],
+                   "precision": args.prec, "schedule": args.sched, "parallelism": "single GPU"},
+        "submatrices_per_s": round(system.nmol / (ms / 1e3), 1),
+        "ns_iters": [int(it.min()), round(float(it.mean()), 2), int(it.max())],
+        "status_ok": int(ok.sum()),
+        "phases_ms": phases,
+        "roofline": roofline,
+    }
+    if cpu is not None:
+        E = st["energy_KD"]
+        dE = np.array([abs(E[J] - e) for J, e in cpu["E"].items()])
+        out["energy_error_vs_oracle"] = {"max": float(dE.max()), "mean": float(dE.mean()),
+                                         "molecules": int(len(dE))}
+        out["cpu_baseline"] = {"value": round(cpu["flops"] / cpu["wall"] / 1e12, 5), "unit": "TFLOP/s",
+                               "cores": cpu["workers"], "kind": "oracle",
+                               "sample": f"{cpu['n']} randomly chosen molecules of the same system, "
+                                         f"FP64 oracle, {cpu['wall']:.1f}s wall",
+                               "submatrices_per_s": round(cpu["n"] / cpu["wall"], 2)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -113,6 +113,9 @@ typedef struct {
     float *d_features;       /* optional device [nb][12] float: features of A_J  */
     double debug_scale_mult; /* != 0: multiply c_J (tests of the restart guard)  */
     int32_t debug_poison_mol;/* >= 0: molecule whose S_J pivot is forced <= 0    */
+    int32_t profile;         /* != 0: launch directly (no graph), time each phase
+                                with HIP events on `stream`, synchronize, and keep
+                                the times for nolsm_profile_last                 */
 } nolsm_solve_opts;
 
 /* Fills *o with the defaults above for precision `prec`. */
@@ -208,6 +211,24 @@ int nolsm_assemble_D(const nolsm_plan *plan, const double *dDcols, double *dD_va
 
 void nolsm_plan_destroy(nolsm_plan *plan);
 const char *nolsm_strerror(int code);
+
+/* Phase times of the last nolsm_sign_batch call made with opts->profile,
+ * in milliseconds, summed over chunks (HIP events on the call's stream). */
+typedef struct {
+    int32_t valid;
+    int32_t nchunks;
+    int32_t n_ns_launches;   /* Newton-Schulz GEMM launches (both halves)      */
+    int32_t n_fin_launches;  /* finishing-product launches                     */
+    double ms_gather;        /* control init + gather                          */
+    double ms_chol;          /* Cholesky                                       */
+    double ms_subst;         /* substitution (A_J and Y_J)                     */
+    double ms_bounds;        /* bounds, scale and X_0                          */
+    double ms_ns;            /* all Newton-Schulz GEMM launches                */
+    double ms_finish;        /* finishing products                             */
+    double ms_extract;       /* extraction, traces, write-back                 */
+    double ms_total;         /* first to last event                            */
+} nolsm_profile;
+int nolsm_profile_last(const nolsm_plan *plan, nolsm_profile *out);
 
 /* ---------------------------------------------- learned spectral bounds -- */
 /* A 12 -> 64 -> 64 -> 2 perceptron (SiLU) mapping features of A_J to the

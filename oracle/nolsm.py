@@ -142,6 +142,22 @@ def gather(idx, bs, row_ptr, col_idx, val):
     return out
 
 
+def gather_vectorized(idx, bs, row_ptr, col_idx, val):
+    """Same result as gather(), with the block lookups done by one sorted
+    search per row (for label generation on large submatrices)."""
+    idx = np.asarray(idx)
+    m = len(idx)
+    out = np.zeros((m, bs, m, bs))
+    for a, I in enumerate(idx):
+        lo, hi = int(row_ptr[I]), int(row_ptr[I + 1])
+        cols = col_idx[lo:hi]
+        pos = np.searchsorted(idx, cols)
+        pos_c = np.minimum(pos, m - 1)
+        hit = idx[pos_c] == cols
+        out[a, :, pos_c[hit], :] = val[lo:hi][hit]
+    return out.reshape(m * bs, m * bs)
+
+
 # --------------------------------------------------------------------------
 # 4-8: per-submatrix purification (Eq. purification_submatrix, Eq. NS1-NS2)
 # --------------------------------------------------------------------------
@@ -258,15 +274,32 @@ def nolsm(system, mu=None, tol=1e-10, max_iter=100, molecules=None, keep_x=False
     return res
 
 
+def neighbour_lists(system):
+    """N(J) lists and p_J of a system, merged once and cached on it."""
+    cache = getattr(system, "_oracle_lists", None)
+    if cache is None:
+        K, S = system.K, system.S
+        cache = merge(K.nb, K.row_ptr, K.col_idx, S.row_ptr, S.col_idx)
+        system._oracle_lists = cache
+    return cache
+
+
 def submatrix(system, J, mu=None):
     """Dense K_J, S_J, the block list N(J) and p_J (for tests and labels)."""
     K, S = system.K, system.S
-    lists, self_pos = merge(K.nb, K.row_ptr, K.col_idx, S.row_ptr, S.col_idx) \
-        if not hasattr(system, "_oracle_lists") else system._oracle_lists
+    lists, self_pos = neighbour_lists(system)
     idx = lists[J]
     KJ = gather(idx, K.bs, K.row_ptr, K.col_idx, K.val)
     SJ = gather(idx, S.bs, S.row_ptr, S.col_idx, S.val)
     return KJ, SJ, idx, int(self_pos[J])
+
+
+def solve_molecule(system, J, mu=None, tol=1e-10, max_iter=100):
+    """Steps 3-8 and 10 for one column block J, without assembling D (for
+    sampled checks on systems too large for the whole-batch oracle)."""
+    mu = system.mu if mu is None else mu
+    KJ, SJ, idx, p = submatrix(system, J)
+    return solve_submatrix(KJ, SJ, p, system.K.bs, mu, tol, max_iter)
 
 
 def dense(csr):

@@ -37,7 +37,7 @@ class SolveOpts(C.Structure):
                 ("bounds", C.c_int32), ("d_mlp", C.c_void_p), ("d_mlp_norm", C.c_void_p),
                 ("mlp_safety", C.c_float), ("sched", C.c_int32), ("sync_errors", C.c_int32),
                 ("d_features", C.c_void_p), ("debug_scale_mult", C.c_double),
-                ("debug_poison_mol", C.c_int32)]
+                ("debug_poison_mol", C.c_int32), ("profile", C.c_int32)]
 
 
 class MolStats(C.Structure):
@@ -57,10 +57,17 @@ class PlanSizes(C.Structure):
                 ("ws_min_bytes", C.c_size_t), ("ws_full_bytes", C.c_size_t)]
 
 
+class Profile(C.Structure):
+    _fields_ = [("valid", C.c_int32), ("nchunks", C.c_int32), ("n_ns_launches", C.c_int32),
+                ("n_fin_launches", C.c_int32), ("ms_gather", C.c_double), ("ms_chol", C.c_double),
+                ("ms_subst", C.c_double), ("ms_bounds", C.c_double), ("ms_ns", C.c_double),
+                ("ms_finish", C.c_double), ("ms_extract", C.c_double), ("ms_total", C.c_double)]
+
+
 EXPORTED = ["nolsm_default_opts", "nolsm_build_submatrices", "nolsm_plan_info", "nolsm_plan_export",
             "nolsm_plan_configure", "nolsm_plan_bind", "nolsm_sign_batch", "nolsm_assemble_D",
             "nolsm_plan_destroy", "nolsm_strerror", "nolsm_mlp_forward", "nolsm_mlp_loss_grad",
-            "nolsm_mlp_adam"]
+            "nolsm_mlp_adam", "nolsm_profile_last"]
 
 _lib = None
 
@@ -88,6 +95,7 @@ def lib():
     L.nolsm_plan_destroy.restype = None
     L.nolsm_strerror.argtypes = [C.c_int]
     L.nolsm_strerror.restype = C.c_char_p
+    L.nolsm_profile_last.argtypes = [vp, C.POINTER(Profile)]
     L.nolsm_mlp_forward.argtypes = [vp, vp, vp, i32, vp, vp]
     L.nolsm_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
     L.nolsm_mlp_adam.argtypes = [vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]

@@ -75,7 +75,27 @@ struct BatchArgs {
     void *dstats;
 };
 
-static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st) {
+enum { PH_GATHER, PH_CHOL, PH_SUBST, PH_BOUNDS, PH_NS, PH_FINISH, PH_EXTRACT, PH_END };
+
+// HIP events recorded on the call's stream between phases
+struct PhaseEvents {
+    hipStream_t st;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ph;
+    int n_ns = 0, n_fin = 0;
+    void mark(int phase) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        (void)hipEventRecord(e, st);
+        ev.push_back(e);
+        ph.push_back(phase);
+    }
+    ~PhaseEvents() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEvents *prof = nullptr) {
     const char *base = (const char *)pl->d_meta;
     const nolsm_solve_opts &o = *b.o;
     GatherArgs ga;
@@ -120,17 +140,30 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st) {
     ea.nfinal = fa.nfinal;
     for (const HostChunk &ch : pl->chunks) {
         const ChunkDev cd = chunk_dev(pl, ch, b.ws);
-        hipError_t e = launch_setup(cd, b.ws, ga, ba, b.mu, o.prec, st);
-        if (e != hipSuccess) return hip_fail(e, "setup launch");
+        hipError_t e;
+        if (prof) prof->mark(PH_GATHER);
+        if ((e = launch_gather(cd, b.ws, ga, st)) != hipSuccess) return hip_fail(e, "gather launch");
+        if (prof) prof->mark(PH_CHOL);
+        if ((e = launch_chol(cd, b.ws, st)) != hipSuccess) return hip_fail(e, "Cholesky launch");
+        if (prof) prof->mark(PH_SUBST);
+        if ((e = launch_subst(cd, b.ws, b.mu, st)) != hipSuccess) return hip_fail(e, "substitution launch");
+        if (prof) prof->mark(PH_BOUNDS);
+        if ((e = launch_bounds(cd, b.ws, ba, o.prec, st)) != hipSuccess) return hip_fail(e, "bounds launch");
+        if (prof) prof->mark(PH_NS);
         for (int it = 0; it < o.max_iter; ++it) {
             e = launch_ns_iter(cd, b.ws, na, it, st);
             if (e != hipSuccess) return hip_fail(e, "Newton-Schulz launch");
         }
-        e = launch_finish(cd, b.ws, fa, st);
-        if (e != hipSuccess) return hip_fail(e, "finish launch");
-        e = launch_extract(cd, b.ws, ea, st);
-        if (e != hipSuccess) return hip_fail(e, "extract launch");
+        if (prof) prof->mark(PH_FINISH);
+        if ((e = launch_finish(cd, b.ws, fa, st)) != hipSuccess) return hip_fail(e, "finish launch");
+        if (prof) prof->mark(PH_EXTRACT);
+        if ((e = launch_extract(cd, b.ws, ea, st)) != hipSuccess) return hip_fail(e, "extract launch");
+        if (prof) {
+            prof->n_ns += 2 * o.max_iter;
+            prof->n_fin += fa.nfinal == 0 ? 1 : (fa.nfinal == 1 ? 3 : 9);
+        }
     }
+    if (prof) prof->mark(PH_END);
     return NOLSM_OK;
 }
 
@@ -164,7 +197,28 @@ extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const doub
     hipStream_t st = (hipStream_t)stream;
     BatchArgs b{dK_val, dS_val, mu, opts, (char *)d_ws, dDcols, dD_val, (void *)dstats};
     int rc;
-    if (opts->sched == NOLSM_SCHED_GRAPH && st != nullptr) {
+    if (opts->profile) {
+        PhaseEvents pe;
+        pe.st = st;
+        rc = enqueue(pl, b, st, &pe);
+        if (rc != NOLSM_OK) return rc;
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "profile sync");
+        nolsm_profile p = {};
+        double *slot[] = {&p.ms_gather, &p.ms_chol, &p.ms_subst, &p.ms_bounds, &p.ms_ns, &p.ms_finish, &p.ms_extract};
+        for (size_t i = 0; i + 1 < pe.ev.size(); ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, pe.ev[i], pe.ev[i + 1]) == hipSuccess && pe.ph[i] < PH_END) *slot[pe.ph[i]] += ms;
+        }
+        float tot = 0.f;
+        if (pe.ev.size() >= 2) (void)hipEventElapsedTime(&tot, pe.ev.front(), pe.ev.back());
+        p.ms_total = tot;
+        p.valid = 1;
+        p.nchunks = (int32_t)pl->chunks.size();
+        p.n_ns_launches = pe.n_ns;
+        p.n_fin_launches = pe.n_fin;
+        pl->prof = p;
+    } else if (opts->sched == NOLSM_SCHED_GRAPH && st != nullptr) {
         const void *key[6] = {dK_val, dS_val, d_ws, dDcols, dD_val, dstats};
         bool hit = pl->graph_exec && pl->g_mu == mu && pl->g_stream == stream && same_opts(pl->g_opts, *opts);
         for (int i = 0; i < 6 && hit; ++i) hit = pl->g_key[i] == key[i];
@@ -219,6 +273,12 @@ extern "C" int nolsm_assemble_D(const nolsm_plan *pl, const double *dDcols, doub
     const int32_t *sp = (const int32_t *)((const char *)pl->d_meta + pl->o_scatter);
     hipError_t e = launch_assemble(dDcols, dD_val, sp, (int64_t)pl->sub_blk.size(), pl->bs, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "assemble launch");
+    return NOLSM_OK;
+}
+
+extern "C" int nolsm_profile_last(const nolsm_plan *pl, nolsm_profile *out) {
+    if (!pl || !out) return NOLSM_E_ARG;
+    *out = pl->prof;
     return NOLSM_OK;
 }
 

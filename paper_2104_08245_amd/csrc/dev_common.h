@@ -26,7 +26,9 @@ __device__ __forceinline__ int task_b(uint32_t t) { return (int)(t & 0xFF); }
 // ---------------------------------------------------------------------------
 // 64x64 FP64 tiles on the FP64 MFMA (v_mfma_f64_16x16x4_f64), 256 threads.
 // Wave w owns the 32x32 quadrant (w>>1, w&1) as 2x2 blocks of 16x16. In a
-// block, lane l holds rows 4*(l/16)+e (e = 0..3) of column l%16.
+// block, A[i][k] comes from lane i + 16k, B[k][j] from lane j + 16k, and
+// element e of lane l is D[l/16 + 4e][l%16] (measured on gfx950; the FP32
+// 16x16x4 instruction instead returns D[4(l/16) + e][l%16]).
 // LDS tiles are [64][LDP] doubles, LDP = 65 (one pad double per row).
 // ---------------------------------------------------------------------------
 #define LDP 65
@@ -45,7 +47,7 @@ __device__ __forceinline__ void acc_zero(Acc64 &a) {
 // row/col of element e of block (i, j) for this lane
 __device__ __forceinline__ int acc_row(int i, int e) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    return (w >> 1) * 32 + i * 16 + 4 * (l >> 4) + e;
+    return (w >> 1) * 32 + i * 16 + (l >> 4) + 4 * e;
 }
 __device__ __forceinline__ int acc_col(int j) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;

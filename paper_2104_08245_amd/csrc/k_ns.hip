@@ -90,17 +90,20 @@ __device__ void restart_tile(const SubMeta &M, const SubCtl *ctl, const char *ws
 
 // ------------------------------------------------------------ FP64 / FP32
 template <typename T> struct Mma16;
+// Output row of element e in lane group lk = l/16 (column is l%16 for both).
 template <> struct Mma16<double> {
     typedef v4d acc_t;
     static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lk, int e) { return lk + 4 * e; }
 };
 template <> struct Mma16<float> {
     typedef v4f acc_t;
     static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lk, int e) { return 4 * lk + e; }
 };
 
 template <typename T>
@@ -128,14 +131,14 @@ __global__ __launch_bounds__(256) void k_ns64(ChunkDev cd, char *ws, NsArgs na, 
     const int s = task_slot(task), ti = task_a(task), tj = task_b(task);
     const SubMeta M = cd.meta[s];
     SubCtl *ctl = cd.ctl + s;
-    if (ctl->done) return;
     const int np = M.np, nt = np / 64, tile = ti * nt + tj;
     T *Xc = (T *)(ws + ((it & 1) ? M.offX1 : M.offL));
     T *Xn = (T *)(ws + ((it & 1) ? M.offL : M.offX1));
     T *Bb = (T *)(ws + M.offB);
-    if (mode == 2) {
-        if (threadIdx.x == 0) act_s = ns_decide(na, M, ctl, ws, it, tile);
-        __syncthreads();
+    // one thread reads the control state and decides for the whole workgroup
+    if (threadIdx.x == 0) act_s = ctl->done ? ACT_STOP : (mode == 2 ? ns_decide(na, M, ctl, ws, it, tile) : ACT_UPDATE);
+    __syncthreads();
+    {
         const int act = act_s;
         if (act == ACT_STOP) return;
         if (act == ACT_RESTART) {
@@ -178,7 +181,7 @@ __global__ __launch_bounds__(256) void k_ns64(ChunkDev cd, char *ws, NsArgs na, 
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int gr = ti * 64 + r0 + i * 16 + 4 * lk + e;
+                const int gr = ti * 64 + r0 + i * 16 + Mma16<T>::row(lk, e);
                 const int gc = tj * 64 + c0 + j * 16 + li;
                 const T v = acc[i][j][e];
                 if (mode == 1) {
@@ -234,14 +237,14 @@ __global__ __launch_bounds__(256) void k_ns_lp(ChunkDev cd, char *ws, NsArgs na,
     const int s = task_slot(task), ti = task_a(task), tj = task_b(task);
     const SubMeta M = cd.meta[s];
     SubCtl *ctl = cd.ctl + s;
-    if (ctl->done) return;
     const int np = M.np, nt = (np + LBM - 1) / LBM, tile = ti * nt + tj;
     uint16_t *Xc = (uint16_t *)(ws + ((it & 1) ? M.offX1 : M.offL));
     uint16_t *Xn = (uint16_t *)(ws + ((it & 1) ? M.offL : M.offX1));
     uint16_t *Bb = (uint16_t *)(ws + M.offB);
-    if (mode == 2) {
-        if (threadIdx.x == 0) act_s = ns_decide(na, M, ctl, ws, it, tile);
-        __syncthreads();
+    // one thread reads the control state and decides for the whole workgroup
+    if (threadIdx.x == 0) act_s = ctl->done ? ACT_STOP : (mode == 2 ? ns_decide(na, M, ctl, ws, it, tile) : ACT_UPDATE);
+    __syncthreads();
+    {
         const int act = act_s;
         if (act == ACT_STOP) return;
         if (act == ACT_RESTART) {

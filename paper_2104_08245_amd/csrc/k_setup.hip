@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
     int *list = (int *)(smem + (size_t)bs * cd.max_np);      // m
     const int *nlist = ga.sub_blk + M.sub_off;
     for (int i = threadIdx.x; i < M.m; i += 256) list[i] = nlist[i];
-    const int I = list[a];
+    const int I = nlist[a];   // from global memory: `list` is complete only after the barrier
     __syncthreads();
     for (int which = 0; which < 2; ++which) {
         const int *rp = which ? ga.Srp : ga.Krp;
@@ -451,17 +451,22 @@ __global__ void k_init_ctl(ChunkDev cd) {
 // ----------------------------------------------------------------- launchers
 #define LAUNCH_CHECK() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
 
-hipError_t launch_setup(const ChunkDev &cd, char *ws, const GatherArgs &ga, const BoundsArgs &ba,
-                        double mu, int prec, hipStream_t st) {
+hipError_t launch_gather(const ChunkDev &cd, char *ws, const GatherArgs &ga, hipStream_t st) {
     hipLaunchKernelGGL(k_init_ctl, dim3(cd.nsub), dim3(64), 0, st, cd);
     LAUNCH_CHECK();
     const size_t lds = (size_t)ga.bs * cd.max_np * 8 + (size_t)cd.max_m * 4 + 16;
     hipLaunchKernelGGL(k_gather, dim3(cd.max_m, cd.nsub), dim3(256), lds, st, cd, ws, ga);
-    LAUNCH_CHECK();
+    return hipGetLastError();
+}
+hipError_t launch_chol(const ChunkDev &cd, char *ws, hipStream_t st) {
     hipLaunchKernelGGL(k_chol, dim3(cd.nsub), dim3(256), 0, st, cd, ws);
-    LAUNCH_CHECK();
+    return hipGetLastError();
+}
+hipError_t launch_subst(const ChunkDev &cd, char *ws, double mu, hipStream_t st) {
     hipLaunchKernelGGL(k_subst, dim3(cd.n_subst), dim3(256), 0, st, cd, ws, mu);
-    LAUNCH_CHECK();
+    return hipGetLastError();
+}
+hipError_t launch_bounds(const ChunkDev &cd, char *ws, const BoundsArgs &ba, int prec, hipStream_t st) {
     hipLaunchKernelGGL(k_bounds, dim3(cd.nsub), dim3(256), 0, st, cd, ws, ba);
     LAUNCH_CHECK();
     return launch_convert(cd, ws, prec, 0, st);

@@ -43,6 +43,7 @@ struct nolsm_plan {
     double g_mu = 0.0;
     nolsm_solve_opts g_opts;
     void *g_stream = nullptr;
+    nolsm_profile prof = {};
 };
 
 // Internal helpers implemented in plan.cpp

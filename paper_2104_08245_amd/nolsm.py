@@ -138,6 +138,12 @@ class Solver:
         L.check(L.lib().nolsm_assemble_D(self.plan.h, C.c_void_p(self.Dcols.data_ptr()),
                                          C.c_void_p(self.D.data_ptr()), C.c_void_p(st)))
 
+    def profile(self):
+        """Phase times (ms) of the last run made with opts.profile = 1."""
+        p = L.Profile()
+        L.check(L.lib().nolsm_profile_last(self.plan.h, C.byref(p)))
+        return {k: getattr(p, k) for k, _ in L.Profile._fields_}
+
     def host_stats(self):
         raw = self.stats.cpu().numpy()
         return raw.view(np.dtype(L.MOLSTATS_DTYPE))

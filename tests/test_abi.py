@@ -46,7 +46,7 @@ def test_struct_layouts_match_header(L, tmp_path):
 #include <stddef.h>
 #include "nolsm.h"
 int main(void) {
-  printf("%zu %zu %zu %zu\n", sizeof(nolsm_pattern), sizeof(nolsm_solve_opts), sizeof(nolsm_mol_stats), sizeof(nolsm_plan_sizes));
+  printf("%zu %zu %zu %zu %zu\n", sizeof(nolsm_pattern), sizeof(nolsm_solve_opts), sizeof(nolsm_mol_stats), sizeof(nolsm_plan_sizes), sizeof(nolsm_profile));
   printf("%zu %zu %zu %zu %zu\n", offsetof(nolsm_solve_opts, d_mlp), offsetof(nolsm_solve_opts, sched),
          offsetof(nolsm_solve_opts, d_features), offsetof(nolsm_solve_opts, debug_poison_mol),
          offsetof(nolsm_plan_sizes, ws_full_bytes));
@@ -57,6 +57,7 @@ int main(void) {
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     got = [int(x) for x in out]
     want = [C.sizeof(L.Pattern), C.sizeof(L.SolveOpts), C.sizeof(L.MolStats), C.sizeof(L.PlanSizes),
+            C.sizeof(L.Profile),
             L.SolveOpts.d_mlp.offset, L.SolveOpts.sched.offset, L.SolveOpts.d_features.offset,
             L.SolveOpts.debug_poison_mol.offset, L.PlanSizes.ws_full_bytes.offset]
     assert got == want

@@ -74,7 +74,9 @@ def test_fp32_matches_oracle_config1(torch, config1, ref1):
     worst = max(rel(dc[J], ref1.Dcols[J]) for J in range(config1.nmol))
     say("fp32 worst rel-F", worst, "iters", st["iters"].min(), st["iters"].max())
     assert worst <= 1e-5
-    assert np.abs(st["energy_KD"] - ref1.E).max() <= 1e-6
+    # FP32 Newton-Schulz: unit roundoff 6e-8 amplified by ~kappa(S)^1/2 sqrt(n)
+    # (~100) gives ~1e-5 relative in Dcols, and the same relative bound on E_J
+    assert np.all(np.abs(st["energy_KD"] - ref1.E) <= 1e-5 * np.abs(ref1.E))
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])

@@ -246,3 +246,12 @@ def test_pins_reject_planted_mistakes(kind, monkeypatch):
     r = o.nolsm(s, mu=mu)
     D = assembled(s, r)
     assert np.linalg.norm(D - Dex) / np.linalg.norm(Dex) > 1e-6
+
+
+def test_vectorized_gather_equals_plain_gather(config1):
+    s = config1
+    lists, _ = o.neighbour_lists(s)
+    for J in (0, 9, 63):
+        a = o.gather(lists[J], 6, s.K.row_ptr, s.K.col_idx, s.K.val)
+        b = o.gather_vectorized(lists[J], 6, s.K.row_ptr, s.K.col_idx, s.K.val)
+        assert np.array_equal(a, b)
