@@ -44,6 +44,12 @@ def log(*a):
 _SYS = None
 
 
+def _single_thread():
+    # numpy's BLAS pool was created before the fork: limit it in each worker
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+
+
 def _oracle_one(J):
     from oracle import nolsm as o
     t = time.perf_counter()
@@ -64,7 +70,7 @@ def cpu_baseline(system, sample, workers):
         os.environ[k] = "1"
     ctx = mp.get_context("fork")
     t = time.perf_counter()
-    with ctx.Pool(workers) as pool:
+    with ctx.Pool(workers, initializer=_single_thread) as pool:
         res = pool.map(_oracle_one, sample, chunksize=1)
     wall = time.perf_counter() - t
     flops = sum((2 * it + 1) * 2.0 * n ** 3 for _, _, it, n, _ in res)

@@ -30,6 +30,11 @@ SOURCES = [("cube4096", 1002, 0.2), ("cube4096", 2002, 0.2), ("cube32768", 1003,
 _SYS = None
 
 
+def _single_thread():
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+
+
 def make(kind, cid):
     if kind == "cube4096":
         return synth.water_cube(4096, 0.9, config_id=cid)
@@ -65,7 +70,7 @@ def main(total=20000, out=None, procs=None):
         rng = np.random.default_rng(cid)
         cnt = min(int(round(total * share)), s.nmol)
         Js = sorted(rng.choice(s.nmol, cnt, replace=False).tolist())
-        with mp.get_context("fork").Pool(procs) as pool:
+        with mp.get_context("fork").Pool(procs, initializer=_single_thread) as pool:
             res = pool.map(one, Js, chunksize=8)
         for J, f, lo, hi, n in res:
             F.append(f)
