@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sched", default="graph", choices=["graph", "stream", "bucket"])
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also run one plain device-to-device copy of this many MiB "
+                         "(reference for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -124,6 +127,13 @@ def main():
     info = sv.plan.info()
     log(f"plan: {info['nchunks']} chunks, workspace {sv.ws_bytes / 2**30:.1f} GiB")
     stream = torch.cuda.Stream(device=dev)
+    if args.copy_calib_mib:
+        src = torch.ones(args.copy_calib_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calib_mib} MiB read + written")
+        del src, dst
     for w in range(args.warmup):
         sv.run(stream=stream)
         stream.synchronize()

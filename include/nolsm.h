@@ -116,6 +116,10 @@ typedef struct {
     int32_t profile;         /* != 0: launch directly (no graph), time each phase
                                 with HIP events on `stream`, synchronize, and keep
                                 the times for nolsm_profile_last                 */
+    uint64_t ns_small_tile_mask; /* FP16/BF16 GEMM tile per size bucket: bit b
+                                set -> submatrices padded to 64(b+1) rows use
+                                64x64 tiles, else 128x128 (default: bits 0, 2,
+                                i.e. 64 and 192 rows). Used by configure.       */
 } nolsm_solve_opts;
 
 /* Fills *o with the defaults above for precision `prec`. */
@@ -208,6 +212,29 @@ int nolsm_sign_batch(nolsm_plan *plan, const double *dK_val, const double *dS_va
  * arrays of sum_m*bs*bs doubles. Requires a bound plan. */
 int nolsm_assemble_D(const nolsm_plan *plan, const double *dDcols, double *dD_val,
                      void *stream);
+
+/* FP64 trace sums over all molecules of the last solve whose stats are in
+ * dstats (device): sums_out[0] = sum_J N_J = Tr(DS) share total,
+ * sums_out[1] = sum_J E_J (band energy, Eq. e_elec), sums_out[2] = number of
+ * molecules whose status is not OK. Uses the first 256 bytes of d_ws (the
+ * workspace of the plan); synchronizes `stream`. */
+int nolsm_trace_sums(const nolsm_plan *plan, const nolsm_mol_stats *dstats, void *d_ws,
+                     double *sums_out, void *stream);
+
+/* Chemical-potential bisection (Sec. IV-A: mu is fixed for charge neutrality
+ * by a bisection-like outer loop around the method). Repeats
+ * nolsm_sign_batch at mu = midpoint of [mu_lo, mu_hi] and halves the
+ * interval until |sum_J N_J - n_target| <= tol_count or max_steps solves.
+ * sum_J N_J must be increasing in mu (it counts occupied orbitals). On
+ * return dDcols / dD_val / dstats hold the last solve; *mu_out, *count_out,
+ * *steps_out (may be NULL) report it. Errors as nolsm_sign_batch, plus
+ * E_ARG (mu_hi <= mu_lo, tol_count <= 0, max_steps < 1) and E_NOCONV when
+ * the count is not reached (the last solve is still returned). */
+int nolsm_mu_bisect(nolsm_plan *plan, const double *dK_val, const double *dS_val, double mu_lo,
+                    double mu_hi, double n_target, double tol_count, int32_t max_steps,
+                    const nolsm_solve_opts *opts, void *d_ws, size_t ws_bytes, double *dDcols,
+                    double *dD_val, nolsm_mol_stats *dstats, void *stream, double *mu_out,
+                    double *count_out, int32_t *steps_out);
 
 void nolsm_plan_destroy(nolsm_plan *plan);
 const char *nolsm_strerror(int code);

@@ -37,7 +37,8 @@ class SolveOpts(C.Structure):
                 ("bounds", C.c_int32), ("d_mlp", C.c_void_p), ("d_mlp_norm", C.c_void_p),
                 ("mlp_safety", C.c_float), ("sched", C.c_int32), ("sync_errors", C.c_int32),
                 ("d_features", C.c_void_p), ("debug_scale_mult", C.c_double),
-                ("debug_poison_mol", C.c_int32), ("profile", C.c_int32)]
+                ("debug_poison_mol", C.c_int32), ("profile", C.c_int32),
+                ("ns_small_tile_mask", C.c_uint64)]
 
 
 class MolStats(C.Structure):
@@ -67,7 +68,7 @@ class Profile(C.Structure):
 EXPORTED = ["nolsm_default_opts", "nolsm_build_submatrices", "nolsm_plan_info", "nolsm_plan_export",
             "nolsm_plan_configure", "nolsm_plan_bind", "nolsm_sign_batch", "nolsm_assemble_D",
             "nolsm_plan_destroy", "nolsm_strerror", "nolsm_mlp_forward", "nolsm_mlp_loss_grad",
-            "nolsm_mlp_adam", "nolsm_profile_last"]
+            "nolsm_mlp_adam", "nolsm_profile_last", "nolsm_trace_sums", "nolsm_mu_bisect"]
 
 _lib = None
 
@@ -96,6 +97,9 @@ def lib():
     L.nolsm_strerror.argtypes = [C.c_int]
     L.nolsm_strerror.restype = C.c_char_p
     L.nolsm_profile_last.argtypes = [vp, C.POINTER(Profile)]
+    L.nolsm_trace_sums.argtypes = [vp, vp, vp, C.POINTER(C.c_double), vp]
+    L.nolsm_mu_bisect.argtypes = [vp, vp, vp, dbl, dbl, dbl, dbl, i32, C.POINTER(SolveOpts), vp, sz, vp, vp,
+                                  vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32)]
     L.nolsm_mlp_forward.argtypes = [vp, vp, vp, i32, vp, vp]
     L.nolsm_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
     L.nolsm_mlp_adam.argtypes = [vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]

@@ -9,6 +9,7 @@
 // later calls with the same buffers and options.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -54,12 +55,15 @@ static ChunkDev chunk_dev(const nolsm_plan *pl, const HostChunk &ch, char *ws) {
     cd.t_subst = (const uint32_t *)(base + ch.o_subst);
     cd.t_conv = (const uint32_t *)(base + ch.o_conv);
     cd.t_ns = (const uint32_t *)(base + ch.o_ns);
+    cd.t_ns64 = (const uint32_t *)(base + ch.o_ns64);
     cd.t_rows = (const uint32_t *)(base + ch.o_rows);
     cd.ctl = (SubCtl *)(ws + ch.off_ctl);
     cd.nsub = (int32_t)ch.meta.size();
     cd.n_subst = (int32_t)ch.t_subst.size();
     cd.n_conv = (int32_t)ch.t_conv.size();
-    cd.n_ns = (int32_t)ch.t_ns.size();
+    // lists without real entries are not launched
+    cd.n_ns = ch.n_ns_real ? (int32_t)ch.t_ns.size() : 0;
+    cd.n_ns64 = ch.n_ns64_real ? (int32_t)ch.t_ns64.size() : 0;
     cd.n_rows = (int32_t)ch.t_rows.size();
     cd.max_m = ch.max_m;
     cd.max_np = ch.max_np;
@@ -146,7 +150,7 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
         if (prof) prof->mark(PH_CHOL);
         if ((e = launch_chol(cd, b.ws, st)) != hipSuccess) return hip_fail(e, "Cholesky launch");
         if (prof) prof->mark(PH_SUBST);
-        if ((e = launch_subst(cd, b.ws, b.mu, st)) != hipSuccess) return hip_fail(e, "substitution launch");
+        if ((e = launch_subst(cd, b.ws, st)) != hipSuccess) return hip_fail(e, "substitution launch");
         if (prof) prof->mark(PH_BOUNDS);
         if ((e = launch_bounds(cd, b.ws, ba, o.prec, st)) != hipSuccess) return hip_fail(e, "bounds launch");
         if (prof) prof->mark(PH_NS);
@@ -197,6 +201,12 @@ extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const doub
     hipStream_t st = (hipStream_t)stream;
     BatchArgs b{dK_val, dS_val, mu, opts, (char *)d_ws, dDcols, dD_val, (void *)dstats};
     int rc;
+    // mu lives in the workspace header (outside any captured graph), so a
+    // captured batch serves every mu
+    {
+        hipError_t e = launch_set_header((char *)d_ws, mu, st);
+        if (e != hipSuccess) return hip_fail(e, "header launch");
+    }
     if (opts->profile) {
         PhaseEvents pe;
         pe.st = st;
@@ -220,7 +230,7 @@ extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const doub
         pl->prof = p;
     } else if (opts->sched == NOLSM_SCHED_GRAPH && st != nullptr) {
         const void *key[6] = {dK_val, dS_val, d_ws, dDcols, dD_val, dstats};
-        bool hit = pl->graph_exec && pl->g_mu == mu && pl->g_stream == stream && same_opts(pl->g_opts, *opts);
+        bool hit = pl->graph_exec && pl->g_stream == stream && same_opts(pl->g_opts, *opts);
         for (int i = 0; i < 6 && hit; ++i) hit = pl->g_key[i] == key[i];
         if (!hit) {
             drop_graph(pl);
@@ -263,6 +273,59 @@ extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const doub
         for (const auto &s : hs) {
             if (s.status == NOLSM_MOL_NOCONV) { nolsm_set_last_error("molecule did not converge"); return NOLSM_E_NOCONV; }
         }
+    }
+    return NOLSM_OK;
+}
+
+extern "C" int nolsm_trace_sums(const nolsm_plan *pl, const nolsm_mol_stats *dstats, void *d_ws,
+                                double *sums_out, void *stream) {
+    if (!pl || !dstats || !d_ws || !sums_out) return NOLSM_E_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_trace_sums(dstats, pl->nb, (char *)d_ws, st);
+    if (e != hipSuccess) return hip_fail(e, "trace-sum launch");
+    WsHeader h;
+    e = hipMemcpyAsync(&h, d_ws, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "trace-sum read-back");
+    sums_out[0] = h.sumN;
+    sums_out[1] = h.sumE;
+    sums_out[2] = (double)h.n_bad;
+    return NOLSM_OK;
+}
+
+// Chemical-potential bisection: the paper fixes mu for charge neutrality by
+// a bisection-like outer loop (Sec. IV-A, simulation details). Each step is a
+// full batched solve (the same captured graph, mu from the workspace header)
+// followed by the FP64 trace sum sum_J N_J; the interval halves towards
+// sum_J N_J = n_target.
+extern "C" int nolsm_mu_bisect(nolsm_plan *pl, const double *dK_val, const double *dS_val, double mu_lo,
+                               double mu_hi, double n_target, double tol_count, int32_t max_steps,
+                               const nolsm_solve_opts *opts, void *d_ws, size_t ws_bytes, double *dDcols,
+                               double *dD_val, nolsm_mol_stats *dstats, void *stream, double *mu_out,
+                               double *count_out, int32_t *steps_out) {
+    if (!pl || !mu_out || !count_out || !(mu_hi > mu_lo) || max_steps < 1 || !(tol_count > 0)) {
+        nolsm_set_last_error("mu_bisect: bad argument");
+        return NOLSM_E_ARG;
+    }
+    double lo = mu_lo, hi = mu_hi, mu = 0.5 * (lo + hi), cnt = 0.0;
+    int32_t step = 0;
+    for (step = 1; step <= max_steps; ++step) {
+        mu = 0.5 * (lo + hi);
+        int rc = nolsm_sign_batch(pl, dK_val, dS_val, mu, opts, d_ws, ws_bytes, dDcols, dD_val, dstats, stream);
+        if (rc != NOLSM_OK) return rc;
+        double sums[3];
+        rc = nolsm_trace_sums(pl, dstats, d_ws, sums, stream);
+        if (rc != NOLSM_OK) return rc;
+        cnt = sums[0];
+        if (std::fabs(cnt - n_target) <= tol_count) break;
+        if (cnt < n_target) lo = mu; else hi = mu;
+    }
+    *mu_out = mu;
+    *count_out = cnt;
+    if (steps_out) *steps_out = step > max_steps ? max_steps : step;
+    if (std::fabs(cnt - n_target) > tol_count) {
+        nolsm_set_last_error("mu_bisect: electron count not reached within max_steps");
+        return NOLSM_E_NOCONV;
     }
     return NOLSM_OK;
 }

@@ -240,6 +240,48 @@ hipError_t launch_extract(const ChunkDev &cd, char *ws, const ExtractArgs &ea, h
     return hipGetLastError();
 }
 
+__global__ void k_set_header(char *ws, double mu) {
+    if (threadIdx.x == 0) {
+        WsHeader *h = (WsHeader *)ws;
+        h->mu = mu;
+        h->sumN = 0.0;
+        h->sumE = 0.0;
+        h->n_bad = 0;
+    }
+}
+
+hipError_t launch_set_header(char *ws, double mu, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_header, dim3(1), dim3(64), 0, st, ws, mu);
+    return hipGetLastError();
+}
+
+// sum_J N_J and sum_J E_J in FP64, one workgroup, fixed summation order
+// (each thread a strided range, then a tree): the trace sums of the
+// chemical-potential bisection.
+__global__ __launch_bounds__(256) void k_trace_sums(const MolStatsDev *st, int nb, char *ws) {
+    __shared__ double red[256];
+    double n = 0.0, e = 0.0, bad = 0.0;
+    for (int J = threadIdx.x; J < nb; J += 256) {
+        n += st[J].trace_SD;
+        e += st[J].energy_KD;
+        bad += st[J].status != NOLSM_MOL_OK ? 1.0 : 0.0;
+    }
+    n = block_sum(n, red);
+    e = block_sum(e, red);
+    bad = block_sum(bad, red);
+    if (threadIdx.x == 0) {
+        WsHeader *h = (WsHeader *)ws;
+        h->sumN = n;
+        h->sumE = e;
+        h->n_bad = (int32_t)bad;
+    }
+}
+
+hipError_t launch_trace_sums(const void *stats, int32_t nb, char *ws, hipStream_t st) {
+    hipLaunchKernelGGL(k_trace_sums, dim3(1), dim3(256), 0, st, (const MolStatsDev *)stats, nb, ws);
+    return hipGetLastError();
+}
+
 __global__ void k_assemble(const double *Dcols, double *Dval, const int32_t *scatter_pos, int64_t sum_m, int bs) {
     const int64_t total = sum_m * bs * bs;
     for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < total; f += (int64_t)gridDim.x * blockDim.x) {

@@ -221,23 +221,32 @@ template <> struct Lp<__bf16> {
     }
 };
 
-#define LBM 128
 #define LBK 64
 #define LPITCH 72   // halves per LDS row (64 + 8 pad)
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_ns_lp(ChunkDev cd, char *ws, NsArgs na, int it, int mode) {
+// BM x BM output tile per workgroup (BM = 128: each wave 64x64 as 2x2
+// 32x32 MFMA blocks; BM = 64: each wave one 32x32 block), K in steps of 64.
+// A (X, row-major) is staged in LDS as [m][k]; B is read row-major from HBM
+// and transposed on its way into LDS ([n][k]) so that both MFMA operands
+// are 16-byte LDS reads of 8 consecutive k.
+template <typename T, int BM>
+__global__ __launch_bounds__(256) void k_ns_lp(ChunkDev cd, const uint32_t *tasks, char *ws, NsArgs na, int it,
+                                               int mode) {
     typedef typename Lp<T>::vec vec;
-    __shared__ __attribute__((aligned(16))) uint16_t sA[2][LBM * LPITCH];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[2][LBM * LPITCH];
+    constexpr int WT = BM / 2;          // wave tile
+    constexpr int NB = WT / 32;         // 32x32 MFMA blocks per wave dimension
+    constexpr int AQ = BM / 32;         // 16-byte A loads per thread
+    constexpr int BT = 2 * BM;          // threads that load a 4(k) x 8(n) B block
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * LPITCH];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BM * LPITCH];
     __shared__ double red[256];
     __shared__ int act_s;
-    const uint32_t task = xcd_task(cd.t_ns);
+    const uint32_t task = xcd_task(tasks);
     if (task == NOLSM_TASK_NONE) return;
     const int s = task_slot(task), ti = task_a(task), tj = task_b(task);
     const SubMeta M = cd.meta[s];
     SubCtl *ctl = cd.ctl + s;
-    const int np = M.np, nt = (np + LBM - 1) / LBM, tile = ti * nt + tj;
+    const int np = M.np, nt = (np + BM - 1) / BM, tile = ti * nt + tj;
     uint16_t *Xc = (uint16_t *)(ws + ((it & 1) ? M.offX1 : M.offL));
     uint16_t *Xn = (uint16_t *)(ws + ((it & 1) ? M.offL : M.offX1));
     uint16_t *Bb = (uint16_t *)(ws + M.offB);
@@ -248,8 +257,7 @@ __global__ __launch_bounds__(256) void k_ns_lp(ChunkDev cd, char *ws, NsArgs na,
         const int act = act_s;
         if (act == ACT_STOP) return;
         if (act == ACT_RESTART) {
-            restart_tile(M, ctl, ws, Xn, ti * LBM, tj * LBM, LBM, LBM,
-                         [](double v) { return Lp<T>::enc((float)v); });
+            restart_tile(M, ctl, ws, Xn, ti * BM, tj * BM, BM, BM, [](double v) { return Lp<T>::enc((float)v); });
             return;
         }
     }
@@ -257,57 +265,60 @@ __global__ __launch_bounds__(256) void k_ns_lp(ChunkDev cd, char *ws, NsArgs na,
     const uint16_t *Bg = (mode == 1) ? Xc : Bb;
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int wm = w >> 1, wn = w & 1;
-    const int row0 = ti * LBM, col0 = tj * LBM;
-    // global -> register staging: A 128x64 (4 x 16 B per thread),
-    // B 64x128 as a 4(k) x 8(n) block per thread (4 x 16 B)
+    const int row0 = ti * BM, col0 = tj * BM;
     const int ac = (t & 7) * 8;
-    const int kq = t >> 4, nc = (t & 15) * 8;
-    uint4 ra[4], rb[4];
+    const bool bload = t < BT;
+    const int kq = t / (BM / 8), nc = (t % (BM / 8)) * 8;
+    uint4 ra[AQ], rb[4];
     auto gload = [&](int k0) {
         // rows/columns past np are loaded clamped (always in bounds) and
         // replaced by zeros afterwards
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < AQ; ++q) {
             const int gr = row0 + q * 32 + (t >> 3);
             const int grc = gr < np ? gr : np - 1;
             const uint4 v = *(const uint4 *)(Ag + (int64_t)grc * np + k0 + ac);
             const uint32_t msk = gr < np ? 0xFFFFFFFFu : 0u;
             ra[q] = make_uint4(v.x & msk, v.y & msk, v.z & msk, v.w & msk);
         }
-        const int gc = col0 + nc;
-        const int gcc = gc < np ? gc : np - 8;
+        if (bload) {
+            const int gc = col0 + nc;
+            const int gcc = gc < np ? gc : np - 8;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int gk = k0 + kq * 4 + r;
-            const uint4 v = *(const uint4 *)(Bg + (int64_t)gk * np + gcc);
-            const uint32_t msk = gc < np ? 0xFFFFFFFFu : 0u;
-            rb[r] = make_uint4(v.x & msk, v.y & msk, v.z & msk, v.w & msk);
+            for (int r = 0; r < 4; ++r) {
+                const int gk = k0 + kq * 4 + r;
+                const uint4 v = *(const uint4 *)(Bg + (int64_t)gk * np + gcc);
+                const uint32_t msk = gc < np ? 0xFFFFFFFFu : 0u;
+                rb[r] = make_uint4(v.x & msk, v.y & msk, v.z & msk, v.w & msk);
+            }
         }
     };
     auto sstore = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) *(uint4 *)&sA[buf][(q * 32 + (t >> 3)) * LPITCH + ac] = ra[q];
-        auto word = [](const uint4 &v, int i) -> uint32_t { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; };
+        for (int q = 0; q < AQ; ++q) *(uint4 *)&sA[buf][(q * 32 + (t >> 3)) * LPITCH + ac] = ra[q];
+        if (bload) {
+            auto word = [](const uint4 &v, int i) -> uint32_t { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; };
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int wd = j >> 1;
-            const uint32_t a0 = word(rb[0], wd), a1 = word(rb[1], wd), a2 = word(rb[2], wd), a3 = word(rb[3], wd);
-            uint32_t lo, hi;
-            if ((j & 1) == 0) {
-                lo = (a0 & 0xFFFFu) | (a1 << 16);
-                hi = (a2 & 0xFFFFu) | (a3 << 16);
-            } else {
-                lo = (a0 >> 16) | (a1 & 0xFFFF0000u);
-                hi = (a2 >> 16) | (a3 & 0xFFFF0000u);
+            for (int j = 0; j < 8; ++j) {
+                const int wd = j >> 1;
+                const uint32_t a0 = word(rb[0], wd), a1 = word(rb[1], wd), a2 = word(rb[2], wd), a3 = word(rb[3], wd);
+                uint32_t lo, hi;
+                if ((j & 1) == 0) {
+                    lo = (a0 & 0xFFFFu) | (a1 << 16);
+                    hi = (a2 & 0xFFFFu) | (a3 << 16);
+                } else {
+                    lo = (a0 >> 16) | (a1 & 0xFFFF0000u);
+                    hi = (a2 >> 16) | (a3 & 0xFFFF0000u);
+                }
+                *(uint2 *)&sB[buf][(nc + j) * LPITCH + kq * 4] = make_uint2(lo, hi);
             }
-            *(uint2 *)&sB[buf][(nc + j) * LPITCH + kq * 4] = make_uint2(lo, hi);
         }
     };
-    v16f acc[2][2];
+    v16f acc[NB][NB];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NB; ++j)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
     const int nk = np / LBK;
@@ -319,30 +330,30 @@ __global__ __launch_bounds__(256) void k_ns_lp(ChunkDev cd, char *ws, NsArgs na,
         if (kt + 1 < nk) gload((kt + 1) * LBK);
 #pragma unroll
         for (int kk = 0; kk < LBK; kk += 16) {
-            vec a[2], b[2];
+            vec a[NB], b[NB];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                a[i] = *(const vec *)&sA[buf][(wm * 64 + i * 32 + (l & 31)) * LPITCH + kk + (l >> 5) * 8];
+            for (int i = 0; i < NB; ++i)
+                a[i] = *(const vec *)&sA[buf][(wm * WT + i * 32 + (l & 31)) * LPITCH + kk + (l >> 5) * 8];
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                b[j] = *(const vec *)&sB[buf][(wn * 64 + j * 32 + (l & 31)) * LPITCH + kk + (l >> 5) * 8];
+            for (int j = 0; j < NB; ++j)
+                b[j] = *(const vec *)&sB[buf][(wn * WT + j * 32 + (l & 31)) * LPITCH + kk + (l >> 5) * 8];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < NB; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = Lp<T>::mma(a[i], b[j], acc[i][j]);
+                for (int j = 0; j < NB; ++j) acc[i][j] = Lp<T>::mma(a[i], b[j], acc[i][j]);
         }
         if (kt + 1 < nk) sstore(buf ^ 1);
         __syncthreads();
     }
     double part = 0.0;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NB; ++j)
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                const int gr = row0 + wm * 64 + i * 32 + (e >> 2) * 8 + (l >> 5) * 4 + (e & 3);
-                const int gc = col0 + wn * 64 + j * 32 + (l & 31);
+                const int gr = row0 + wm * WT + i * 32 + (e >> 2) * 8 + (l >> 5) * 4 + (e & 3);
+                const int gc = col0 + wn * WT + j * 32 + (l & 31);
                 if (gr < np && gc < np) {
                     const float v = acc[i][j][e];
                     if (mode == 1) {
@@ -360,13 +371,21 @@ __global__ __launch_bounds__(256) void k_ns_lp(ChunkDev cd, char *ws, NsArgs na,
     }
 }
 
+template <typename T>
+static void launch_lp(const ChunkDev &cd, char *ws, const NsArgs &na, int it, int mode, hipStream_t st) {
+    if (cd.n_ns > 0)
+        hipLaunchKernelGGL((k_ns_lp<T, 128>), dim3(cd.n_ns), dim3(256), 0, st, cd, cd.t_ns, ws, na, it, mode);
+    if (cd.n_ns64 > 0)
+        hipLaunchKernelGGL((k_ns_lp<T, 64>), dim3(cd.n_ns64), dim3(256), 0, st, cd, cd.t_ns64, ws, na, it, mode);
+}
+
 hipError_t launch_ns_iter(const ChunkDev &cd, char *ws, const NsArgs &na, int it, hipStream_t st) {
     for (int mode = 1; mode <= 2; ++mode) {
         switch (na.prec) {
             case NOLSM_FP64: hipLaunchKernelGGL(k_ns64<double>, dim3(cd.n_ns), dim3(256), 0, st, cd, ws, na, it, mode); break;
             case NOLSM_FP32: hipLaunchKernelGGL(k_ns64<float>, dim3(cd.n_ns), dim3(256), 0, st, cd, ws, na, it, mode); break;
-            case NOLSM_FP16: hipLaunchKernelGGL(k_ns_lp<_Float16>, dim3(cd.n_ns), dim3(256), 0, st, cd, ws, na, it, mode); break;
-            default: hipLaunchKernelGGL(k_ns_lp<__bf16>, dim3(cd.n_ns), dim3(256), 0, st, cd, ws, na, it, mode); break;
+            case NOLSM_FP16: launch_lp<_Float16>(cd, ws, na, it, mode, st); break;
+            default: launch_lp<__bf16>(cd, ws, na, it, mode, st); break;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -202,7 +202,8 @@ __global__ __launch_bounds__(256) void k_chol(ChunkDev cd, char *ws) {
 // the complete |A| column sums and a partial Frobenius sum (bounds inputs).
 // Task list: (slot, cc), cc = 0..P (P is the E tile).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_subst(ChunkDev cd, char *ws, double mu) {
+__global__ __launch_bounds__(256) void k_subst(ChunkDev cd, char *ws) {
+    const double mu = ((const WsHeader *)ws)->mu;
     __shared__ double sA[64][LDP];
     __shared__ double sB[64][LDP];
     __shared__ double red[256];
@@ -462,8 +463,8 @@ hipError_t launch_chol(const ChunkDev &cd, char *ws, hipStream_t st) {
     hipLaunchKernelGGL(k_chol, dim3(cd.nsub), dim3(256), 0, st, cd, ws);
     return hipGetLastError();
 }
-hipError_t launch_subst(const ChunkDev &cd, char *ws, double mu, hipStream_t st) {
-    hipLaunchKernelGGL(k_subst, dim3(cd.n_subst), dim3(256), 0, st, cd, ws, mu);
+hipError_t launch_subst(const ChunkDev &cd, char *ws, hipStream_t st) {
+    hipLaunchKernelGGL(k_subst, dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
     return hipGetLastError();
 }
 hipError_t launch_bounds(const ChunkDev &cd, char *ws, const BoundsArgs &ba, int prec, hipStream_t st) {

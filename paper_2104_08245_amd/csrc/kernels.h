@@ -48,7 +48,9 @@ struct ExtractArgs {
 
 hipError_t launch_gather(const ChunkDev &cd, char *ws, const GatherArgs &ga, hipStream_t st);
 hipError_t launch_chol(const ChunkDev &cd, char *ws, hipStream_t st);
-hipError_t launch_subst(const ChunkDev &cd, char *ws, double mu, hipStream_t st);
+hipError_t launch_subst(const ChunkDev &cd, char *ws, hipStream_t st);
+hipError_t launch_set_header(char *ws, double mu, hipStream_t st);
+hipError_t launch_trace_sums(const void *stats, int32_t nb, char *ws, hipStream_t st);
 hipError_t launch_bounds(const ChunkDev &cd, char *ws, const BoundsArgs &ba, int prec, hipStream_t st);
 hipError_t launch_convert(const ChunkDev &cd, char *ws, int prec, int use_scale_g, hipStream_t st);
 hipError_t launch_ns_iter(const ChunkDev &cd, char *ws, const NsArgs &na, int it, hipStream_t st);

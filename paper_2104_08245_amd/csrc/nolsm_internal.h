@@ -45,6 +45,17 @@ struct SubCtl {
     double rhist[NOLSM_MAX_ITER_CAP];
 };
 
+// First 256 bytes of the workspace: values that change between calls without
+// changing the captured launch sequence.
+struct WsHeader {
+    double mu;          // chemical potential of the current solve
+    double sumN;        // sum_J N_J (FP64), written by the trace reduction
+    double sumE;        // sum_J E_J
+    int32_t n_bad;      // molecules with status != OK
+    int32_t pad_;
+};
+#define NOLSM_WS_HEADER 256
+
 // Packed task: slot (16 bits) | a (8 bits) | b (8 bits); 0xFFFFFFFF = no-op.
 #define NOLSM_TASK(slot, a, b) (((uint32_t)(slot) << 16) | ((uint32_t)(a) << 8) | (uint32_t)(b))
 #define NOLSM_TASK_NONE 0xFFFFFFFFu
@@ -54,8 +65,9 @@ struct ChunkDev {
     const SubMeta *meta;
     const uint32_t *t_subst;   // (slot, column tile 0..P)
     const uint32_t *t_conv;    // (slot, 64x64 tile i, j) for X_0
-    const uint32_t *t_ns;      // (slot, NS tile i, j)
+    const uint32_t *t_ns;      // (slot, NS tile i, j): 64x64 (FP64/FP32) or 128x128 (FP16/BF16) tiles
+    const uint32_t *t_ns64;    // FP16/BF16 slots that use 64x64 tiles
     const uint32_t *t_rows;    // (slot, 64-row block) for the skinny products
     SubCtl *ctl;               // in the workspace
-    int32_t nsub, n_subst, n_conv, n_ns, n_rows, max_m, max_np;
+    int32_t nsub, n_subst, n_conv, n_ns, n_ns64, n_rows, max_m, max_np;
 };

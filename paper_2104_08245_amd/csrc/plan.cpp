@@ -21,7 +21,13 @@ void nolsm_set_last_error(const std::string &s) { g_last_error = s; }
 
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int nolsm_ns_tile_for(int32_t prec) { return (prec == NOLSM_FP16 || prec == NOLSM_BF16) ? 128 : 64; }
+// Newton-Schulz tile edge of a submatrix with np rows: FP64/FP32 use 64;
+// FP16/BF16 use 128 unless bit (np/64 - 1) of small_mask asks for 64.
+int nolsm_ns_tile_for(int32_t prec, int32_t np, uint64_t small_mask) {
+    if (prec != NOLSM_FP16 && prec != NOLSM_BF16) return 64;
+    const int b = np / 64 - 1;
+    return (b >= 0 && b < 64 && ((small_mask >> b) & 1u)) ? 64 : 128;
+}
 int nolsm_elem_for(int32_t prec) {
     switch (prec) {
         case NOLSM_FP64: return 8;
@@ -163,6 +169,7 @@ extern "C" void nolsm_default_opts(nolsm_solve_opts *o, int32_t prec) {
     o->mlp_safety = 1.05f;
     o->sched = NOLSM_SCHED_GRAPH;
     o->debug_poison_mol = -1;
+    o->ns_small_tile_mask = 0x5;   // 64 and 192 rows: 128-row tiles would waste work
 }
 
 extern "C" int nolsm_plan_info(const nolsm_plan *p, nolsm_plan_sizes *o) {
@@ -226,14 +233,18 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
         pl->prec = opts->prec;
         pl->sched = opts->sched;
         pl->max_iter = opts->max_iter;
-        pl->ns_tile = nolsm_ns_tile_for(opts->prec);
         pl->elem = nolsm_elem_for(opts->prec);
         const int32_t nb = pl->nb, bs = pl->bs;
-        const int32_t T = pl->ns_tile;
         auto np_of = [&](int32_t J) {
             const int32_t n = bs * (pl->sub_ptr[J + 1] - pl->sub_ptr[J]);
             return (n + NOLSM_TILE - 1) / NOLSM_TILE * NOLSM_TILE;
         };
+        const uint64_t mask = opts->ns_small_tile_mask;
+        auto tile_of = [&](int32_t J) { return nolsm_ns_tile_for(opts->prec, np_of(J), mask); };
+        if ((size_t)pl->m_max * bs > 4032) {
+            nolsm_set_last_error("submatrices above 4032 rows are not supported");
+            return NOLSM_E_ARG;
+        }
         // order: decreasing np (largest-first keeps the tail short), then J
         std::vector<int32_t> order(nb);
         for (int32_t J = 0; J < nb; ++J) order[J] = J;
@@ -242,7 +253,7 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
         pl->ws_min = 0;
         pl->ws_full = 0;
         for (int32_t J = 0; J < nb; ++J) {
-            const size_t sb = nolsm_slot_bytes(np_of(J), T, pl->elem, pl->max_iter) + ctl_bytes;
+            const size_t sb = nolsm_slot_bytes(np_of(J), tile_of(J), pl->elem, pl->max_iter) + ctl_bytes;
             pl->ws_min = std::max(pl->ws_min, sb);
             pl->ws_full += sb;
         }
@@ -263,15 +274,16 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
             while (i < order.size() && js.size() < 65535) {
                 const int32_t J = order[i];
                 if (pl->sched == NOLSM_SCHED_PER_BUCKET && np_of(J) != bucket) break;
-                const size_t sb = nolsm_slot_bytes(np_of(J), T, pl->elem, pl->max_iter) + ctl_bytes;
+                const size_t sb = nolsm_slot_bytes(np_of(J), tile_of(J), pl->elem, pl->max_iter) + ctl_bytes;
                 if (used + sb + 256 > ws_bytes) break;
                 used += sb;
                 js.push_back(J);
                 ++i;
             }
             // layout: SubCtl array first, then the slots
-            size_t off = align256(js.size() * sizeof(SubCtl));
-            ch.off_ctl = 0;
+            // layout: workspace header, SubCtl array, then the slots
+            size_t off = NOLSM_WS_HEADER + align256(js.size() * sizeof(SubCtl));
+            ch.off_ctl = NOLSM_WS_HEADER;
             for (size_t s = 0; s < js.size(); ++s) {
                 const int32_t J = js[s];
                 SubMeta m;
@@ -283,6 +295,7 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
                 m.p = pl->self_pos[J];
                 m.P = m.np / NOLSM_TILE;
                 m.sub_off = pl->sub_ptr[J];
+                const int32_t T = tile_of(J);
                 const int32_t nt = (m.np + T - 1) / T;
                 m.ntile_ns = nt * nt;
                 const size_t n = (size_t)m.np;
@@ -301,14 +314,20 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
                 for (int32_t c = 0; c <= m.P; ++c) ch.t_subst.push_back(NOLSM_TASK(s, c, 0));
                 for (int32_t a = 0; a < m.P; ++a)
                     for (int32_t b = 0; b < m.P; ++b) ch.t_conv.push_back(NOLSM_TASK(s, a, b));
+                // FP16/BF16 slots with 64-row tiles get their own list
+                std::vector<uint32_t> &tl =
+                    (T == 64 && (pl->prec == NOLSM_FP16 || pl->prec == NOLSM_BF16)) ? ch.t_ns64 : ch.t_ns;
                 for (int32_t a = 0; a < nt; ++a)
-                    for (int32_t b = 0; b < nt; ++b) ch.t_ns.push_back(NOLSM_TASK(s, a, b));
+                    for (int32_t b = 0; b < nt; ++b) tl.push_back(NOLSM_TASK(s, a, b));
                 for (int32_t a = 0; a < m.P; ++a) ch.t_rows.push_back(NOLSM_TASK(s, a, 0));
             }
             ch.ws_used = off;
+            ch.n_ns_real = ch.t_ns.size();
+            ch.n_ns64_real = ch.t_ns64.size();
             pad8(ch.t_subst);
             pad8(ch.t_conv);
             pad8(ch.t_ns);
+            pad8(ch.t_ns64);
             pad8(ch.t_rows);
             pl->chunks.push_back(std::move(ch));
         }
@@ -327,6 +346,7 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
             ch.o_subst = put(pl->image, ch.t_subst.data(), ch.t_subst.size());
             ch.o_conv = put(pl->image, ch.t_conv.data(), ch.t_conv.size());
             ch.o_ns = put(pl->image, ch.t_ns.data(), ch.t_ns.size());
+            ch.o_ns64 = put(pl->image, ch.t_ns64.data(), ch.t_ns64.size());
             ch.o_rows = put(pl->image, ch.t_rows.data(), ch.t_rows.size());
         }
         pl->image.resize(align256(pl->image.size()));

@@ -11,12 +11,13 @@
 
 struct HostChunk {
     std::vector<SubMeta> meta;
-    std::vector<uint32_t> t_subst, t_conv, t_ns, t_rows;
+    std::vector<uint32_t> t_subst, t_conv, t_ns, t_ns64, t_rows;
     int32_t max_m = 0, max_np = 0;
+    size_t n_ns_real = 0, n_ns64_real = 0;   // task counts before padding
     size_t ws_used = 0;       // bytes of the workspace this chunk uses
     size_t off_ctl = 0;       // workspace offset of the SubCtl array
     // metadata image offsets (bytes from d_meta)
-    size_t o_meta = 0, o_subst = 0, o_conv = 0, o_ns = 0, o_rows = 0;
+    size_t o_meta = 0, o_subst = 0, o_conv = 0, o_ns = 0, o_ns64 = 0, o_rows = 0;
 };
 
 struct nolsm_plan {
@@ -48,6 +49,6 @@ struct nolsm_plan {
 
 // Internal helpers implemented in plan.cpp
 size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_iter);
-int nolsm_ns_tile_for(int32_t prec);
+int nolsm_ns_tile_for(int32_t prec, int32_t np, uint64_t small_mask);
 int nolsm_elem_for(int32_t prec);
 void nolsm_set_last_error(const std::string &s);

@@ -133,6 +133,26 @@ class Solver:
             C.c_void_p(self.Dcols.data_ptr()), C.c_void_p(self.D.data_ptr() if scatter else None),
             C.c_void_p(self.stats.data_ptr()), C.c_void_p(st)))
 
+    def trace_sums(self, stream=None):
+        """(sum_J N_J, sum_J E_J, #molecules not OK) of the last solve, FP64 on the GPU."""
+        out = (C.c_double * 3)()
+        st = _stream_ptr(stream, self.device)
+        L.check(L.lib().nolsm_trace_sums(self.plan.h, C.c_void_p(self.stats.data_ptr()),
+                                         C.c_void_p(self.ws.data_ptr()), out, C.c_void_p(st)))
+        return out[0], out[1], int(out[2])
+
+    def mu_bisect(self, mu_lo, mu_hi, n_target, tol_count=0.5, max_steps=40, stream=None):
+        """Chemical potential with sum_J N_J = n_target (bisection on the GPU solves)."""
+        st = _stream_ptr(stream, self.device)
+        mu, cnt, steps = C.c_double(), C.c_double(), C.c_int32()
+        L.check(L.lib().nolsm_mu_bisect(
+            self.plan.h, C.c_void_p(self.Kv.data_ptr()), C.c_void_p(self.Sv.data_ptr()), float(mu_lo),
+            float(mu_hi), float(n_target), float(tol_count), int(max_steps), C.byref(self.opts),
+            C.c_void_p(self.ws.data_ptr()), self.ws_bytes, C.c_void_p(self.Dcols.data_ptr()),
+            C.c_void_p(self.D.data_ptr()), C.c_void_p(self.stats.data_ptr()), C.c_void_p(st),
+            C.byref(mu), C.byref(cnt), C.byref(steps)))
+        return mu.value, cnt.value, steps.value
+
     def assemble(self, stream=None):
         st = _stream_ptr(stream, self.device)
         L.check(L.lib().nolsm_assemble_D(self.plan.h, C.c_void_p(self.Dcols.data_ptr()),

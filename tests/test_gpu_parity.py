@@ -183,6 +183,25 @@ def test_mu_outside_spectrum(torch, config1):
     assert np.abs(sv.Dcols.cpu().numpy()).max() < 1e-12
 
 
+def test_trace_sums_match_oracle(torch, config1, ref1):
+    sv = solve(config1, "fp64")
+    n, e, bad = sv.trace_sums()
+    assert bad == 0
+    assert abs(n - ref1.N.sum()) <= 1e-9 and abs(e - ref1.E.sum()) <= 1e-9
+
+
+@pytest.mark.parametrize("target", [256.0, 320.0])
+def test_mu_bisection_reaches_count(torch, config1, target):
+    from paper_2104_08245_amd import Solver
+    sv = Solver(config1, prec="fp64", device="cuda:0")
+    say(f"[gpu] mu bisection target {target}")
+    mu, cnt, steps = sv.mu_bisect(-2.0, 2.0, target, tol_count=0.5, max_steps=50)
+    assert abs(cnt - target) <= 0.5 and steps <= 50
+    # the oracle at that mu gives the same count
+    ref = o.nolsm(config1, mu=mu)
+    assert abs(ref.N.sum() - cnt) <= 1e-8
+
+
 def test_features_match_oracle(torch, config1):
     from oracle import mlp
     from paper_2104_08245_amd import Solver
