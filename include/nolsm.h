@@ -88,8 +88,11 @@ typedef enum {
     NOLSM_SCHED_GRAPH = 0,         /* whole batch captured once into a hipGraph
                                       and launched as one graph                */
     NOLSM_SCHED_STREAM = 1,        /* same kernels launched directly           */
-    NOLSM_SCHED_PER_BUCKET = 2     /* baseline: one launch per size bucket per
+    NOLSM_SCHED_PER_BUCKET = 2,    /* baseline: one launch per size bucket per
                                       phase (buckets of 64 rows)               */
+    NOLSM_SCHED_PERSISTENT = 3     /* as GRAPH, but each Newton-Schulz launch is a
+                                      fixed grid (2 workgroups per CU) draining
+                                      per-XCD device work queues of tiles      */
 } nolsm_sched;
 
 typedef struct {

@@ -45,6 +45,10 @@ extern "C" int nolsm_plan_bind(nolsm_plan *pl, void *d_meta, size_t bytes, void 
     pl->d_meta = d_meta;
     pl->bound = true;
     (void)hipGetDevice(&pl->device);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess || cus < 1)
+        cus = 256;
+    pl->pgrid = 2 * cus;   // two 256-thread workgroups per CU (LDS-limited)
     return NOLSM_OK;
 }
 
@@ -58,6 +62,8 @@ static ChunkDev chunk_dev(const nolsm_plan *pl, const HostChunk &ch, char *ws) {
     cd.t_ns64 = (const uint32_t *)(base + ch.o_ns64);
     cd.t_rows = (const uint32_t *)(base + ch.o_rows);
     cd.ctl = (SubCtl *)(ws + ch.off_ctl);
+    cd.queues = (int32_t *)(ws + ch.off_q);
+    cd.nqueue = pl->max_iter * 2 * 2 * 8;
     cd.nsub = (int32_t)ch.meta.size();
     cd.n_subst = (int32_t)ch.t_subst.size();
     cd.n_conv = (int32_t)ch.t_conv.size();
@@ -127,6 +133,8 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
     na.tol = o.tol;
     na.theta = o.switch_theta > 0 ? o.switch_theta : 0.7;
     na.rmax = o.switch_rmax > 0 ? o.switch_rmax : 0.5;
+    na.persistent = o.sched == NOLSM_SCHED_PERSISTENT;
+    na.pgrid = pl->pgrid;
     FinishArgs fa;
     fa.prec = o.prec;
     fa.nfinal = (o.prec == NOLSM_FP16 || o.prec == NOLSM_BF16) ? o.n_final_fp32 : 0;
@@ -228,7 +236,7 @@ extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const doub
         p.n_ns_launches = pe.n_ns;
         p.n_fin_launches = pe.n_fin;
         pl->prof = p;
-    } else if (opts->sched == NOLSM_SCHED_GRAPH && st != nullptr) {
+    } else if ((opts->sched == NOLSM_SCHED_GRAPH || opts->sched == NOLSM_SCHED_PERSISTENT) && st != nullptr) {
         const void *key[6] = {dK_val, dS_val, d_ws, dDcols, dD_val, dstats};
         bool hit = pl->graph_exec && pl->g_stream == stream && same_opts(pl->g_opts, *opts);
         for (int i = 0; i < 6 && hit; ++i) hit = pl->g_key[i] == key[i];

@@ -119,14 +119,16 @@ __device__ __forceinline__ void g2s_t(T (*s)[LDP], const T *g, int64_t ld) {
     }
 }
 
+// One 64x64 output tile of one half-iteration (body shared by the
+// one-workgroup-per-tile launch and the persistent queue launch).
 template <typename T>
-__global__ __launch_bounds__(256) void k_ns64(ChunkDev cd, char *ws, NsArgs na, int it, int mode) {
+__device__ __forceinline__ void ns64_tile(const ChunkDev &cd, uint32_t task, char *ws, const NsArgs &na, int it,
+                                          int mode) {
     typedef typename Mma16<T>::acc_t acc_t;
     __shared__ T sA[64][LDP];
     __shared__ T sB[64][LDP];
     __shared__ double red[256];
     __shared__ int act_s;
-    const uint32_t task = xcd_task(cd.t_ns);
     if (task == NOLSM_TASK_NONE) return;
     const int s = task_slot(task), ti = task_a(task), tj = task_b(task);
     const SubMeta M = cd.meta[s];
@@ -198,6 +200,34 @@ __global__ __launch_bounds__(256) void k_ns64(ChunkDev cd, char *ws, NsArgs na, 
     }
 }
 
+// Persistent launches: a fixed grid whose workgroups pop entries from the
+// task-list segment of their XCD through an atomic counter (one counter per
+// XCD, per launch, zeroed at chunk start). No workgroup ever waits for
+// another one, so every wave exits once its segment is drained.
+__device__ __forceinline__ int queue_pop(int *q, int *slot) {
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = atomicAdd(q, 1);
+    __syncthreads();
+    return *slot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ns64(ChunkDev cd, char *ws, NsArgs na, int it, int mode) {
+    ns64_tile<T>(cd, xcd_task(cd.t_ns), ws, na, it, mode);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ns64_pq(ChunkDev cd, int ntask, int *q, char *ws, NsArgs na, int it,
+                                                 int mode) {
+    __shared__ int idx_s;
+    const int x = blockIdx.x & 7, seg = ntask >> 3;
+    for (;;) {
+        const int i = queue_pop(q + x, &idx_s);
+        if (i >= seg) break;
+        ns64_tile<T>(cd, cd.t_ns[x * seg + i], ws, na, it, mode);
+    }
+}
+
 // ------------------------------------------------------------ FP16 / BF16
 template <typename T> struct Lp;
 template <> struct Lp<_Float16> {
@@ -230,8 +260,8 @@ template <> struct Lp<__bf16> {
 // and transposed on its way into LDS ([n][k]) so that both MFMA operands
 // are 16-byte LDS reads of 8 consecutive k.
 template <typename T, int BM>
-__global__ __launch_bounds__(256) void k_ns_lp(ChunkDev cd, const uint32_t *tasks, char *ws, NsArgs na, int it,
-                                               int mode) {
+__device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, char *ws, const NsArgs &na, int it,
+                                           int mode) {
     typedef typename Lp<T>::vec vec;
     constexpr int WT = BM / 2;          // wave tile
     constexpr int NB = WT / 32;         // 32x32 MFMA blocks per wave dimension
@@ -241,7 +271,6 @@ __global__ __launch_bounds__(256) void k_ns_lp(ChunkDev cd, const uint32_t *task
     __shared__ __attribute__((aligned(16))) uint16_t sB[2][BM * LPITCH];
     __shared__ double red[256];
     __shared__ int act_s;
-    const uint32_t task = xcd_task(tasks);
     if (task == NOLSM_TASK_NONE) return;
     const int s = task_slot(task), ti = task_a(task), tj = task_b(task);
     const SubMeta M = cd.meta[s];
@@ -371,19 +400,66 @@ __global__ __launch_bounds__(256) void k_ns_lp(ChunkDev cd, const uint32_t *task
     }
 }
 
+template <typename T, int BM>
+__global__ __launch_bounds__(256) void k_ns_lp(ChunkDev cd, const uint32_t *tasks, char *ws, NsArgs na, int it,
+                                               int mode) {
+    ns_lp_tile<T, BM>(cd, xcd_task(tasks), ws, na, it, mode);
+}
+
+template <typename T, int BM>
+__global__ __launch_bounds__(256) void k_ns_lp_pq(ChunkDev cd, const uint32_t *tasks, int ntask, int *q, char *ws,
+                                                  NsArgs na, int it, int mode) {
+    __shared__ int idx_s;
+    const int x = blockIdx.x & 7, seg = ntask >> 3;
+    for (;;) {
+        const int i = queue_pop(q + x, &idx_s);
+        if (i >= seg) break;
+        ns_lp_tile<T, BM>(cd, tasks[x * seg + i], ws, na, it, mode);
+    }
+}
+
+// queue counters of one launch: [iteration][half][tile class][XCD]
+static int *launch_queue(const ChunkDev &cd, int it, int mode, int cls) {
+    return cd.queues + (((size_t)it * 2 + (mode - 1)) * 2 + cls) * 8;
+}
+static int persistent_grid(const NsArgs &na, int ntask) {
+    int g = na.pgrid < ntask ? na.pgrid : ntask;
+    g = (g + 7) / 8 * 8;
+    return g < 8 ? 8 : g;
+}
+
 template <typename T>
 static void launch_lp(const ChunkDev &cd, char *ws, const NsArgs &na, int it, int mode, hipStream_t st) {
+    if (na.persistent) {
+        if (cd.n_ns > 0)
+            hipLaunchKernelGGL((k_ns_lp_pq<T, 128>), dim3(persistent_grid(na, cd.n_ns)), dim3(256), 0, st, cd, cd.t_ns,
+                               cd.n_ns, launch_queue(cd, it, mode, 0), ws, na, it, mode);
+        if (cd.n_ns64 > 0)
+            hipLaunchKernelGGL((k_ns_lp_pq<T, 64>), dim3(persistent_grid(na, cd.n_ns64)), dim3(256), 0, st, cd,
+                               cd.t_ns64, cd.n_ns64, launch_queue(cd, it, mode, 1), ws, na, it, mode);
+        return;
+    }
     if (cd.n_ns > 0)
         hipLaunchKernelGGL((k_ns_lp<T, 128>), dim3(cd.n_ns), dim3(256), 0, st, cd, cd.t_ns, ws, na, it, mode);
     if (cd.n_ns64 > 0)
         hipLaunchKernelGGL((k_ns_lp<T, 64>), dim3(cd.n_ns64), dim3(256), 0, st, cd, cd.t_ns64, ws, na, it, mode);
 }
 
+template <typename T>
+static void launch_64(const ChunkDev &cd, char *ws, const NsArgs &na, int it, int mode, hipStream_t st) {
+    if (cd.n_ns <= 0) return;
+    if (na.persistent)
+        hipLaunchKernelGGL(k_ns64_pq<T>, dim3(persistent_grid(na, cd.n_ns)), dim3(256), 0, st, cd, cd.n_ns,
+                           launch_queue(cd, it, mode, 0), ws, na, it, mode);
+    else
+        hipLaunchKernelGGL(k_ns64<T>, dim3(cd.n_ns), dim3(256), 0, st, cd, ws, na, it, mode);
+}
+
 hipError_t launch_ns_iter(const ChunkDev &cd, char *ws, const NsArgs &na, int it, hipStream_t st) {
     for (int mode = 1; mode <= 2; ++mode) {
         switch (na.prec) {
-            case NOLSM_FP64: hipLaunchKernelGGL(k_ns64<double>, dim3(cd.n_ns), dim3(256), 0, st, cd, ws, na, it, mode); break;
-            case NOLSM_FP32: hipLaunchKernelGGL(k_ns64<float>, dim3(cd.n_ns), dim3(256), 0, st, cd, ws, na, it, mode); break;
+            case NOLSM_FP64: launch_64<double>(cd, ws, na, it, mode, st); break;
+            case NOLSM_FP32: launch_64<float>(cd, ws, na, it, mode, st); break;
             case NOLSM_FP16: launch_lp<_Float16>(cd, ws, na, it, mode, st); break;
             default: launch_lp<__bf16>(cd, ws, na, it, mode, st); break;
         }

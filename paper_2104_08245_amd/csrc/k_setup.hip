@@ -447,6 +447,8 @@ __global__ void k_init_ctl(ChunkDev cd) {
         c->scale = 0; c->scale_g = 0; c->resid = 0;
     }
     for (int i = threadIdx.x; i < NOLSM_MAX_ITER_CAP; i += blockDim.x) c->rhist[i] = 0.0;
+    if (s == 0)
+        for (int i = threadIdx.x; i < cd.nqueue; i += blockDim.x) cd.queues[i] = 0;
 }
 
 // ----------------------------------------------------------------- launchers

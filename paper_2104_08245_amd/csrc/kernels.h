@@ -28,6 +28,8 @@ struct NsArgs {
     int32_t allow_restart; // Gershgorin restart on divergence
     double tol;            // stop when r < tol (0: unused)
     double theta, rmax;    // stagnation switch: r_k > theta r_{k-1} and r_k < rmax
+    int32_t persistent;    // queue-driven fixed grid instead of one workgroup per tile
+    int32_t pgrid;         // workgroups of a persistent launch
 };
 
 struct FinishArgs {

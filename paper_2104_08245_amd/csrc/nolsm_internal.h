@@ -69,5 +69,7 @@ struct ChunkDev {
     const uint32_t *t_ns64;    // FP16/BF16 slots that use 64x64 tiles
     const uint32_t *t_rows;    // (slot, 64-row block) for the skinny products
     SubCtl *ctl;               // in the workspace
+    int32_t *queues;           // persistent launches: [max_iter][2][2][8] counters
+    int32_t nqueue;            // number of counters
     int32_t nsub, n_subst, n_conv, n_ns, n_ns64, n_rows, max_m, max_np;
 };

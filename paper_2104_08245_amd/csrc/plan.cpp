@@ -225,7 +225,7 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
     if (!pl || !opts) { nolsm_set_last_error("configure: null argument"); return NOLSM_E_ARG; }
     if (opts->prec < NOLSM_FP64 || opts->prec > NOLSM_BF16) { nolsm_set_last_error("bad precision"); return NOLSM_E_ARG; }
     if (opts->max_iter < 2 || opts->max_iter > NOLSM_MAX_ITER_CAP) { nolsm_set_last_error("max_iter must be 2..128"); return NOLSM_E_ARG; }
-    if (opts->sched < NOLSM_SCHED_GRAPH || opts->sched > NOLSM_SCHED_PER_BUCKET) { nolsm_set_last_error("bad schedule"); return NOLSM_E_ARG; }
+    if (opts->sched < NOLSM_SCHED_GRAPH || opts->sched > NOLSM_SCHED_PERSISTENT) { nolsm_set_last_error("bad schedule"); return NOLSM_E_ARG; }
     try {
         pl->configured = false;
         pl->bound = false;
@@ -250,6 +250,9 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
         for (int32_t J = 0; J < nb; ++J) order[J] = J;
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return np_of(a) > np_of(b); });
         const size_t ctl_bytes = align256(sizeof(SubCtl));
+        // queue counters of the persistent launches, per chunk
+        const size_t nqueue = (size_t)pl->max_iter * 2 * 2 * 8;
+        const size_t qbytes = align256(nqueue * sizeof(int32_t));
         pl->ws_min = 0;
         pl->ws_full = 0;
         for (int32_t J = 0; J < nb; ++J) {
@@ -257,8 +260,8 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
             pl->ws_min = std::max(pl->ws_min, sb);
             pl->ws_full += sb;
         }
-        pl->ws_full += 256;
-        if (ws_bytes < pl->ws_min + 256) {
+        pl->ws_full += 256 + qbytes;
+        if (ws_bytes < pl->ws_min + 256 + qbytes) {
             nolsm_set_last_error("workspace smaller than the largest submatrix needs");
             return NOLSM_E_WORKSPACE;
         }
@@ -275,15 +278,16 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
                 const int32_t J = order[i];
                 if (pl->sched == NOLSM_SCHED_PER_BUCKET && np_of(J) != bucket) break;
                 const size_t sb = nolsm_slot_bytes(np_of(J), tile_of(J), pl->elem, pl->max_iter) + ctl_bytes;
-                if (used + sb + 256 > ws_bytes) break;
+                if (used + sb + 256 + qbytes > ws_bytes) break;
                 used += sb;
                 js.push_back(J);
                 ++i;
             }
             // layout: SubCtl array first, then the slots
-            // layout: workspace header, SubCtl array, then the slots
-            size_t off = NOLSM_WS_HEADER + align256(js.size() * sizeof(SubCtl));
+            // layout: workspace header, SubCtl array, queue counters, slots
             ch.off_ctl = NOLSM_WS_HEADER;
+            ch.off_q = NOLSM_WS_HEADER + align256(js.size() * sizeof(SubCtl));
+            size_t off = ch.off_q + qbytes;
             for (size_t s = 0; s < js.size(); ++s) {
                 const int32_t J = js[s];
                 SubMeta m;

@@ -16,6 +16,7 @@ struct HostChunk {
     size_t n_ns_real = 0, n_ns64_real = 0;   // task counts before padding
     size_t ws_used = 0;       // bytes of the workspace this chunk uses
     size_t off_ctl = 0;       // workspace offset of the SubCtl array
+    size_t off_q = 0;         // workspace offset of the queue counters
     // metadata image offsets (bytes from d_meta)
     size_t o_meta = 0, o_subst = 0, o_conv = 0, o_ns = 0, o_ns64 = 0, o_rows = 0;
 };
@@ -38,6 +39,7 @@ struct nolsm_plan {
            o_self = 0, o_scatter = 0;
     void *d_meta = nullptr;
     int device = -1;
+    int32_t pgrid = 512;      // persistent-launch grid (2 x CUs), set by bind
     // graph cache
     void *graph_exec = nullptr;
     const void *g_key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};

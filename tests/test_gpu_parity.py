@@ -101,6 +101,8 @@ def test_schedules_and_replays_bit_identical(torch, config1, prec):
     ref = base.Dcols.cpu().numpy()
     pb = solve(config1, prec, sched=L.SCHED_PER_BUCKET)
     assert np.array_equal(pb.Dcols.cpu().numpy(), ref)
+    ps = solve(config1, prec, sched=L.SCHED_PERSISTENT)
+    assert np.array_equal(ps.Dcols.cpu().numpy(), ref)
     # graph capture needs a non-default stream; replay twice with work between
     from paper_2104_08245_amd import Solver
     sv = Solver(config1, prec=prec, device="cuda:0", sched=L.SCHED_GRAPH)
@@ -214,6 +216,44 @@ def test_features_match_oracle(torch, config1):
     for J in (2, 40):
         ref = mlp.features(r.xs[J][1])
         assert np.allclose(f[J], ref, rtol=1e-5, atol=1e-6), (J, f[J], ref)
+
+
+@pytest.fixture(scope="module")
+def slab():
+    # a small two-density slab: submatrices from ~400 (dilute) to ~1500 (dense) rows
+    return synth.water_slab(config_id=77, r_c=1.2, n_dense=400, n_dilute=400,
+                            box=np.array([3.0, 3.0, 5.0]), z_split=400 / 33.4 / 9.0)
+
+
+@pytest.mark.parametrize("prec,sched", [("fp64", "stream"), ("fp16", "graph"), ("fp16", "persistent"),
+                                        ("fp16", "bucket")])
+def test_uneven_sizes_slab(torch, slab, prec, sched):
+    from paper_2104_08245_amd import _lib as L
+    s = slab
+    m = np.diff(s.K.row_ptr)
+    dense = int(np.argmax(m))
+    dilute = int(np.argmin(m))
+    mols = [dense, dilute, 3, s.nmol - 5]
+    ref = {J: o.solve_molecule(s, J) for J in mols}
+    sc = {"stream": L.SCHED_STREAM, "graph": L.SCHED_GRAPH, "persistent": L.SCHED_PERSISTENT,
+          "bucket": L.SCHED_PER_BUCKET}[sched]
+    import torch as T
+    from paper_2104_08245_amd import Solver
+    say(f"[gpu] slab {prec} {sched}: n {6 * m.min()}..{6 * m.max()}")
+    sv = Solver(s, prec=prec, sched=sc, ws_budget=8 << 30)
+    stream = T.cuda.Stream()
+    sv.run(stream=stream)
+    stream.synchronize()
+    st = sv.host_stats()
+    dc = sv.host_dcols()
+    assert np.all(st["status"] == 0)
+    for J in mols:
+        err = rel(dc[J], ref[J].Dcols)
+        dE = abs(st["energy_KD"][J] - ref[J].E_J)
+        if prec == "fp64":
+            assert err <= 1e-10 and dE <= 1e-9, (J, err, dE)
+        else:
+            assert err <= MIXED[prec]["dcols"] and dE <= MIXED[prec]["energy"], (J, err, dE)
 
 
 def test_config2_sample_fp64(torch):
