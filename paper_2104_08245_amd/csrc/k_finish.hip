@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void k_skinny(ChunkDev cd, char *ws, SkinnyArg
         for (int j = 0; j < BSMAX; ++j) in[j] = (j < bs) ? vec_in<TV>(sa, M, ws, c, j) : (TV)0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const TV p = (TV)Dec<TP>::get(P[(int64_t)(rbase + r) * np + c]);
+            const TV p = (TV)Dec<TP>::get(P[(int64_t)(rbase + r) * M.ldx + c]);
 #pragma unroll
             for (int j = 0; j < BSMAX; ++j) acc[r][j] += p * in[j];
         }

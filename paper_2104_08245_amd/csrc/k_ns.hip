@@ -84,7 +84,7 @@ __device__ void restart_tile(const SubMeta &M, const SubCtl *ctl, const char *ws
         const int r = r0 + f / cols, q = c0 + f % cols;
         if (r >= M.np || q >= M.np) continue;
         const double v = (r < M.n && q < M.n) ? c * A[(int64_t)r * ldk + q] : (r == q ? 1.0 : 0.0);
-        Xn[(int64_t)r * M.np + q] = cvt(v);
+        Xn[(int64_t)r * M.ldx + q] = cvt(v);
     }
 }
 
@@ -186,12 +186,14 @@ __device__ __forceinline__ void ns64_tile(const ChunkDev &cd, uint32_t task, cha
                 const int gr = ti * 64 + r0 + i * 16 + Mma16<T>::row(lk, e);
                 const int gc = tj * 64 + c0 + j * 16 + li;
                 const T v = acc[i][j][e];
+                const int64_t o = (int64_t)gr * np + gc;
                 if (mode == 1) {
-                    const double d = (double)v - (gr == gc ? 1.0 : 0.0);
-                    part += d * d;
-                    Bb[(int64_t)gr * np + gc] = (gr == gc ? (T)3 : (T)0) - v;
+                    // R = I - X^2; the update below is X + X R / 2 = X (3I - X^2) / 2
+                    const T rr = (gr == gc ? (T)1 : (T)0) - v;
+                    part += (double)rr * (double)rr;
+                    Bb[o] = rr;
                 } else {
-                    Xn[(int64_t)gr * np + gc] = (T)0.5 * v;
+                    Xn[o] = Xc[o] + (T)0.5 * v;
                 }
             }
     if (mode == 1) {
@@ -239,6 +241,7 @@ template <> struct Lp<_Float16> {
         _Float16 h = (_Float16)x;
         return __builtin_bit_cast(uint16_t, h);
     }
+    static __device__ __forceinline__ float dec(uint16_t x) { return (float)__builtin_bit_cast(_Float16, x); }
 };
 template <> struct Lp<__bf16> {
     typedef v8bf vec;
@@ -249,6 +252,7 @@ template <> struct Lp<__bf16> {
         __bf16 h = (__bf16)x;
         return __builtin_bit_cast(uint16_t, h);
     }
+    static __device__ __forceinline__ float dec(uint16_t x) { return (float)__builtin_bit_cast(__bf16, x); }
 };
 
 #define LBK 64
@@ -298,51 +302,62 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
     const int ac = (t & 7) * 8;
     const bool bload = t < BT;
     const int kq = t / (BM / 8), nc = (t % (BM / 8)) * 8;
-    uint4 ra[AQ], rb[4];
-    auto gload = [&](int k0) {
-        // rows/columns past np are loaded clamped (always in bounds) and
-        // replaced by zeros afterwards
-#pragma unroll
-        for (int q = 0; q < AQ; ++q) {
-            const int gr = row0 + q * 32 + (t >> 3);
-            const int grc = gr < np ? gr : np - 1;
-            const uint4 v = *(const uint4 *)(Ag + (int64_t)grc * np + k0 + ac);
-            const uint32_t msk = gr < np ? 0xFFFFFFFFu : 0u;
-            ra[q] = make_uint4(v.x & msk, v.y & msk, v.z & msk, v.w & msk);
-        }
-        if (bload) {
-            const int gc = col0 + nc;
-            const int gcc = gc < np ? gc : np - 8;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gk = k0 + kq * 4 + r;
-                const uint4 v = *(const uint4 *)(Bg + (int64_t)gk * np + gcc);
-                const uint32_t msk = gc < np ? 0xFFFFFFFFu : 0u;
-                rb[r] = make_uint4(v.x & msk, v.y & msk, v.z & msk, v.w & msk);
-            }
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < AQ; ++q) *(uint4 *)&sA[buf][(q * 32 + (t >> 3)) * LPITCH + ac] = ra[q];
-        if (bload) {
-            auto word = [](const uint4 &v, int i) -> uint32_t { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; };
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int wd = j >> 1;
-                const uint32_t a0 = word(rb[0], wd), a1 = word(rb[1], wd), a2 = word(rb[2], wd), a3 = word(rb[3], wd);
-                uint32_t lo, hi;
-                if ((j & 1) == 0) {
-                    lo = (a0 & 0xFFFFu) | (a1 << 16);
-                    hi = (a2 & 0xFFFFu) | (a3 << 16);
-                } else {
-                    lo = (a0 >> 16) | (a1 & 0xFFFF0000u);
-                    hi = (a2 >> 16) | (a3 & 0xFFFF0000u);
-                }
-                *(uint2 *)&sB[buf][(nc + j) * LPITCH + kq * 4] = make_uint2(lo, hi);
-            }
-        }
-    };
+    // The buffers have ldx >= the tile extent rows and columns, so loads need
+    // no masking: rows of A / columns of B past np only feed outputs that are
+    // never stored (an output (r, c) reads only row r of A and column c of B),
+    // and the k range stops at np. Staging is straight-line code on named
+    // registers (no arrays or lambdas, which the compiler spilled to scratch).
+    const int ldx = M.ldx;
+    const uint16_t *pa = Ag + (int64_t)(row0 + (t >> 3)) * ldx + ac;
+    const uint16_t *pb = Bg + (int64_t)(kq * 4) * ldx + col0 + nc;
+    const int64_t l32 = (int64_t)32 * ldx;
+    uint4 ra0, ra1, ra2 = {0, 0, 0, 0}, ra3 = {0, 0, 0, 0};
+    uint4 rb0 = {0, 0, 0, 0}, rb1 = {0, 0, 0, 0}, rb2 = {0, 0, 0, 0}, rb3 = {0, 0, 0, 0};
+#define NS_GLOAD(k0)                                                             \
+    do {                                                                         \
+        ra0 = *(const uint4 *)(pa + (k0));                                       \
+        ra1 = *(const uint4 *)(pa + l32 + (k0));                                 \
+        if constexpr (AQ > 2) {                                                  \
+            ra2 = *(const uint4 *)(pa + 2 * l32 + (k0));                         \
+            ra3 = *(const uint4 *)(pa + 3 * l32 + (k0));                         \
+        }                                                                        \
+        if (bload) {                                                             \
+            const uint16_t *q_ = pb + (int64_t)(k0) * ldx;                       \
+            rb0 = *(const uint4 *)(q_);                                          \
+            rb1 = *(const uint4 *)(q_ + ldx);                                    \
+            rb2 = *(const uint4 *)(q_ + 2 * ldx);                                \
+            rb3 = *(const uint4 *)(q_ + 3 * ldx);                                \
+        }                                                                        \
+    } while (0)
+// B is a 4(k) x 8(n) block in rb0..rb3 (one k row each); column j of it
+// becomes 4 consecutive k for LDS row n = nc + j
+#define NS_BCOL(j, W)                                                            \
+    do {                                                                         \
+        uint32_t lo_, hi_;                                                       \
+        if (((j) & 1) == 0) {                                                    \
+            lo_ = (rb0.W & 0xFFFFu) | (rb1.W << 16);                             \
+            hi_ = (rb2.W & 0xFFFFu) | (rb3.W << 16);                             \
+        } else {                                                                 \
+            lo_ = (rb0.W >> 16) | (rb1.W & 0xFFFF0000u);                         \
+            hi_ = (rb2.W >> 16) | (rb3.W & 0xFFFF0000u);                         \
+        }                                                                        \
+        *(uint2 *)&sB[buf_][(nc + (j)) * LPITCH + kq * 4] = make_uint2(lo_, hi_); \
+    } while (0)
+#define NS_SSTORE(bufi)                                                          \
+    do {                                                                         \
+        const int buf_ = (bufi);                                                 \
+        uint16_t *sa_ = &sA[buf_][(t >> 3) * LPITCH + ac];                       \
+        *(uint4 *)(sa_) = ra0;                                                   \
+        *(uint4 *)(sa_ + 32 * LPITCH) = ra1;                                     \
+        if constexpr (AQ > 2) {                                                  \
+            *(uint4 *)(sa_ + 64 * LPITCH) = ra2;                                 \
+            *(uint4 *)(sa_ + 96 * LPITCH) = ra3;                                 \
+        }                                                                        \
+        if (bload) {                                                             \
+            NS_BCOL(0, x); NS_BCOL(1, x); NS_BCOL(2, y); NS_BCOL(3, y);          \
+            NS_BCOL(4, z); NS_BCOL(5, z); NS_BCOL(6, w); NS_BCOL(7, w);          \
+        }                                                                        \
+    } while (0)
     v16f acc[NB][NB];
 #pragma unroll
     for (int i = 0; i < NB; ++i)
@@ -351,12 +366,15 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
     const int nk = np / LBK;
-    gload(0);
-    sstore(0);
+    NS_GLOAD(0);
+    NS_SSTORE(0);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * LBK);
+        // prefetch the next k slice (the last iteration reloads its own slice,
+        // in bounds, so the loads stay unconditional)
+        const int knext = (kt + 1 < nk ? kt + 1 : kt) * LBK;
+        NS_GLOAD(knext);
 #pragma unroll
         for (int kk = 0; kk < LBK; kk += 16) {
             vec a[NB], b[NB];
@@ -371,9 +389,12 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
 #pragma unroll
                 for (int j = 0; j < NB; ++j) acc[i][j] = Lp<T>::mma(a[i], b[j], acc[i][j]);
         }
-        if (kt + 1 < nk) sstore(buf ^ 1);
+        if (kt + 1 < nk) NS_SSTORE(buf ^ 1);
         __syncthreads();
     }
+#undef NS_GLOAD
+#undef NS_BCOL
+#undef NS_SSTORE
     double part = 0.0;
 #pragma unroll
     for (int i = 0; i < NB; ++i)
@@ -385,12 +406,17 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
                 const int gc = col0 + wn * WT + j * 32 + (l & 31);
                 if (gr < np && gc < np) {
                     const float v = acc[i][j][e];
+                    const int64_t o = (int64_t)gr * ldx + gc;
                     if (mode == 1) {
-                        const double d = (double)v - (gr == gc ? 1.0 : 0.0);
-                        part += d * d;
-                        Bb[(int64_t)gr * np + gc] = Lp<T>::enc((gr == gc ? 3.0f : 0.0f) - v);
+                        // R = I - X^2 is small near convergence and keeps full
+                        // relative precision in 16 bits (3I - X^2 would not:
+                        // its diagonal ~2 is quantised at 2^-9 in FP16)
+                        const float rr = (gr == gc ? 1.0f : 0.0f) - v;
+                        part += (double)rr * (double)rr;
+                        Bb[o] = Lp<T>::enc(rr);
                     } else {
-                        Xn[(int64_t)gr * np + gc] = Lp<T>::enc(0.5f * v);
+                        // X_{k+1} = X_k + X_k R / 2 = X_k (3I - X_k^2) / 2
+                        Xn[o] = Lp<T>::enc(Lp<T>::dec(Xc[o]) + 0.5f * v);
                     }
                 }
             }

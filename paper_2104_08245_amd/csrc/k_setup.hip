@@ -396,7 +396,10 @@ __global__ __launch_bounds__(256) void k_bounds(ChunkDev cd, char *ws, BoundsArg
         }
         __syncthreads();
         const double rho_hat = fmax(fabs((double)outp[0] * glo), fabs((double)outp[1] * ghi));
-        if (rho_hat > 0 && isfinite(rho_hat)) c = fmax(1.0 / ((double)ba.safety * rho_hat), cg);
+        // c in [c_G, 1.7 c_G]: since rho(A) <= rho_G, c rho(A) <= 1.7 < sqrt(3)
+        // whatever the prediction, so no eigenvalue can be mapped past the
+        // point where the iteration would converge to the wrong sign
+        if (rho_hat > 0 && isfinite(rho_hat)) c = fmin(fmax(1.0 / ((double)ba.safety * rho_hat), cg), 1.7 * cg);
     }
     if (ba.scale_mult != 0.0) c *= ba.scale_mult;
     if (t == 0) {
@@ -433,7 +436,7 @@ __global__ __launch_bounds__(256) void k_convert(ChunkDev cd, char *ws, int use_
     for (int f = threadIdx.x; f < 4096; f += 256) {
         const int r = ti * 64 + (f >> 6), q = tj * 64 + (f & 63);
         const double v = (r < n && q < n) ? c * A[(int64_t)r * ldk + q] : (r == q ? 1.0 : 0.0);
-        X[(int64_t)r * np + q] = cvt<T>(v);
+        X[(int64_t)r * M.ldx + q] = cvt<T>(v);
     }
 }
 

@@ -20,13 +20,16 @@ struct SubMeta {
     int32_t P;        // np / NOLSM_TILE
     int32_t sub_off;  // sub_ptr[J]
     int32_t ntile_ns; // NS GEMM tiles of this slot (for residual partials)
+    int32_t ldx;      // leading dimension of the X / R buffers: np rounded up
+                      // to the NS tile, so tile loads never leave the buffer
+    int32_t pad_;
     int64_t offL;     // np*np doubles: S -> L; later X buffer 0
     int64_t offK;     // np*(np+64) doubles: K -> W -> [A | Y]
     int64_t offDinv;  // P*64*64 doubles: inverses of the diagonal tiles of L
     int64_t offRow;   // (P+1)*np doubles: partial |A| row sums per column tile
     int64_t offCol;   // np doubles col sums of |A|, then 64 more: P frob partials
-    int64_t offX1;    // np*np elements of the NS precision: X buffer 1
-    int64_t offB;     // np*np elements: B = 3I - X^2
+    int64_t offX1;    // ldx*ldx elements of the NS precision: X buffer 1
+    int64_t offB;     // ldx*ldx elements: R = I - X^2
     int64_t offVec;   // NOLSM_NVEC * np * 6 floats/doubles: finishing vectors
     int64_t offRes;   // max_iter * ntile_ns doubles: residual partials
 };

@@ -46,8 +46,9 @@ size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_i
     b += align256(P * 64 * 64 * 8);           // Dinv
     b += align256((P + 1) * n * 8);           // row partials
     b += align256((n + 64) * 8);              // col sums + frob partials
-    b += align256(n * n * (size_t)elem);      // X1
-    b += align256(n * n * (size_t)elem);      // B
+    const size_t ldx = nt * (size_t)ns_tile;   // X0 (in the L buffer) also fits: ldx <= np + 64
+    b += align256(ldx * ldx * (size_t)elem);  // X1
+    b += align256(ldx * ldx * (size_t)elem);  // R
     b += align256((size_t)NOLSM_NVEC * n * 6 * 8);  // finishing vectors
     b += align256((size_t)max_iter * nt * nt * 8);  // residual partials
     return b;
@@ -308,8 +309,10 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
                 m.offDinv = (int64_t)off; off += align256((size_t)m.P * 4096 * 8);
                 m.offRow = (int64_t)off; off += align256((size_t)(m.P + 1) * n * 8);
                 m.offCol = (int64_t)off; off += align256((n + 64) * 8);
-                m.offX1 = (int64_t)off; off += align256(n * n * pl->elem);
-                m.offB = (int64_t)off; off += align256(n * n * pl->elem);
+                m.ldx = nt * T;
+                const size_t ldx = (size_t)m.ldx;
+                m.offX1 = (int64_t)off; off += align256(ldx * ldx * pl->elem);
+                m.offB = (int64_t)off; off += align256(ldx * ldx * pl->elem);
                 m.offVec = (int64_t)off; off += align256((size_t)NOLSM_NVEC * n * 6 * 8);
                 m.offRes = (int64_t)off; off += align256((size_t)pl->max_iter * m.ntile_ns * 8);
                 ch.meta.push_back(m);

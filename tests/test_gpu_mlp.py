@@ -58,6 +58,11 @@ def test_adam_matches_oracle(torch):
     torch.cuda.synchronize()
     r, rm, rv = mlp.adam_step(th.astype(np.float32).astype(np.float64), g.astype(np.float32),
                               m.astype(np.float32), v.astype(np.float32), 5, lr=1e-3)
-    assert np.allclose(tp.cpu().numpy(), r, rtol=1e-5, atol=1e-6)
-    assert np.allclose(tm.cpu().numpy(), rm, rtol=1e-5, atol=1e-7)
+    # FP32 kernel vs FP64 oracle: the step is lr * m/(sqrt(v)+eps) ~ 1e-3, so
+    # the FP32 rounding of the quotient shows up at ~1e-3 * 1e-6 absolute,
+    # plus the FP32 spacing of the parameters themselves (|p| ~ 3 -> 2.4e-7)
+    assert np.allclose(tp.cpu().numpy(), r, rtol=2e-6, atol=1e-7)
+    # (1 - beta1) = 0.1 is inexact in FP32 (relative 2.4e-7): ~1e-7 absolute on
+    # m when |g| ~ 4, which dominates where m is near zero
+    assert np.allclose(tm.cpu().numpy(), rm, rtol=1e-5, atol=5e-7)
     assert np.allclose(tv.cpu().numpy(), rv, rtol=1e-5, atol=1e-8)
