@@ -102,7 +102,7 @@ def lib():
                                   vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32)]
     L.nolsm_mlp_forward.argtypes = [vp, vp, vp, i32, vp, vp]
     L.nolsm_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
-    L.nolsm_mlp_adam.argtypes = [vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+    L.nolsm_mlp_adam.argtypes = [vp, vp, vp, vp, i32, C.c_double, C.c_double, C.c_double, C.c_double, vp]
     for name in EXPORTED:
         f = getattr(L, name)
         if f.restype is C.c_int or name not in ("nolsm_default_opts", "nolsm_plan_destroy", "nolsm_strerror"):

@@ -167,13 +167,15 @@ __global__ __launch_bounds__(1024) void k_mlp_loss_grad(const float *__restrict_
     }
 }
 
-__global__ void k_mlp_adam(float *p, const float *g, float *m, float *v, float lr, float b1, float b2, float eps,
-                           float bc1, float bc2) {
+// omb1 = 1 - beta1 and omb2 = 1 - beta2 are formed on the host from the
+// double-precision hyper-parameters and rounded once to FP32.
+__global__ void k_mlp_adam(float *p, const float *g, float *m, float *v, float lr, float b1, float b2, float omb1,
+                           float omb2, float eps, float bc1, float bc2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NPAR) return;
     const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    const float mi = b1 * m[i] + omb1 * gi;
+    const float vi = b2 * v[i] + omb2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
@@ -196,12 +198,13 @@ extern "C" int nolsm_mlp_loss_grad(const float *d_params, const float *d_norm, c
     return hipGetLastError() == hipSuccess ? NOLSM_OK : NOLSM_E_HIP;
 }
 
-extern "C" int nolsm_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, int32_t t, float lr,
-                              float beta1, float beta2, float eps, void *stream) {
+extern "C" int nolsm_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, int32_t t, double lr,
+                              double beta1, double beta2, double eps, void *stream) {
     if (!d_params || !d_grad || !d_m || !d_v || t < 1) return NOLSM_E_ARG;
-    const float bc1 = (float)(1.0 - pow((double)beta1, (double)t));
-    const float bc2 = (float)(1.0 - pow((double)beta2, (double)t));
+    const float bc1 = (float)(1.0 - pow(beta1, (double)t));
+    const float bc2 = (float)(1.0 - pow(beta2, (double)t));
+    const float omb1 = (float)(1.0 - beta1), omb2 = (float)(1.0 - beta2);
     hipLaunchKernelGGL(k_mlp_adam, dim3((NPAR + 255) / 256), dim3(256), 0, (hipStream_t)stream, d_params, d_grad,
-                       d_m, d_v, lr, beta1, beta2, eps, bc1, bc2);
+                       d_m, d_v, (float)lr, (float)beta1, (float)beta2, omb1, omb2, (float)eps, bc1, bc2);
     return hipGetLastError() == hipSuccess ? NOLSM_OK : NOLSM_E_HIP;
 }

@@ -256,7 +256,13 @@ template <> struct Lp<__bf16> {
 };
 
 #define LBK 64
-#define LPITCH 72   // halves per LDS row (64 + 8 pad)
+
+// LDS tiles hold 64 k per row (128 bytes, no padding). The 16-byte chunk c
+// (8 consecutive k) of row n sits at chunk position c ^ ((n ^ n >> 3) & 7):
+// an MFMA operand read (32 rows, one chunk) then touches 8 distinct chunk
+// positions in every 8 consecutive rows, and the transposing B stores (one
+// row per 8 columns) spread over all positions as well.
+__device__ __forceinline__ int lds_swz(int n, int c) { return n * LBK + ((c ^ ((n ^ (n >> 3)) & 7)) << 3); }
 
 // BM x BM output tile per workgroup (BM = 128: each wave 64x64 as 2x2
 // 32x32 MFMA blocks; BM = 64: each wave one 32x32 block), K in steps of 64.
@@ -271,8 +277,8 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
     constexpr int NB = WT / 32;         // 32x32 MFMA blocks per wave dimension
     constexpr int AQ = BM / 32;         // 16-byte A loads per thread
     constexpr int BT = 2 * BM;          // threads that load a 4(k) x 8(n) B block
-    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * LPITCH];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BM * LPITCH];
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * LBK];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BM * LBK];
     __shared__ double red[256];
     __shared__ int act_s;
     if (task == NOLSM_TASK_NONE) return;
@@ -300,62 +306,100 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
     const int wm = w >> 1, wn = w & 1;
     const int row0 = ti * BM, col0 = tj * BM;
     const int ac = (t & 7) * 8;
-    const bool bload = t < BT;
-    const int kq = t / (BM / 8), nc = (t % (BM / 8)) * 8;
+    const bool bload = (BT >= 256) || t < BT;   // BM = 128: every thread
+    // B block of thread t: k rows 4 kq .. 4 kq + 3, columns 8 nci .. 8 nci + 7.
+    // Each group of 16 lanes covers 8 column blocks and two k quads, so its
+    // 8-byte LDS stores land on 16 distinct 8-byte bank slots.
+    const int nci = (BM == 128) ? ((t & 7) | (((t >> 4) & 1) << 3)) : (t & 7);
+    const int kq = (BM == 128) ? (((t >> 3) & 1) | ((t >> 5) << 1)) : (t >> 3);
+    const int nc = nci * 8;
     // The buffers have ldx >= the tile extent rows and columns, so loads need
     // no masking: rows of A / columns of B past np only feed outputs that are
     // never stored (an output (r, c) reads only row r of A and column c of B),
     // and the k range stops at np. Staging is straight-line code on named
     // registers (no arrays or lambdas, which the compiler spilled to scratch).
     const int ldx = M.ldx;
-    const uint16_t *pa = Ag + (int64_t)(row0 + (t >> 3)) * ldx + ac;
-    const uint16_t *pb = Bg + (int64_t)(kq * 4) * ldx + col0 + nc;
-    const int64_t l32 = (int64_t)32 * ldx;
-    uint4 ra0, ra1, ra2 = {0, 0, 0, 0}, ra3 = {0, 0, 0, 0};
-    uint4 rb0 = {0, 0, 0, 0}, rb1 = {0, 0, 0, 0}, rb2 = {0, 0, 0, 0}, rb3 = {0, 0, 0, 0};
-#define NS_GLOAD(k0)                                                             \
+    // Slices are fetched with raw buffer loads over the ldx x ldx buffers:
+    // a 32-bit lane offset plus a uniform row-block offset. A slice past the
+    // end (and B for threads that stage none) gets a lane offset beyond the
+    // buffer size, which the hardware answers with zeros and no memory
+    // access, so every load is unconditional and the compiler's wait counts
+    // stay exact across the prefetch ring.
+    const int nrec = ldx * ldx * 2;
+    const __amdgpu_buffer_rsrc_t rsA = __builtin_amdgcn_make_buffer_rsrc((void *)Ag, (short)0, nrec, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsB = __builtin_amdgcn_make_buffer_rsrc((void *)Bg, (short)0, nrec, 0x00020000);
+    const uint32_t va = (uint32_t)(((row0 + (t >> 3)) * ldx + ac) * 2);
+    const uint32_t vb = (uint32_t)((kq * 4 * ldx + col0 + nc) * 2);
+    const int sa32 = 64 * ldx, srow = 2 * ldx;   // bytes of 32 rows / one row
+    const int nk = np / LBK;
+    // two register sets (p and q) of one k slice each: the load of slice
+    // kt + 3 is issued at the end of step kt and stored to LDS at the end of
+    // step kt + 2, so global latency is covered by two compute phases
+    const uint4 z4 = {0, 0, 0, 0};
+    uint4 pa0 = z4, pa1 = z4, pa2 = z4, pa3 = z4, pb0 = z4, pb1 = z4, pb2 = z4, pb3 = z4;
+    uint4 qa0 = z4, qa1 = z4, qa2 = z4, qa3 = z4, qb0 = z4, qb1 = z4, qb2 = z4, qb3 = z4;
+#define NS_BUF(rs, vo, so) __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, so, 0))
+#define NS_GLOAD(S, ks)                                                          \
     do {                                                                         \
-        ra0 = *(const uint4 *)(pa + (k0));                                       \
-        ra1 = *(const uint4 *)(pa + l32 + (k0));                                 \
+        const bool in_ = (ks) < nk;                                              \
+        const uint32_t oa_ = in_ ? va + (uint32_t)((ks) * LBK * 2) : 0x80000000u; \
+        const uint32_t ob_ = (in_ && bload) ? vb + (uint32_t)((ks) * LBK * srow) \
+                                            : 0x80000000u;                       \
+        S##a0 = NS_BUF(rsA, oa_, 0);                                             \
+        S##a1 = NS_BUF(rsA, oa_, sa32);                                          \
         if constexpr (AQ > 2) {                                                  \
-            ra2 = *(const uint4 *)(pa + 2 * l32 + (k0));                         \
-            ra3 = *(const uint4 *)(pa + 3 * l32 + (k0));                         \
+            S##a2 = NS_BUF(rsA, oa_, 2 * sa32);                                  \
+            S##a3 = NS_BUF(rsA, oa_, 3 * sa32);                                  \
         }                                                                        \
-        if (bload) {                                                             \
-            const uint16_t *q_ = pb + (int64_t)(k0) * ldx;                       \
-            rb0 = *(const uint4 *)(q_);                                          \
-            rb1 = *(const uint4 *)(q_ + ldx);                                    \
-            rb2 = *(const uint4 *)(q_ + 2 * ldx);                                \
-            rb3 = *(const uint4 *)(q_ + 3 * ldx);                                \
-        }                                                                        \
+        S##b0 = NS_BUF(rsB, ob_, 0);                                             \
+        S##b1 = NS_BUF(rsB, ob_, srow);                                          \
+        S##b2 = NS_BUF(rsB, ob_, 2 * srow);                                      \
+        S##b3 = NS_BUF(rsB, ob_, 3 * srow);                                      \
     } while (0)
-// B is a 4(k) x 8(n) block in rb0..rb3 (one k row each); column j of it
+// B is a 4(k) x 8(n) block in S##b0..S##b3 (one k row each); column j of it
 // becomes 4 consecutive k for LDS row n = nc + j
-#define NS_BCOL(j, W)                                                            \
+#define NS_BCOL(S, j, W)                                                         \
     do {                                                                         \
         uint32_t lo_, hi_;                                                       \
         if (((j) & 1) == 0) {                                                    \
-            lo_ = (rb0.W & 0xFFFFu) | (rb1.W << 16);                             \
-            hi_ = (rb2.W & 0xFFFFu) | (rb3.W << 16);                             \
+            lo_ = (S##b0.W & 0xFFFFu) | (S##b1.W << 16);                         \
+            hi_ = (S##b2.W & 0xFFFFu) | (S##b3.W << 16);                         \
         } else {                                                                 \
-            lo_ = (rb0.W >> 16) | (rb1.W & 0xFFFF0000u);                         \
-            hi_ = (rb2.W >> 16) | (rb3.W & 0xFFFF0000u);                         \
+            lo_ = (S##b0.W >> 16) | (S##b1.W & 0xFFFF0000u);                     \
+            hi_ = (S##b2.W >> 16) | (S##b3.W & 0xFFFF0000u);                     \
         }                                                                        \
-        *(uint2 *)&sB[buf_][(nc + (j)) * LPITCH + kq * 4] = make_uint2(lo_, hi_); \
+        *(uint2 *)&sB[buf_][lds_swz(nc + (j), kq >> 1) + (kq & 1) * 4] =         \
+            make_uint2(lo_, hi_);                                                \
     } while (0)
-#define NS_SSTORE(bufi)                                                          \
+#define NS_SSTORE(S, bufi)                                                       \
     do {                                                                         \
         const int buf_ = (bufi);                                                 \
-        uint16_t *sa_ = &sA[buf_][(t >> 3) * LPITCH + ac];                       \
-        *(uint4 *)(sa_) = ra0;                                                   \
-        *(uint4 *)(sa_ + 32 * LPITCH) = ra1;                                     \
+        *(uint4 *)&sA[buf_][lds_swz(t >> 3, t & 7)] = S##a0;                     \
+        *(uint4 *)&sA[buf_][lds_swz((t >> 3) + 32, t & 7)] = S##a1;              \
         if constexpr (AQ > 2) {                                                  \
-            *(uint4 *)(sa_ + 64 * LPITCH) = ra2;                                 \
-            *(uint4 *)(sa_ + 96 * LPITCH) = ra3;                                 \
+            *(uint4 *)&sA[buf_][lds_swz((t >> 3) + 64, t & 7)] = S##a2;          \
+            *(uint4 *)&sA[buf_][lds_swz((t >> 3) + 96, t & 7)] = S##a3;          \
         }                                                                        \
         if (bload) {                                                             \
-            NS_BCOL(0, x); NS_BCOL(1, x); NS_BCOL(2, y); NS_BCOL(3, y);          \
-            NS_BCOL(4, z); NS_BCOL(5, z); NS_BCOL(6, w); NS_BCOL(7, w);          \
+            NS_BCOL(S, 0, x); NS_BCOL(S, 1, x); NS_BCOL(S, 2, y);                \
+            NS_BCOL(S, 3, y); NS_BCOL(S, 4, z); NS_BCOL(S, 5, z);                \
+            NS_BCOL(S, 6, w); NS_BCOL(S, 7, w);                                  \
+        }                                                                        \
+    } while (0)
+// one k slice of MFMA work from LDS buffer bufi
+#define NS_COMPUTE(bufi)                                                         \
+    do {                                                                         \
+        _Pragma("unroll") for (int kk = 0; kk < LBK; kk += 16) {                 \
+            vec a[NB], b[NB];                                                    \
+            _Pragma("unroll") for (int i = 0; i < NB; ++i) a[i] =                \
+                *(const vec *)&sA[bufi][lds_swz(wm * WT + i * 32 + (l & 31),     \
+                                                (kk >> 3) + (l >> 5))];          \
+            _Pragma("unroll") for (int j = 0; j < NB; ++j) b[j] =                \
+                *(const vec *)&sB[bufi][lds_swz(wn * WT + j * 32 + (l & 31),     \
+                                                (kk >> 3) + (l >> 5))];          \
+            _Pragma("unroll") for (int i = 0; i < NB; ++i)                       \
+                _Pragma("unroll") for (int j = 0; j < NB; ++j)                   \
+                    acc[i][j] = Lp<T>::mma(a[i], b[j], acc[i][j]);               \
         }                                                                        \
     } while (0)
     v16f acc[NB][NB];
@@ -365,75 +409,86 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
         for (int j = 0; j < NB; ++j)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
-    const int nk = np / LBK;
-    NS_GLOAD(0);
-    NS_SSTORE(0);
+    // nk >= 1 slices; set p holds slice kt + 1 at even steps, set q at odd ones
+    NS_GLOAD(p, 0);
+    NS_SSTORE(p, 0);
+    NS_GLOAD(p, 1);
+    NS_GLOAD(q, 2);
     __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
-        // prefetch the next k slice (the last iteration reloads its own slice,
-        // in bounds, so the loads stay unconditional)
-        const int knext = (kt + 1 < nk ? kt + 1 : kt) * LBK;
-        NS_GLOAD(knext);
-#pragma unroll
-        for (int kk = 0; kk < LBK; kk += 16) {
-            vec a[NB], b[NB];
-#pragma unroll
-            for (int i = 0; i < NB; ++i)
-                a[i] = *(const vec *)&sA[buf][(wm * WT + i * 32 + (l & 31)) * LPITCH + kk + (l >> 5) * 8];
-#pragma unroll
-            for (int j = 0; j < NB; ++j)
-                b[j] = *(const vec *)&sB[buf][(wn * WT + j * 32 + (l & 31)) * LPITCH + kk + (l >> 5) * 8];
-#pragma unroll
-            for (int i = 0; i < NB; ++i)
-#pragma unroll
-                for (int j = 0; j < NB; ++j) acc[i][j] = Lp<T>::mma(a[i], b[j], acc[i][j]);
-        }
-        if (kt + 1 < nk) NS_SSTORE(buf ^ 1);
+    int kt = 0;
+    for (; kt + 1 < nk; kt += 2) {
+        NS_COMPUTE(0);
+        NS_SSTORE(p, 1);
+        NS_GLOAD(p, kt + 3);
+        __syncthreads();
+        NS_COMPUTE(1);
+        if (kt + 2 < nk) NS_SSTORE(q, 0);
+        NS_GLOAD(q, kt + 4);
         __syncthreads();
     }
+    if (kt < nk) NS_COMPUTE(0);   // odd nk: the last slice sits in buffer 0
+#undef NS_BUF
 #undef NS_GLOAD
 #undef NS_BCOL
 #undef NS_SSTORE
-    double part = 0.0;
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int gr = row0 + wm * WT + i * 32 + (e >> 2) * 8 + (l >> 5) * 4 + (e & 3);
-                const int gc = col0 + wn * WT + j * 32 + (l & 31);
-                if (gr < np && gc < np) {
-                    const float v = acc[i][j][e];
-                    const int64_t o = (int64_t)gr * ldx + gc;
-                    if (mode == 1) {
-                        // R = I - X^2 is small near convergence and keeps full
-                        // relative precision in 16 bits (3I - X^2 would not:
-                        // its diagonal ~2 is quantised at 2^-9 in FP16)
-                        const float rr = (gr == gc ? 1.0f : 0.0f) - v;
-                        part += (double)rr * (double)rr;
-                        Bb[o] = Lp<T>::enc(rr);
-                    } else {
-                        // X_{k+1} = X_k + X_k R / 2 = X_k (3I - X_k^2) / 2
-                        Xn[o] = Lp<T>::enc(Lp<T>::dec(Xc[o]) + 0.5f * v);
-                    }
-                }
-            }
+#undef NS_COMPUTE
+    // Epilogue over the whole tile, padding included: rows and columns in
+    // [np, ldx) of R and X_{k+1} only ever feed outputs that are never used,
+    // so the accesses need no bounds test and the X_k reads of the update
+    // are issued together rather than one guarded load at a time.
+    // element e of block (i, j) sits (i * 32 + (e / 4) * 8 + e % 4) rows and
+    // j * 32 columns from the lane's base: a uniform offset per element
+    const int er0 = row0 + wm * WT + (l >> 5) * 4, ec0 = col0 + wn * WT + (l & 31);
+    const uint32_t eo = (uint32_t)((er0 * ldx + ec0) * 2);
+#define NS_EOFF(i, j, e) ((((i) * 32 + ((e) >> 2) * 8 + ((e) & 3)) * ldx + (j) * 32) * 2)
     if (mode == 1) {
+        const __amdgpu_buffer_rsrc_t rsR = __builtin_amdgcn_make_buffer_rsrc((void *)Bb, (short)0, nrec, 0x00020000);
+        double part = 0.0;
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int gr = er0 + i * 32 + (e >> 2) * 8 + (e & 3), gc = ec0 + j * 32;
+                    // R = I - X^2 is small near convergence and keeps full
+                    // relative precision in 16 bits (3I - X^2 would not: its
+                    // diagonal ~2 is quantised at 2^-9 in FP16)
+                    const float rr = (gr == gc ? 1.0f : 0.0f) - acc[i][j][e];
+                    __builtin_amdgcn_raw_buffer_store_b16(Lp<T>::enc(rr), rsR, eo, NS_EOFF(i, j, e), 0);
+                    if (gr < np && gc < np) part += (double)rr * (double)rr;
+                }
         const double sum = block_sum(part, red);
         if (threadIdx.x == 0) ((double *)(ws + M.offRes))[(int64_t)it * M.ntile_ns + tile] = sum;
+    } else {
+        const __amdgpu_buffer_rsrc_t rsX = __builtin_amdgcn_make_buffer_rsrc((void *)Xc, (short)0, nrec, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rsN = __builtin_amdgcn_make_buffer_rsrc((void *)Xn, (short)0, nrec, 0x00020000);
+        // X_{k+1} = X_k + X_k R / 2 = X_k (3I - X_k^2) / 2, one block at a time
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                uint16_t xo[16];
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    xo[e] = __builtin_amdgcn_raw_buffer_load_b16(rsX, eo, NS_EOFF(i, j, e), 0);
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    __builtin_amdgcn_raw_buffer_store_b16(Lp<T>::enc(Lp<T>::dec(xo[e]) + 0.5f * acc[i][j][e]), rsN,
+                                                          eo, NS_EOFF(i, j, e), 0);
+            }
     }
+#undef NS_EOFF
 }
 
 template <typename T, int BM>
-__global__ __launch_bounds__(256) void k_ns_lp(ChunkDev cd, const uint32_t *tasks, char *ws, NsArgs na, int it,
+__global__ __launch_bounds__(256, 2) void k_ns_lp(ChunkDev cd, const uint32_t *tasks, char *ws, NsArgs na, int it,
                                                int mode) {
     ns_lp_tile<T, BM>(cd, xcd_task(tasks), ws, na, it, mode);
 }
 
 template <typename T, int BM>
-__global__ __launch_bounds__(256) void k_ns_lp_pq(ChunkDev cd, const uint32_t *tasks, int ntask, int *q, char *ws,
+__global__ __launch_bounds__(256, 2) void k_ns_lp_pq(ChunkDev cd, const uint32_t *tasks, int ntask, int *q, char *ws,
                                                   NsArgs na, int it, int mode) {
     __shared__ int idx_s;
     const int x = blockIdx.x & 7, seg = ntask >> 3;
