@@ -40,6 +40,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ns_lp_fp16_cube32768_traffic.md")
+NS_SOURCE = os.path.join(ROOT, "paper_2104_08245_amd", "csrc", "k_ns.hip")
+
+
+def measured_traffic(config, prec):
+    """HBM bytes per NS launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary (copy-calibrated), or None when the summary does not cover this
+    workload or the kernel source has changed since the counters were taken."""
+    import hashlib
+    if config != 3 or prec != "fp16" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    sha, nbytes = None, None
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("kernel_source_sha256 "):
+            sha = line.split(":", 1)[1].strip()
+        elif line.startswith("k_ns_lp traffic_bytes_per_launch:"):
+            nbytes = int(line.split(":", 1)[1])
+    cur = hashlib.sha256(open(NS_SOURCE, "rb").read()).hexdigest()
+    return nbytes if (sha == cur and nbytes) else None
+
+
 # ------------------------------------------------------------------ CPU leg
 _SYS = None
 
@@ -88,7 +109,7 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sched", default="graph", choices=["graph", "stream", "bucket"])
+    ap.add_argument("--sched", default="graph", choices=["graph", "stream", "bucket", "persistent"])
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB "
                          "(reference for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -121,7 +142,8 @@ def main():
     import torch
     from paper_2104_08245_amd import Solver, _lib as L
 
-    sched = {"graph": L.SCHED_GRAPH, "stream": L.SCHED_STREAM, "bucket": L.SCHED_PER_BUCKET}[args.sched]
+    sched = {"graph": L.SCHED_GRAPH, "stream": L.SCHED_STREAM, "bucket": L.SCHED_PER_BUCKET,
+             "persistent": L.SCHED_PERSISTENT}[args.sched]
     dev = torch.device("cuda:0")
     sv = Solver(system, prec=args.prec, device=dev, ws_budget=int(args.ws_gb * (1 << 30)), sched=sched)
     info = sv.plan.info()
@@ -166,11 +188,22 @@ def main():
     ns_tf = gemm_flops / (prof["ms_ns"] / 1e3) / 1e12 if prof["ms_ns"] > 0 else 0.0
     peak = PEAK_TFLOPS[args.prec]
     roofline = {"bound": "mfma", "achieved": round(ns_tf, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(ns_tf / peak, 4), "traffic": None,
+                "frac": round(ns_tf / peak, 4), "traffic": measured_traffic(args.config, args.prec),
                 "kernel": "k_ns_lp" if args.prec in ("fp16", "bf16") else "k_ns64",
                 "launches": prof["n_ns_launches"],
                 "avg_launch_ms": round(prof["ms_ns"] / max(1, prof["n_ns_launches"]), 4)}
     phases = {k: round(v, 2) for k, v in prof.items() if k.startswith("ms_")}
+    # composite bound: each phase's algorithmic work at its own peak (NS GEMMs
+    # on the MFMA peak of the precision, finishing products at the FP32 peak,
+    # the FP64 Cholesky + solves at the FP64 peak, the gather at 8 TB/s)
+    m = n / 6.0
+    setup_flops = float((n ** 3 / 3.0 + 2.0 * n ** 3 + 12.0 * n ** 2).sum())
+    gather_bytes = float((576.0 * m ** 2 + 288.0 * m).sum())
+    terms = {"ns": gemm_flops / (peak * 1e12), "finish": fin_flops / 157.3e12,
+             "setup_fp64": setup_flops / 78.6e12, "gather_scatter": gather_bytes / 8e12}
+    t_bound = sum(terms.values())
+    composite = {"ms": round(1e3 * t_bound, 2), "frac": round(1e3 * t_bound / ms, 4),
+                 "terms_ms": {k: round(1e3 * v, 2) for k, v in terms.items()}}
 
     out = {
         "metric": "NOLSM sign-solve TFLOP/s + submatrices/s, mixed vs FP64 at stated energy error",
@@ -193,6 +226,7 @@ def main():
         "status_ok": int(ok.sum()),
         "phases_ms": phases,
         "roofline": roofline,
+        "composite_bound": composite,
     }
     if cpu is not None:
         E = st["energy_KD"]
