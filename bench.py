@@ -98,6 +98,71 @@ def cpu_baseline(system, sample, workers):
     return dict(wall=wall, flops=flops, E={J: e for J, e, _, _, _ in res}, n=len(res))
 
 
+def bounds_eval(args):
+    """Learned vs Gershgorin spectral bounds on the trajectory workload: the
+    MLP is trained with the library's kernels on the oracle-labelled set in
+    tests/golden, then every frame is solved in FP16 with both bounds. The
+    energy error of each is taken against the FP64 GPU solve of the same
+    frame (which matches the oracle to 1e-10 relative)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2104_08245_amd import Solver, _lib as L
+    from paper_2104_08245_amd import learned
+
+    dev = torch.device("cuda:0")
+    ts = np.load(os.path.join(ROOT, "tests", "golden", "mlp_train.npz"))
+    t0 = time.perf_counter()
+    tr = learned.train(ts["features"], ts["labels"], epochs=200, device=dev)
+    torch.cuda.synchronize()
+    log(f"trained the MLP on {len(ts['labels'])} submatrices in {time.perf_counter() - t0:.1f}s")
+    frames = synth.trajectory(nframes=10)
+    log(f"generated {len(frames)} frames of {frames[0].nmol} molecules")
+    res = {"gershgorin": [[], 0, []], "learned": [[], 0, []]}
+    ms = {"gershgorin": 0.0, "learned": 0.0}
+    for f, sysf in enumerate(frames):
+        ref = Solver(sysf, prec="fp64", device=dev)
+        ref.run()
+        torch.cuda.synchronize()
+        e64 = ref.host_stats()["energy_KD"]
+        del ref
+        for mode in ("gershgorin", "learned"):
+            kw = {}
+            if mode == "learned":
+                kw = dict(bounds=L.BOUNDS_LEARNED, d_mlp=tr["params"].data_ptr(),
+                          d_mlp_norm=tr["norm"].data_ptr())
+            sv = Solver(sysf, prec="fp16", device=dev, **kw)
+            sv.run()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            sv.run()
+            torch.cuda.synchronize()
+            ms[mode] += 1e3 * (time.perf_counter() - t)
+            st = sv.host_stats()
+            res[mode][0].append(st["iters"].astype(np.int64))
+            res[mode][1] += int(st["fallback"].sum())
+            res[mode][2].append(np.abs(st["energy_KD"] - e64))
+            del sv
+        log(f"frame {f}: gershgorin {res['gershgorin'][0][-1].mean():.3f}, "
+            f"learned {res['learned'][0][-1].mean():.3f} mean iterations")
+    out = {"metric": "NS iterations per submatrix, learned vs Gershgorin bounds",
+           "data": "synthetic", "dtype": "f16",
+           "config": {"workload": "10-frame water-like trajectory, 4096 molecules, r_c 0.9 nm",
+                      "frames": len(frames), "molecules": frames[0].nmol}}
+    for mode, (its, fb, dE) in res.items():
+        its = np.concatenate(its)
+        dE = np.concatenate(dE)
+        vals, cnt = np.unique(its, return_counts=True)
+        out[mode] = {"mean_iters": round(float(its.mean()), 4),
+                     "histogram": {int(v): int(c) for v, c in zip(vals, cnt)},
+                     "restarts": fb, "ms_per_frame": round(ms[mode] / len(frames), 2),
+                     "energy_error_vs_fp64_gpu": {"max": float(dE.max()), "mean": float(dE.mean())}}
+    g, l = out["gershgorin"]["mean_iters"], out["learned"]["mean_iters"]
+    out["iterations_saved_per_submatrix"] = round(g - l, 4)
+    out["iterations_saved_frac"] = round((g - l) / g, 4)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +178,9 @@ def main():
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB "
                          "(reference for the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--bounds-eval", action="store_true",
+                    help="instead of the throughput line: NS iteration counts with learned vs "
+                         "Gershgorin bounds over the 10-frame trajectory (FP16)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -122,6 +190,10 @@ def main():
 
     import numpy as np
     import synth
+
+    if args.bounds_eval:
+        bounds_eval(args)
+        return
 
     t0 = time.perf_counter()
     system = synth.make_config(args.config)

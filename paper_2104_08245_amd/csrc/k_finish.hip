@@ -49,69 +49,64 @@ __device__ __forceinline__ TV vec_in(const SkinnyArgs &a, const SubMeta &M, cons
     return v;
 }
 
-// out = P * in for 64 rows per workgroup; wave w takes rows 16w..16w+15,
-// lanes split the columns, then a butterfly reduction across the wave.
+// out = P * in for 256 rows per workgroup, one row per lane. The input block
+// (n x bs, formed from up to two stored vectors) is staged once per
+// workgroup in LDS and read as a broadcast; each lane streams its row of P
+// with 16-byte loads, so the kernel is a plain HBM stream of P.
+// Dynamic LDS: max_np x 6 values of TV.
 template <typename TP, typename TV>
 __global__ __launch_bounds__(256) void k_skinny(ChunkDev cd, char *ws, SkinnyArgs sa, int bs) {
     typedef typename Dec<TP>::storage ST;
+    constexpr int EPL = 16 / (int)sizeof(ST);   // elements per 16-byte load
+    extern __shared__ __attribute__((aligned(16))) char skm[];
+    TV *vin = (TV *)skm;
     const uint32_t task = xcd_task(cd.t_rows);
     if (task == NOLSM_TASK_NONE) return;
-    const int s = task_slot(task), rb = task_a(task);
+    const int s = task_slot(task), rq = task_a(task);
     const SubMeta M = cd.meta[s];
     const SubCtl *ctl = cd.ctl + s;
     if (ctl->status == NOLSM_MOL_NOT_SPD) return;
-    const int np = M.np;
+    const int np = M.np, t = threadIdx.x;
     const int K = ctl->iters;
     const ST *P = (const ST *)(ws + ((K & 1) ? M.offX1 : M.offL));
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    TV acc[16][BSMAX];
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-#pragma unroll
-        for (int j = 0; j < BSMAX; ++j) acc[r][j] = 0;
-    const int rbase = rb * 64 + w * 16;
-    for (int c = l; c < np; c += 64) {
-        TV in[BSMAX];
-#pragma unroll
-        for (int j = 0; j < BSMAX; ++j) in[j] = (j < bs) ? vec_in<TV>(sa, M, ws, c, j) : (TV)0;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const TV p = (TV)Dec<TP>::get(P[(int64_t)(rbase + r) * M.ldx + c]);
-#pragma unroll
-            for (int j = 0; j < BSMAX; ++j) acc[r][j] += p * in[j];
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-#pragma unroll
-        for (int j = 0; j < BSMAX; ++j) {
-            TV v = acc[r][j];
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-            acc[r][j] = v;
-        }
     TV *V = (TV *)(ws + M.offVec);
     const int64_t vs = (int64_t)np * 6 * 8 / sizeof(TV);
-    if (l == 0) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-#pragma unroll
-            for (int j = 0; j < BSMAX; ++j)
-                if (j < bs) V[(int64_t)sa.out * vs + (int64_t)(rbase + r) * 6 + j] = acc[r][j];
+    for (int f = t; f < np * 6; f += 256) {
+        const int r = f / 6, j = f - r * 6;
+        vin[f] = (j < bs) ? vec_in<TV>(sa, M, ws, r, j) : (TV)0;
     }
-    if (sa.save >= 0) {
-        for (int f = threadIdx.x; f < 64 * bs; f += 256) {
-            const int r = rb * 64 + f / bs, j = f % bs;
-            V[(int64_t)sa.save * vs + (int64_t)r * 6 + j] = vec_in<TV>(sa, M, ws, r, j);
+    __syncthreads();
+    const int row = rq * 256 + t;
+    if (row >= np) return;   // np is a multiple of 64: whole waves leave
+    if (sa.save >= 0)
+        for (int j = 0; j < bs; ++j) V[(int64_t)sa.save * vs + (int64_t)row * 6 + j] = vin[row * 6 + j];
+    const ST *prow = P + (int64_t)row * M.ldx;
+    TV acc[BSMAX];
+#pragma unroll
+    for (int j = 0; j < BSMAX; ++j) acc[j] = 0;
+#pragma unroll 4
+    for (int c = 0; c < np; c += EPL) {
+        const uint4 raw = *(const uint4 *)(prow + c);
+        const ST *pe = (const ST *)&raw;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+            const TV p = (TV)Dec<TP>::get(pe[e]);
+            const TV *vi = vin + (c + e) * 6;
+#pragma unroll
+            for (int j = 0; j < BSMAX; ++j) acc[j] += p * vi[j];
         }
     }
+#pragma unroll
+    for (int j = 0; j < BSMAX; ++j)
+        if (j < bs) V[(int64_t)sa.out * vs + (int64_t)row * 6 + j] = acc[j];
 }
 
 template <typename TP, typename TV>
 static hipError_t run_finish(const ChunkDev &cd, char *ws, int nfinal, int bs, hipStream_t st) {
     auto L = [&](int ina, int inb, double al, double be, int out, int save) {
         SkinnyArgs a{ina, inb, al, be, out, save};
-        hipLaunchKernelGGL((k_skinny<TP, TV>), dim3(cd.n_rows), dim3(256), 0, st, cd, ws, a, bs);
+        hipLaunchKernelGGL((k_skinny<TP, TV>), dim3(cd.n_rows), dim3(256), (size_t)cd.max_np * 6 * sizeof(TV), st, cd,
+                           ws, a, bs);
         return hipGetLastError();
     };
     hipError_t e;
@@ -301,8 +296,11 @@ hipError_t launch_assemble(const double *Dcols, double *Dval, const int32_t *sca
 }
 
 hipError_t nolsm_finish_init() {
-    return hipFuncSetAttribute((const void *)k_extract<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) ||
-                   hipFuncSetAttribute((const void *)k_extract<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024)
-               ? hipErrorInvalidValue
-               : hipSuccess;
+    const void *fns[] = {(const void *)k_extract<double>,          (const void *)k_extract<float>,
+                         (const void *)k_skinny<double, double>,   (const void *)k_skinny<float, float>,
+                         (const void *)k_skinny<F16, float>,       (const void *)k_skinny<BF16, float>};
+    for (const void *f : fns)
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+            return hipErrorInvalidValue;
+    return hipSuccess;
 }

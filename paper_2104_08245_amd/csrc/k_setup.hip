@@ -15,74 +15,78 @@
 // buffer gets 64 extra columns holding E_cJ (identity on the molecule's own
 // bs rows), which the substitution turns into Y_J. Padding rows/columns
 // n..np-1: S = I, K = 0.
-// grid (max_m, nsub), 256 threads; dynamic LDS: bs*np doubles + m ints.
+// One workgroup per (block row a, submatrix). Each stored block (I, C) of
+// row I = N(J)_a is located in N(J) by one binary search, giving the inverse
+// map pos[b] = CSR entry of block column N(J)_b (or -1); the 6 x np stripes
+// are then written straight to HBM, coalesced along the row.
+// grid (max_m, nsub), 256 threads; dynamic LDS: 3 m ints.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArgs ga) {
-    extern __shared__ double smem[];
+    extern __shared__ int gsm[];
     const int s = blockIdx.y, a = blockIdx.x;
     if (s >= cd.nsub) return;
     const SubMeta M = cd.meta[s];
     if (a >= M.m) return;
-    const int bs = ga.bs, np = M.np, n = M.n;
-    double *stripe = smem;                                   // bs x np
-    int *list = (int *)(smem + (size_t)bs * cd.max_np);      // m
+    const int bs = ga.bs, np = M.np, n = M.n, m = M.m, t = threadIdx.x;
+    int *list = gsm;                 // N(J)
+    int *posK = gsm + cd.max_m;      // block column b -> CSR entry in K's row I, or -1
+    int *posS = gsm + 2 * cd.max_m;  // the same for S
     const int *nlist = ga.sub_blk + M.sub_off;
-    for (int i = threadIdx.x; i < M.m; i += 256) list[i] = nlist[i];
+    for (int i = t; i < m; i += 256) {
+        list[i] = nlist[i];
+        posK[i] = -1;
+        posS[i] = -1;
+    }
     const int I = nlist[a];   // from global memory: `list` is complete only after the barrier
     __syncthreads();
     for (int which = 0; which < 2; ++which) {
         const int *rp = which ? ga.Srp : ga.Krp;
         const int *ci = which ? ga.Sci : ga.Kci;
-        const double *val = which ? ga.Sval : ga.Kval;
-        for (int i = threadIdx.x; i < bs * np; i += 256) stripe[i] = 0.0;
-        __syncthreads();
+        int *pos = which ? posS : posK;
         const int lo = rp[I], hi = rp[I + 1];
-        const int nel = (hi - lo) * bs * bs;
-        for (int f = threadIdx.x; f < nel; f += 256) {
-            const int e = lo + f / (bs * bs);
-            const int rc = f % (bs * bs);
+        for (int e = lo + t; e < hi; e += 256) {
             const int C = ci[e];
-            // binary search C in N(J)
-            int l = 0, h = M.m - 1, b = -1;
+            int l = 0, h = m - 1;
             while (l <= h) {
                 const int mid = (l + h) >> 1;
                 const int v = list[mid];
-                if (v == C) { b = mid; break; }
+                if (v == C) { pos[mid] = e; break; }
                 if (v < C) l = mid + 1; else h = mid - 1;
             }
-            if (b >= 0) {
-                const int r = rc / bs, c = rc % bs;
-                double v = val[(int64_t)e * bs * bs + rc];
-                if (which == 1 && M.J == ga.poison_J && a == 0 && b == 0 && r == 0 && c == 0) v = -1.0;
-                stripe[r * np + b * bs + c] = v;
-            }
         }
-        __syncthreads();
-        double *dst = (double *)(ws + (which ? M.offL : M.offK));
-        const int64_t ld = which ? np : np + 64;
-        for (int i = threadIdx.x; i < bs * np; i += 256) {
-            const int r = i / np, c = i % np;
-            dst[(int64_t)(a * bs + r) * ld + c] = stripe[i];
+    }
+    __syncthreads();
+    double *Kd = (double *)(ws + M.offK);
+    double *Sd = (double *)(ws + M.offL);
+    const int64_t ldk = np + 64, lds = np;
+    const int bb = bs * bs;
+    const bool poison = (M.J == ga.poison_J && a == 0);
+    for (int i = t; i < bs * np; i += 256) {
+        const int r = i / np, c = i - r * np;
+        double vk = 0.0, vs = 0.0;
+        if (c < n) {
+            const int b = c / bs, cc = c - b * bs;
+            const int ek = posK[b], es = posS[b];
+            if (ek >= 0) vk = ga.Kval[(int64_t)ek * bb + r * bs + cc];
+            if (es >= 0) vs = ga.Sval[(int64_t)es * bb + r * bs + cc];
         }
-        if (which == 0) {
-            // E tile: columns np..np+63 of the K buffer
-            for (int i = threadIdx.x; i < bs * 64; i += 256) {
-                const int r = i / 64, c = i % 64;
-                dst[(int64_t)(a * bs + r) * ld + np + c] = (a == M.p && c == r) ? 1.0 : 0.0;
-            }
-        }
-        __syncthreads();
+        if (poison && i == 0) vs = -1.0;
+        Kd[(int64_t)(a * bs + r) * ldk + c] = vk;
+        Sd[(int64_t)(a * bs + r) * lds + c] = vs;
+    }
+    // E tile: columns np..np+63 of the K buffer
+    for (int i = t; i < bs * 64; i += 256) {
+        const int r = i / 64, c = i % 64;
+        Kd[(int64_t)(a * bs + r) * ldk + np + c] = (a == M.p && c == r) ? 1.0 : 0.0;
     }
     // padding rows (one workgroup per submatrix does it)
     if (a == 0 && np > n) {
-        double *Ld = (double *)(ws + M.offL);
-        double *Kd = (double *)(ws + M.offK);
         const int rows = np - n;
-        for (int i = threadIdx.x; i < rows * np; i += 256) {
+        for (int i = t; i < rows * np; i += 256) {
             const int r = n + i / np, c = i % np;
-            Ld[(int64_t)r * np + c] = (r == c) ? 1.0 : 0.0;
+            Sd[(int64_t)r * np + c] = (r == c) ? 1.0 : 0.0;
         }
-        for (int i = threadIdx.x; i < rows * (np + 64); i += 256) {
+        for (int i = t; i < rows * (np + 64); i += 256) {
             const int r = n + i / (np + 64), c = i % (np + 64);
             Kd[(int64_t)r * (np + 64) + c] = 0.0;
         }
@@ -460,7 +464,7 @@ __global__ void k_init_ctl(ChunkDev cd) {
 hipError_t launch_gather(const ChunkDev &cd, char *ws, const GatherArgs &ga, hipStream_t st) {
     hipLaunchKernelGGL(k_init_ctl, dim3(cd.nsub), dim3(64), 0, st, cd);
     LAUNCH_CHECK();
-    const size_t lds = (size_t)ga.bs * cd.max_np * 8 + (size_t)cd.max_m * 4 + 16;
+    const size_t lds = (size_t)cd.max_m * 3 * sizeof(int);
     hipLaunchKernelGGL(k_gather, dim3(cd.max_m, cd.nsub), dim3(256), lds, st, cd, ws, ga);
     return hipGetLastError();
 }

@@ -326,7 +326,7 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
                     (T == 64 && (pl->prec == NOLSM_FP16 || pl->prec == NOLSM_BF16)) ? ch.t_ns64 : ch.t_ns;
                 for (int32_t a = 0; a < nt; ++a)
                     for (int32_t b = 0; b < nt; ++b) tl.push_back(NOLSM_TASK(s, a, b));
-                for (int32_t a = 0; a < m.P; ++a) ch.t_rows.push_back(NOLSM_TASK(s, a, 0));
+                for (int32_t a = 0; a < (m.P + 3) / 4; ++a) ch.t_rows.push_back(NOLSM_TASK(s, a, 0));
             }
             ch.ws_used = off;
             ch.n_ns_real = ch.t_ns.size();
