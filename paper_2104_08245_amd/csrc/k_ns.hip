@@ -4,14 +4,15 @@
 // One iteration is two batched GEMM launches over the tiles of every active
 // submatrix of a chunk:
 //   mode 1: T = X_k X_k; epilogue: partial sums of ||T - I||_F^2 per tile and
-//           B = 3I - T stored in the iteration precision;
+//           R = I - T stored in the iteration precision;
 //   mode 2: every workgroup of a submatrix reads the finished residual
 //           r_k = ||X_k^2 - I||_F, takes the same stop/continue/restart
-//           decision, and if continuing writes X_{k+1} = X_k B / 2.
+//           decision, and if continuing writes X_{k+1} = X_k + X_k R / 2,
+//           which equals X_k (3I - X_k^2) / 2 of Eq. NS1.
 // X ping-pongs between two buffers (X_k in buffer k % 2). Precisions:
 // FP64 / FP32 use 64x64 tiles on v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4;
-// FP16 / BF16 use 128x128 tiles on v_mfma_f32_32x32x16_{f16,bf16} with FP32
-// accumulation.
+// FP16 / BF16 use 128x128 (or 64x64) tiles on v_mfma_f32_32x32x16_{f16,bf16}
+// with FP32 accumulation.
 #include "dev_common.h"
 #include "kernels.h"
 
@@ -277,8 +278,8 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
     constexpr int NB = WT / 32;         // 32x32 MFMA blocks per wave dimension
     constexpr int AQ = BM / 32;         // 16-byte A loads per thread
     constexpr int BT = 2 * BM;          // threads that load a 4(k) x 8(n) B block
-    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * LBK];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BM * LBK];
+    __shared__ __attribute__((aligned(16))) uint16_t sA[1][BM * LBK];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[1][BM * LBK];
     __shared__ double red[256];
     __shared__ int act_s;
     if (task == NOLSM_TASK_NONE) return;
@@ -332,12 +333,12 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
     const uint32_t vb = (uint32_t)((kq * 4 * ldx + col0 + nc) * 2);
     const int sa32 = 64 * ldx, srow = 2 * ldx;   // bytes of 32 rows / one row
     const int nk = np / LBK;
-    // two register sets (p and q) of one k slice each: the load of slice
-    // kt + 3 is issued at the end of step kt and stored to LDS at the end of
-    // step kt + 2, so global latency is covered by two compute phases
+    // One LDS buffer and one register set per workgroup (32 KB of LDS and
+    // about 140 VGPRs for BM = 128), so three workgroups share a CU: slice
+    // kt + 1 is fetched into registers while slice kt is multiplied from LDS,
+    // and latency is hidden across workgroups rather than by a deeper ring.
     const uint4 z4 = {0, 0, 0, 0};
     uint4 pa0 = z4, pa1 = z4, pa2 = z4, pa3 = z4, pb0 = z4, pb1 = z4, pb2 = z4, pb3 = z4;
-    uint4 qa0 = z4, qa1 = z4, qa2 = z4, qa3 = z4, qb0 = z4, qb1 = z4, qb2 = z4, qb3 = z4;
 #define NS_BUF(rs, vo, so) __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, so, 0))
 #define NS_GLOAD(S, ks)                                                          \
     do {                                                                         \
@@ -409,24 +410,16 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
         for (int j = 0; j < NB; ++j)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
-    // nk >= 1 slices; set p holds slice kt + 1 at even steps, set q at odd ones
     NS_GLOAD(p, 0);
     NS_SSTORE(p, 0);
-    NS_GLOAD(p, 1);
-    NS_GLOAD(q, 2);
     __syncthreads();
-    int kt = 0;
-    for (; kt + 1 < nk; kt += 2) {
+    for (int kt = 0; kt < nk; ++kt) {
+        NS_GLOAD(p, kt + 1);   // past the last slice: zeros, no memory access
         NS_COMPUTE(0);
-        NS_SSTORE(p, 1);
-        NS_GLOAD(p, kt + 3);
         __syncthreads();
-        NS_COMPUTE(1);
-        if (kt + 2 < nk) NS_SSTORE(q, 0);
-        NS_GLOAD(q, kt + 4);
+        if (kt + 1 < nk) NS_SSTORE(p, 0);
         __syncthreads();
     }
-    if (kt < nk) NS_COMPUTE(0);   // odd nk: the last slice sits in buffer 0
 #undef NS_BUF
 #undef NS_GLOAD
 #undef NS_BCOL
@@ -482,13 +475,13 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
 }
 
 template <typename T, int BM>
-__global__ __launch_bounds__(256, 2) void k_ns_lp(ChunkDev cd, const uint32_t *tasks, char *ws, NsArgs na, int it,
+__global__ __launch_bounds__(256, 3) void k_ns_lp(ChunkDev cd, const uint32_t *tasks, char *ws, NsArgs na, int it,
                                                int mode) {
     ns_lp_tile<T, BM>(cd, xcd_task(tasks), ws, na, it, mode);
 }
 
 template <typename T, int BM>
-__global__ __launch_bounds__(256, 2) void k_ns_lp_pq(ChunkDev cd, const uint32_t *tasks, int ntask, int *q, char *ws,
+__global__ __launch_bounds__(256, 3) void k_ns_lp_pq(ChunkDev cd, const uint32_t *tasks, int ntask, int *q, char *ws,
                                                   NsArgs na, int it, int mode) {
     __shared__ int idx_s;
     const int x = blockIdx.x & 7, seg = ntask >> 3;
