@@ -173,6 +173,7 @@ class SubResult:
     scale: float
     N_J: float
     E_J: float
+    Wcols: np.ndarray | None = None   # (n_J, bs), only when asked for
 
 
 def newton_schulz_sign(A, c, tol=1e-10, max_iter=100):
@@ -192,8 +193,11 @@ def newton_schulz_sign(A, c, tol=1e-10, max_iter=100):
     return X, max_iter, r, False
 
 
-def solve_submatrix(KJ, SJ, p, bs, mu, tol=1e-10, max_iter=100, scale=None):
-    """Everything inside one submatrix, for the molecule at block position p."""
+def solve_submatrix(KJ, SJ, p, bs, mu, tol=1e-10, max_iter=100, scale=None, want_w=False):
+    """Everything inside one submatrix, for the molecule at block position p.
+    With want_w, also the owned columns of the energy-weighted density
+    matrix T_J(W) = T_J(D) T_J(K) T_J(D) (Sec. III-B.2), from the full
+    T_J(D) = (I - X) T_J(S)^-1 / 2."""
     n = KJ.shape[0]
     try:
         L = np.linalg.cholesky(SJ)
@@ -214,7 +218,11 @@ def solve_submatrix(KJ, SJ, p, bs, mu, tol=1e-10, max_iter=100, scale=None):
     rows = slice(p * bs, (p + 1) * bs)
     N_J = float(np.trace(SJ[rows, :] @ Dcols))
     E_J = float(np.trace(KJ[rows, :] @ Dcols))
-    return SubResult(OK if conv else NOCONV, Dcols, X, A, iters, r, c, N_J, E_J)
+    Wcols = None
+    if want_w:
+        DJ = 0.5 * (np.eye(n) - X) @ s_inv(np.eye(n))
+        Wcols = DJ @ (KJ @ Dcols)
+    return SubResult(OK if conv else NOCONV, Dcols, X, A, iters, r, c, N_J, E_J, Wcols)
 
 
 # --------------------------------------------------------------------------
@@ -232,12 +240,15 @@ class BatchResult:
     scale: np.ndarray
     N: np.ndarray          # per-molecule Tr(S D) share
     E: np.ndarray          # per-molecule Tr(K D) share
+    Wcols: list | None = None     # per J, (n_J, bs), with want_w
+    W_val: np.ndarray | None = None   # W on D's block-CSR, with want_w
 
 
-def nolsm(system, mu=None, tol=1e-10, max_iter=100, molecules=None, keep_x=False):
+def nolsm(system, mu=None, tol=1e-10, max_iter=100, molecules=None, keep_x=False, want_w=False):
     """The NOLSM density matrix of a synth.System (or anything with the same
     K/S block-CSR fields). `molecules` restricts the solve to a subset of
-    column blocks (the remaining Dcols entries are None)."""
+    column blocks (the remaining Dcols entries are None). With want_w, also
+    the energy-weighted density matrix W, written back like D."""
     K, S = system.K, system.S
     nb, bs = K.nb, K.bs
     mu = system.mu if mu is None else mu
@@ -252,13 +263,15 @@ def nolsm(system, mu=None, tol=1e-10, max_iter=100, molecules=None, keep_x=False
     scale = np.full(nb, np.nan)
     N = np.full(nb, np.nan)
     E = np.full(nb, np.nan)
+    Wcols = [None] * nb if want_w else None
+    W_val = np.zeros_like(D_val) if want_w else None
     xs = {}
     for J in todo:
         idx = sub_blk[sub_ptr[J]:sub_ptr[J + 1]]
         p = int(plan["self_pos"][J])
         KJ = gather(idx, bs, K.row_ptr, K.col_idx, K.val)
         SJ = gather(idx, bs, S.row_ptr, S.col_idx, S.val)
-        r = solve_submatrix(KJ, SJ, p, bs, mu, tol, max_iter)
+        r = solve_submatrix(KJ, SJ, p, bs, mu, tol, max_iter, want_w=want_w)
         status[J], iters[J], resid[J], scale[J] = r.status, r.iters, r.resid, r.scale
         if r.Dcols is None:
             continue
@@ -266,9 +279,13 @@ def nolsm(system, mu=None, tol=1e-10, max_iter=100, molecules=None, keep_x=False
         N[J], E[J] = r.N_J, r.E_J
         for a in range(len(idx)):
             D_val[plan["scatter_pos"][sub_ptr[J] + a]] = r.Dcols[a * bs:(a + 1) * bs, :]
+        if want_w:
+            Wcols[J] = r.Wcols
+            for a in range(len(idx)):
+                W_val[plan["scatter_pos"][sub_ptr[J] + a]] = r.Wcols[a * bs:(a + 1) * bs, :]
         if keep_x:
             xs[J] = (r.X, r.A)
-    res = BatchResult(plan, Dcols, D_val, status, iters, resid, scale, N, E)
+    res = BatchResult(plan, Dcols, D_val, status, iters, resid, scale, N, E, Wcols, W_val)
     if keep_x:
         res.xs = xs
     return res
@@ -294,12 +311,12 @@ def submatrix(system, J, mu=None):
     return KJ, SJ, idx, int(self_pos[J])
 
 
-def solve_molecule(system, J, mu=None, tol=1e-10, max_iter=100):
+def solve_molecule(system, J, mu=None, tol=1e-10, max_iter=100, want_w=False):
     """Steps 3-8 and 10 for one column block J, without assembling D (for
     sampled checks on systems too large for the whole-batch oracle)."""
     mu = system.mu if mu is None else mu
     KJ, SJ, idx, p = submatrix(system, J)
-    return solve_submatrix(KJ, SJ, p, system.K.bs, mu, tol, max_iter)
+    return solve_submatrix(KJ, SJ, p, system.K.bs, mu, tol, max_iter, want_w=want_w)
 
 
 def dense(csr):
