@@ -123,6 +123,14 @@ typedef struct {
                                 set -> submatrices padded to 64(b+1) rows use
                                 64x64 tiles, else 128x128 (default: bits 0, 2,
                                 i.e. 64 and 192 rows). Used by configure.       */
+    double *d_wcols;         /* optional device [sum_m*bs*bs], Dcols layout: the
+                                owned columns of the energy-weighted density
+                                matrix T_J(W) = T_J(D) T_J(K) T_J(D) (Sec. III-B.2).
+                                Computed as (A_J + mu I) Dcols_J, which equals
+                                the definition because T_J(D) = P T_J(S)^-1 with
+                                P = (I - sign A_J)/2 a projector commuting with
+                                A_J. Zero for NOT_SPD molecules. Null: skipped.
+                                Assemble W with nolsm_assemble_D.                */
 } nolsm_solve_opts;
 
 /* Fills *o with the defaults above for precision `prec`. */

@@ -38,7 +38,7 @@ class SolveOpts(C.Structure):
                 ("mlp_safety", C.c_float), ("sched", C.c_int32), ("sync_errors", C.c_int32),
                 ("d_features", C.c_void_p), ("debug_scale_mult", C.c_double),
                 ("debug_poison_mol", C.c_int32), ("profile", C.c_int32),
-                ("ns_small_tile_mask", C.c_uint64)]
+                ("ns_small_tile_mask", C.c_uint64), ("d_wcols", C.c_void_p)]
 
 
 class MolStats(C.Structure):

@@ -146,6 +146,7 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
     ea.Sval = b.dS;
     ea.Dcols = b.dDcols;
     ea.Dval = b.dD;
+    ea.Wcols = o.d_wcols;
     ea.stats = b.dstats;
     ea.bs = pl->bs;
     ea.prec = o.prec;
@@ -170,6 +171,7 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
         if ((e = launch_finish(cd, b.ws, fa, st)) != hipSuccess) return hip_fail(e, "finish launch");
         if (prof) prof->mark(PH_EXTRACT);
         if ((e = launch_extract(cd, b.ws, ea, st)) != hipSuccess) return hip_fail(e, "extract launch");
+        if (ea.Wcols && (e = launch_wcols(cd, b.ws, ea, st)) != hipSuccess) return hip_fail(e, "W launch");
         if (prof) {
             prof->n_ns += 2 * o.max_iter;
             prof->n_fin += fa.nfinal == 0 ? 1 : (fa.nfinal == 1 ? 3 : 9);
@@ -195,6 +197,10 @@ extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const doub
         ((opts->sched == NOLSM_SCHED_PER_BUCKET) != (pl->sched == NOLSM_SCHED_PER_BUCKET))) {
         nolsm_set_last_error("sign_batch: options differ from the configured ones");
         return NOLSM_E_STATE;
+    }
+    if (opts->d_wcols && (pl->bs & 1)) {
+        nolsm_set_last_error("sign_batch: the energy-weighted output needs an even block size");
+        return NOLSM_E_ARG;
     }
     if (opts->bounds == NOLSM_BOUNDS_LEARNED && (!opts->d_mlp || !opts->d_mlp_norm)) {
         nolsm_set_last_error("sign_batch: learned bounds need d_mlp and d_mlp_norm");

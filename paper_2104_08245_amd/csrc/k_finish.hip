@@ -226,6 +226,57 @@ __global__ __launch_bounds__(256) void k_extract(ChunkDev cd, char *ws, ExtractA
     }
 }
 
+// ---------------------------------------------------------------------------
+// Owned columns of the energy-weighted density matrix (Sec. III-B.2):
+//   T_J(W)[:, cJ] = T_J(D) T_J(K) T_J(D)[:, cJ].
+// With T_J(D) = P T_J(S)^-1, P = (I - sign A_J)/2 a projector that commutes
+// with A_J = T_J(S)^-1 T_J(K) - mu I, this is P (A_J + mu I) P Y_J =
+// (A_J + mu I) Dcols_J: one n x n by n x bs product with the FP64 A_J still in
+// the workspace. One row per lane, 256 rows per workgroup; Dcols_J staged in
+// LDS (max_np x bs doubles). NOT_SPD molecules get zeros.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_wcols(ChunkDev cd, char *ws, ExtractArgs ea) {
+    extern __shared__ __attribute__((aligned(16))) double dcs[];
+    const uint32_t task = xcd_task(cd.t_rows);
+    if (task == NOLSM_TASK_NONE) return;
+    const int s = task_slot(task), rq = task_a(task);
+    const SubMeta M = cd.meta[s];
+    const int n = M.n, np = M.np, bs = ea.bs, t = threadIdx.x;
+    const double mu = ((const WsHeader *)ws)->mu;
+    const bool ok = cd.ctl[s].status != NOLSM_MOL_NOT_SPD;
+    const double *Dc = ea.Dcols + (int64_t)bs * bs * M.sub_off;
+    double *Wc = ea.Wcols + (int64_t)bs * bs * M.sub_off;
+    for (int f = t; f < n * bs; f += 256) dcs[f] = Dc[f];
+    __syncthreads();
+    const int row = rq * 256 + t;
+    if (row >= n) return;
+    double acc[BSMAX];
+#pragma unroll
+    for (int j = 0; j < BSMAX; ++j) acc[j] = 0.0;
+    if (ok) {
+        const double *arow = (const double *)(ws + M.offK) + (int64_t)row * (np + 64);
+#pragma unroll 4
+        for (int k = 0; k < n; k += 2) {   // n = bs m is even for bs = 6
+            const double2 a = *(const double2 *)(arow + k);
+#pragma unroll
+            for (int j = 0; j < BSMAX; ++j)
+                if (j < bs) acc[j] += a.x * dcs[k * bs + j] + a.y * dcs[(k + 1) * bs + j];
+        }
+#pragma unroll
+        for (int j = 0; j < BSMAX; ++j)
+            if (j < bs) acc[j] += mu * dcs[row * bs + j];
+    }
+#pragma unroll
+    for (int j = 0; j < BSMAX; ++j)
+        if (j < bs) Wc[(int64_t)row * bs + j] = acc[j];
+}
+
+hipError_t launch_wcols(const ChunkDev &cd, char *ws, const ExtractArgs &ea, hipStream_t st) {
+    if (ea.bs & 1) return hipErrorInvalidValue;   // the row loop takes k in pairs
+    hipLaunchKernelGGL(k_wcols, dim3(cd.n_rows), dim3(256), (size_t)cd.max_np * ea.bs * 8, st, cd, ws, ea);
+    return hipGetLastError();
+}
+
 hipError_t launch_extract(const ChunkDev &cd, char *ws, const ExtractArgs &ea, hipStream_t st) {
     const size_t lds = (size_t)cd.max_np * ea.bs * 8 + (size_t)cd.max_m * 4 + 16;
     if (ea.prec == NOLSM_FP64)
@@ -298,7 +349,8 @@ hipError_t launch_assemble(const double *Dcols, double *Dval, const int32_t *sca
 hipError_t nolsm_finish_init() {
     const void *fns[] = {(const void *)k_extract<double>,          (const void *)k_extract<float>,
                          (const void *)k_skinny<double, double>,   (const void *)k_skinny<float, float>,
-                         (const void *)k_skinny<F16, float>,       (const void *)k_skinny<BF16, float>};
+                         (const void *)k_skinny<F16, float>,       (const void *)k_skinny<BF16, float>,
+                         (const void *)k_wcols};
     for (const void *f : fns)
         if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
             return hipErrorInvalidValue;

@@ -42,6 +42,7 @@ struct ExtractArgs {
     const double *Kval, *Sval;
     double *Dcols;         // [36 * sum_m] for bs = 6
     double *Dval;          // optional
+    double *Wcols;         // optional, Dcols layout: owned columns of T_J(W)
     void *stats;           // nolsm_mol_stats[nb]
     int32_t bs;
     int32_t prec;
@@ -49,6 +50,7 @@ struct ExtractArgs {
 };
 
 hipError_t launch_gather(const ChunkDev &cd, char *ws, const GatherArgs &ga, hipStream_t st);
+hipError_t launch_wcols(const ChunkDev &cd, char *ws, const ExtractArgs &ea, hipStream_t st);
 hipError_t launch_chol(const ChunkDev &cd, char *ws, hipStream_t st);
 hipError_t launch_subst(const ChunkDev &cd, char *ws, hipStream_t st);
 hipError_t launch_set_header(char *ws, double mu, hipStream_t st);

@@ -114,10 +114,21 @@ class Solver:
         self.stats = torch.zeros(self.nb * C.sizeof(L.MolStats), dtype=torch.uint8, device=self.device)
         self.mu = system.mu
         self.features = None
+        self.Wcols = None
+        self.W = None
 
     def set_opts(self, **kw):
         for k, v in kw.items():
             setattr(self.opts, k, v)
+
+    def want_w(self):
+        """Also compute the owned columns of the energy-weighted density
+        matrix T_J(W) = T_J(D) T_J(K) T_J(D) on every run (Sec. III-B.2)."""
+        torch = _torch()
+        n = self.sum_m * self.bs * self.bs
+        self.Wcols = torch.zeros(n, dtype=torch.float64, device=self.device)
+        self.W = torch.zeros(n, dtype=torch.float64, device=self.device)
+        self.opts.d_wcols = self.Wcols.data_ptr()
 
     def want_features(self):
         torch = _torch()
@@ -158,6 +169,12 @@ class Solver:
         L.check(L.lib().nolsm_assemble_D(self.plan.h, C.c_void_p(self.Dcols.data_ptr()),
                                          C.c_void_p(self.D.data_ptr()), C.c_void_p(st)))
 
+    def assemble_w(self, stream=None):
+        """Write W back into D's block-CSR pattern (same scatter as D)."""
+        st = _stream_ptr(stream, self.device)
+        L.check(L.lib().nolsm_assemble_D(self.plan.h, C.c_void_p(self.Wcols.data_ptr()),
+                                         C.c_void_p(self.W.data_ptr()), C.c_void_p(st)))
+
     def profile(self):
         """Phase times (ms) of the last run made with opts.profile = 1."""
         p = L.Profile()
@@ -168,9 +185,9 @@ class Solver:
         raw = self.stats.cpu().numpy()
         return raw.view(np.dtype(L.MOLSTATS_DTYPE))
 
-    def host_dcols(self):
-        """List of (n_J, bs) arrays, one per molecule."""
-        flat = self.Dcols.cpu().numpy()
+    def host_dcols(self, which="D"):
+        """List of (n_J, bs) arrays, one per molecule (which="W": T_J(W))."""
+        flat = (self.Wcols if which == "W" else self.Dcols).cpu().numpy()
         ex = self.plan.export()
         sp = ex["sub_ptr"]
         bs = self.bs

@@ -1,0 +1,97 @@
+"""Energy-weighted density matrix T_J(W) = T_J(D) T_J(K) T_J(D) on the GPU
+(owned columns, Sec. III-B.2) vs the CPU oracle, through the C ABI.
+
+The GPU forms (A_J + mu I) Dcols_J; the oracle forms the definition with the
+full T_J(D) = (I - X) T_J(S)^-1 / 2. For a sign converged to ||X^2 - I||_F <
+1e-10 the two differ by (A_J + mu I)(X^2 - I) Y_J / 4, i.e. ~1e-10 relative,
+so FP64 is held to 1e-9. Mixed precision: W inherits the Dcols error
+amplified by ||A_J + mu I||_2 / |eps| over the occupied eigenvalues eps, about
+1.3 for this generator (spectra within [-1.3, 1.3], occupied |eps| ~ 1), so
+the FP16 bound is the Dcols bound 5e-3 times 1.3, with a factor 1.5 margin:
+1e-2.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import nolsm as o
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def refw(config1):
+    return o.nolsm(config1, want_w=True, keep_x=True)
+
+
+def solve_w(system, prec):
+    from paper_2104_08245_amd import Solver
+    import torch
+    say(f"[gpu] W solve prec={prec} nmol={system.nmol}")
+    sv = Solver(system, prec=prec, device="cuda:0")
+    sv.want_w()
+    sv.run()
+    sv.assemble_w()
+    torch.cuda.synchronize()
+    return sv
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_w_fp64_matches_oracle_config1(torch, config1, refw):
+    sv = solve_w(config1, "fp64")
+    assert np.all(sv.host_stats()["status"] == 0)
+    wc = sv.host_dcols("W")
+    worst = max(rel(wc[J], refw.Wcols[J]) for J in range(config1.nmol))
+    say("W fp64 worst per-molecule rel-F", worst)
+    assert worst <= 1e-9
+    W = sv.W.cpu().numpy().reshape(-1, 6, 6)
+    assert rel(W, refw.W_val) <= 1e-9
+
+
+def test_w_kernel_is_the_exact_product(torch, config1, refw):
+    # isolates the W kernel: its output equals (A_J + mu I) Dcols_J formed on
+    # the CPU from the oracle's A_J and the GPU's own Dcols_J
+    sv = solve_w(config1, "fp16")
+    dc, wc = sv.host_dcols(), sv.host_dcols("W")
+    for J in range(0, config1.nmol, 5):
+        _, A = refw.xs[J]
+        ref = (A + config1.mu * np.eye(A.shape[0])) @ dc[J]
+        assert rel(wc[J], ref) <= 1e-10
+
+
+def test_w_fp16_within_stated_error(torch, config1, refw):
+    sv = solve_w(config1, "fp16")
+    wc = sv.host_dcols("W")
+    errs = [rel(wc[J], refw.Wcols[J]) for J in range(config1.nmol)]
+    say("W fp16 per-molecule rel-F max", max(errs), "mean", float(np.mean(errs)))
+    assert max(errs) <= 1e-2
+
+
+def test_w_not_spd_molecule_is_zero(torch, config1):
+    from paper_2104_08245_amd import Solver
+    import torch as T
+    sv = Solver(config1, prec="fp64", device="cuda:0", debug_poison_mol=3)
+    sv.want_w()
+    sv.run()
+    T.cuda.synchronize()
+    st = sv.host_stats()
+    assert st["status"][3] == 1
+    wc = sv.host_dcols("W")
+    assert np.all(wc[3] == 0.0)
+    assert np.all(np.isfinite(np.concatenate([w.ravel() for w in wc])))

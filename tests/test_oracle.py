@@ -214,7 +214,7 @@ def test_not_spd_and_noconv_flags(config1):
 # --------------------------------------------------------------------------
 
 def _mutant(kind):
-    def solve(KJ, SJ, p, bs, mu, tol=1e-10, max_iter=100, scale=None):
+    def solve(KJ, SJ, p, bs, mu, tol=1e-10, max_iter=100, scale=None, want_w=False):
         n = KJ.shape[0]
         Sinv = np.linalg.inv(SJ)
         A = Sinv @ KJ - (0.0 if kind == "drop_mu" else mu) * np.eye(n)
