@@ -178,6 +178,8 @@ def main():
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB "
                          "(reference for the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--want-w", action="store_true",
+                    help="also compute the energy-weighted density matrix columns each step")
     ap.add_argument("--bounds-eval", action="store_true",
                     help="instead of the throughput line: NS iteration counts with learned vs "
                          "Gershgorin bounds over the 10-frame trajectory (FP16)")
@@ -218,6 +220,8 @@ def main():
              "persistent": L.SCHED_PERSISTENT}[args.sched]
     dev = torch.device("cuda:0")
     sv = Solver(system, prec=args.prec, device=dev, ws_budget=int(args.ws_gb * (1 << 30)), sched=sched)
+    if args.want_w:
+        sv.want_w()
     info = sv.plan.info()
     log(f"plan: {info['nchunks']} chunks, workspace {sv.ws_bytes / 2**30:.1f} GiB")
     stream = torch.cuda.Stream(device=dev)
@@ -264,7 +268,7 @@ def main():
                 "kernel": "k_ns_lp" if args.prec in ("fp16", "bf16") else "k_ns64",
                 "launches": prof["n_ns_launches"],
                 "avg_launch_ms": round(prof["ms_ns"] / max(1, prof["n_ns_launches"]), 4)}
-    phases = {k: round(v, 2) for k, v in prof.items() if k.startswith("ms_")}
+    phases = {k: round(v, 2) for k, v in prof.items() if k.startswith("ms_") and (k != "ms_wmat" or args.want_w)}
     # composite bound: each phase's algorithmic work at its own peak (NS GEMMs
     # on the MFMA peak of the precision, finishing products at the FP32 peak,
     # the FP64 Cholesky + solves at the FP64 peak, the gather at 8 TB/s)
@@ -300,6 +304,12 @@ def main():
         "roofline": roofline,
         "composite_bound": composite,
     }
+    if args.want_w:
+        # T_J(W) columns: reads A_J (8 n^2 B) and Dcols_J, writes Wcols_J
+        wbytes = float((8.0 * n ** 2 + 96.0 * n).sum())
+        out["w_matrix"] = {"ms": round(prof["ms_wmat"], 3),
+                           "GB_per_s": round(wbytes / (prof["ms_wmat"] / 1e3) / 1e9, 1) if prof["ms_wmat"] > 0 else None,
+                           "bytes": wbytes}
     if cpu is not None:
         E = st["energy_KD"]
         dE = np.array([abs(E[J] - e) for J, e in cpu["E"].items()])

@@ -265,6 +265,7 @@ typedef struct {
     double ms_finish;        /* finishing products                             */
     double ms_extract;       /* extraction, traces, write-back                 */
     double ms_total;         /* first to last event                            */
+    double ms_wmat;          /* owned columns of T_J(W), when requested        */
 } nolsm_profile;
 int nolsm_profile_last(const nolsm_plan *plan, nolsm_profile *out);
 

@@ -62,7 +62,8 @@ class Profile(C.Structure):
     _fields_ = [("valid", C.c_int32), ("nchunks", C.c_int32), ("n_ns_launches", C.c_int32),
                 ("n_fin_launches", C.c_int32), ("ms_gather", C.c_double), ("ms_chol", C.c_double),
                 ("ms_subst", C.c_double), ("ms_bounds", C.c_double), ("ms_ns", C.c_double),
-                ("ms_finish", C.c_double), ("ms_extract", C.c_double), ("ms_total", C.c_double)]
+                ("ms_finish", C.c_double), ("ms_extract", C.c_double), ("ms_total", C.c_double),
+                ("ms_wmat", C.c_double)]
 
 
 EXPORTED = ["nolsm_default_opts", "nolsm_build_submatrices", "nolsm_plan_info", "nolsm_plan_export",

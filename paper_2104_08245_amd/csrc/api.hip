@@ -85,7 +85,7 @@ struct BatchArgs {
     void *dstats;
 };
 
-enum { PH_GATHER, PH_CHOL, PH_SUBST, PH_BOUNDS, PH_NS, PH_FINISH, PH_EXTRACT, PH_END };
+enum { PH_GATHER, PH_CHOL, PH_SUBST, PH_BOUNDS, PH_NS, PH_FINISH, PH_EXTRACT, PH_WMAT, PH_END };
 
 // HIP events recorded on the call's stream between phases
 struct PhaseEvents {
@@ -171,7 +171,10 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
         if ((e = launch_finish(cd, b.ws, fa, st)) != hipSuccess) return hip_fail(e, "finish launch");
         if (prof) prof->mark(PH_EXTRACT);
         if ((e = launch_extract(cd, b.ws, ea, st)) != hipSuccess) return hip_fail(e, "extract launch");
-        if (ea.Wcols && (e = launch_wcols(cd, b.ws, ea, st)) != hipSuccess) return hip_fail(e, "W launch");
+        if (ea.Wcols) {
+            if (prof) prof->mark(PH_WMAT);
+            if ((e = launch_wcols(cd, b.ws, ea, st)) != hipSuccess) return hip_fail(e, "W launch");
+        }
         if (prof) {
             prof->n_ns += 2 * o.max_iter;
             prof->n_fin += fa.nfinal == 0 ? 1 : (fa.nfinal == 1 ? 3 : 9);
@@ -229,7 +232,8 @@ extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const doub
         hipError_t e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "profile sync");
         nolsm_profile p = {};
-        double *slot[] = {&p.ms_gather, &p.ms_chol, &p.ms_subst, &p.ms_bounds, &p.ms_ns, &p.ms_finish, &p.ms_extract};
+        double *slot[] = {&p.ms_gather, &p.ms_chol,   &p.ms_subst,   &p.ms_bounds, &p.ms_ns,
+                          &p.ms_finish, &p.ms_extract, &p.ms_wmat};
         for (size_t i = 0; i + 1 < pe.ev.size(); ++i) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, pe.ev[i], pe.ev[i + 1]) == hipSuccess && pe.ph[i] < PH_END) *slot[pe.ph[i]] += ms;
