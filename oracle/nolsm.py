@@ -193,8 +193,34 @@ def newton_schulz_sign(A, c, tol=1e-10, max_iter=100):
     return X, max_iter, r, False
 
 
-def solve_submatrix(KJ, SJ, p, bs, mu, tol=1e-10, max_iter=100, scale=None, want_w=False):
+def coupled_ns_inverse(S, c, tol=1e-12, max_iter=100):
+    """Inverse of an SPD submatrix by the coupled Newton-Schulz iteration
+    (Eq. inv1-inv3): Y_0 = c S, Z_0 = I, V_k = Z_k Y_k,
+    Y_{k+1} = Y_k (3I - V_k) / 2, Z_{k+1} = (3I - V_k) Z_k / 2; Z_k tends to
+    (c S)^(-1/2), so S^-1 = c Z^2. Returns (S^-1, iterations, ||V - I||_F,
+    converged); stops at the first k with ||V_k - I||_F < tol. c must put the
+    spectrum of c S inside (0, 2) (here: c = 1 / max row sum of |S|)."""
+    n = S.shape[0]
+    I = np.eye(n)
+    Y = c * S
+    Z = I.copy()
+    r = np.inf
+    for k in range(max_iter):
+        V = Z @ Y
+        r = float(np.linalg.norm(V - I, "fro"))
+        if r < tol:
+            return c * (Z @ Z), k, r, True
+        T = 3.0 * I - V
+        Y, Z = 0.5 * (Y @ T), 0.5 * (T @ Z)
+    return c * (Z @ Z), max_iter, r, False
+
+
+def solve_submatrix(KJ, SJ, p, bs, mu, tol=1e-10, max_iter=100, scale=None, want_w=False,
+                    inverse="cholesky"):
     """Everything inside one submatrix, for the molecule at block position p.
+    inverse="coupled_ns" applies T_J(S)^-1 from the coupled Newton-Schulz
+    iteration (Eq. inv1-inv3, FP64, converged to 1e-12) instead of the
+    Cholesky factor; both give the same D up to rounding.
     With want_w, also the owned columns of the energy-weighted density
     matrix T_J(W) = T_J(D) T_J(K) T_J(D) (Sec. III-B.2), from the full
     T_J(D) = (I - X) T_J(S)^-1 / 2."""
@@ -205,9 +231,17 @@ def solve_submatrix(KJ, SJ, p, bs, mu, tol=1e-10, max_iter=100, scale=None, want
         return SubResult(NOT_SPD, None, None, None, 0, np.nan, np.nan, np.nan, np.nan)
     if not np.all(np.diag(L) > 0):
         return SubResult(NOT_SPD, None, None, None, 0, np.nan, np.nan, np.nan, np.nan)
-    def s_inv(B):
-        W = sla.solve_triangular(L, B, lower=True)
-        return sla.solve_triangular(L.T, W, lower=False)
+    if inverse == "coupled_ns":
+        Sinv, _, _, ok = coupled_ns_inverse(SJ, 1.0 / np.abs(SJ).sum(axis=1).max())
+        if not ok:
+            return SubResult(NOT_SPD, None, None, None, 0, np.nan, np.nan, np.nan, np.nan)
+
+        def s_inv(B):
+            return Sinv @ B
+    else:
+        def s_inv(B):
+            W = sla.solve_triangular(L, B, lower=True)
+            return sla.solve_triangular(L.T, W, lower=False)
     A = s_inv(KJ) - mu * np.eye(n)
     E = np.zeros((n, bs))
     E[p * bs:(p + 1) * bs, :] = np.eye(bs)
@@ -311,12 +345,12 @@ def submatrix(system, J, mu=None):
     return KJ, SJ, idx, int(self_pos[J])
 
 
-def solve_molecule(system, J, mu=None, tol=1e-10, max_iter=100, want_w=False):
+def solve_molecule(system, J, mu=None, tol=1e-10, max_iter=100, want_w=False, inverse="cholesky"):
     """Steps 3-8 and 10 for one column block J, without assembling D (for
     sampled checks on systems too large for the whole-batch oracle)."""
     mu = system.mu if mu is None else mu
     KJ, SJ, idx, p = submatrix(system, J)
-    return solve_submatrix(KJ, SJ, p, system.K.bs, mu, tol, max_iter, want_w=want_w)
+    return solve_submatrix(KJ, SJ, p, system.K.bs, mu, tol, max_iter, want_w=want_w, inverse=inverse)
 
 
 def dense(csr):
