@@ -178,6 +178,9 @@ def main():
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB "
                          "(reference for the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--inverse", default="cholesky", choices=["cholesky", "coupled_ns"],
+                    help="route to T_J(S)^-1: FP64 Cholesky, or the coupled Newton-Schulz "
+                         "iteration in the NS precision (16-bit only)")
     ap.add_argument("--want-w", action="store_true",
                     help="also compute the energy-weighted density matrix columns each step")
     ap.add_argument("--bounds-eval", action="store_true",
@@ -219,7 +222,9 @@ def main():
     sched = {"graph": L.SCHED_GRAPH, "stream": L.SCHED_STREAM, "bucket": L.SCHED_PER_BUCKET,
              "persistent": L.SCHED_PERSISTENT}[args.sched]
     dev = torch.device("cuda:0")
-    sv = Solver(system, prec=args.prec, device=dev, ws_budget=int(args.ws_gb * (1 << 30)), sched=sched)
+    inv = L.INV_COUPLED_NS if args.inverse == "coupled_ns" else L.INV_CHOLESKY
+    sv = Solver(system, prec=args.prec, device=dev, ws_budget=int(args.ws_gb * (1 << 30)), sched=sched,
+                inverse=inv)
     if args.want_w:
         sv.want_w()
     info = sv.plan.info()
@@ -252,9 +257,13 @@ def main():
     ok = st["status"] == 0
     it = st["iters"].astype(np.float64)
     gemm_flops = float(((2 * it + 1) * 2.0 * n ** 3)[ok].sum())
+    # coupled Newton-Schulz inverse: K+1 residual GEMMs, 2K updates, Z^2 and
+    # S^-1 K, each 2 n^3 like every counted GEMM
+    iti = st["iters_inv"].astype(np.float64)
+    inv_flops = float(((3 * iti + 3) * 2.0 * n ** 3)[ok].sum()) if args.inverse == "coupled_ns" else 0.0
     nfin = st["iters_fp32"].astype(np.float64)
     fin_flops = float((np.where(nfin == 2, 9, np.where(nfin == 1, 3, 1)) * 12.0 * n ** 2)[ok].sum())
-    tflops = (gemm_flops + fin_flops) / (ms / 1e3) / 1e12
+    tflops = (gemm_flops + inv_flops + fin_flops) / (ms / 1e3) / 1e12
 
     # one profiled step (direct launches, HIP events between phases)
     sv.set_opts(profile=1)
@@ -268,7 +277,10 @@ def main():
                 "kernel": "k_ns_lp" if args.prec in ("fp16", "bf16") else "k_ns64",
                 "launches": prof["n_ns_launches"],
                 "avg_launch_ms": round(prof["ms_ns"] / max(1, prof["n_ns_launches"]), 4)}
-    phases = {k: round(v, 2) for k, v in prof.items() if k.startswith("ms_") and (k != "ms_wmat" or args.want_w)}
+    phases = {k: round(v, 2) for k, v in prof.items()
+              if k.startswith("ms_") and (k != "ms_wmat" or args.want_w)
+              and (k != "ms_inverse" or args.inverse == "coupled_ns")
+              and (k not in ("ms_chol", "ms_subst") or args.inverse == "cholesky")}
     # composite bound: each phase's algorithmic work at its own peak (NS GEMMs
     # on the MFMA peak of the precision, finishing products at the FP32 peak,
     # the FP64 Cholesky + solves at the FP64 peak, the gather at 8 TB/s)
@@ -276,7 +288,11 @@ def main():
     setup_flops = float((n ** 3 / 3.0 + 2.0 * n ** 3 + 12.0 * n ** 2).sum())
     gather_bytes = float((576.0 * m ** 2 + 288.0 * m).sum())
     terms = {"ns": gemm_flops / (peak * 1e12), "finish": fin_flops / 157.3e12,
-             "setup_fp64": setup_flops / 78.6e12, "gather_scatter": gather_bytes / 8e12}
+             "gather_scatter": gather_bytes / 8e12}
+    if args.inverse == "coupled_ns":
+        terms["inverse"] = inv_flops / (peak * 1e12)
+    else:
+        terms["setup_fp64"] = setup_flops / 78.6e12
     t_bound = sum(terms.values())
     composite = {"ms": round(1e3 * t_bound, 2), "frac": round(1e3 * t_bound / ms, 4),
                  "terms_ms": {k: round(1e3 * v, 2) for k, v in terms.items()}}
@@ -296,9 +312,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD.get(args.config, str(args.config)), "molecules": system.nmol,
                    "submatrix_rows": [int(n.min()), int(round(n.mean())), int(n.max())],
-                   "precision": args.prec, "schedule": args.sched, "parallelism": "single GPU"},
+                   "precision": args.prec, "schedule": args.sched, "inverse": args.inverse,
+                   "parallelism": "single GPU"},
         "submatrices_per_s": round(system.nmol / (ms / 1e3), 1),
         "ns_iters": [int(it.min()), round(float(it.mean()), 2), int(it.max())],
+        **({"inverse_iters": [int(iti.min()), round(float(iti.mean()), 2), int(iti.max())]}
+           if args.inverse == "coupled_ns" else {}),
         "status_ok": int(ok.sum()),
         "phases_ms": phases,
         "roofline": roofline,

@@ -95,6 +95,25 @@ typedef enum {
                                       per-XCD device work queues of tiles      */
 } nolsm_sched;
 
+/* How T_J(S)^-1 is applied when forming A_J = T_J(S)^-1 T_J(K) - mu I and
+ * Y_J = T_J(S)^-1 E_cJ. */
+typedef enum {
+    NOLSM_INV_CHOLESKY = 0,        /* FP64 Cholesky factor and substitution      */
+    NOLSM_INV_COUPLED_NS = 1       /* FP16/BF16 only: the coupled Newton-Schulz
+                                      iteration of Eq. inv1-inv3 on the matrix
+                                      cores (FP32 accumulation): Y_0 = c S_J,
+                                      Z_0 = I, R_k = I - Z_k Y_k,
+                                      Y_{k+1} = Y_k + Y_k R_k / 2,
+                                      Z_{k+1} = Z_k + R_k Z_k / 2 (the paper's
+                                      update written with R_k, which keeps its
+                                      relative precision in 16 bits), stopped
+                                      like the sign iteration (stagnation of
+                                      ||R_k||_F); then S^-1 = c Z^2 and A_J =
+                                      S^-1 K_J - mu I by two more GEMMs, with
+                                      c = 1 / max row sum of |S_J|. A diverging
+                                      iteration marks the molecule NOT_SPD.   */
+} nolsm_inverse;
+
 typedef struct {
     int32_t prec;            /* nolsm_prec                                       */
     int32_t n_final_fp32;    /* FP16/BF16: FP32 finishing iterations, 0..2
@@ -131,6 +150,9 @@ typedef struct {
                                 P = (I - sign A_J)/2 a projector commuting with
                                 A_J. Zero for NOT_SPD molecules. Null: skipped.
                                 Assemble W with nolsm_assemble_D.                */
+    int32_t inverse;         /* nolsm_inverse (default NOLSM_INV_CHOLESKY)       */
+    int32_t inv_max_iter;    /* coupled Newton-Schulz iteration slots, 2..128
+                                (default 40; used by configure)                  */
 } nolsm_solve_opts;
 
 /* Fills *o with the defaults above for precision `prec`. */
@@ -146,6 +168,9 @@ typedef struct {
     double resid;            /* ||X_k^2 - I||_F of the returned iterate           */
     double trace_SD;         /* N_J = sum_c (S_J Dcols_J)[cJ_c, c]                */
     double energy_KD;        /* E_J = sum_c (K_J Dcols_J)[cJ_c, c]                */
+    int32_t iters_inv;       /* coupled Newton-Schulz inverse updates (0 with the
+                                Cholesky route)                                   */
+    int32_t reserved_;
 } nolsm_mol_stats;
 
 typedef struct nolsm_plan nolsm_plan;
@@ -266,6 +291,8 @@ typedef struct {
     double ms_extract;       /* extraction, traces, write-back                 */
     double ms_total;         /* first to last event                            */
     double ms_wmat;          /* owned columns of T_J(W), when requested        */
+    double ms_inverse;       /* coupled Newton-Schulz route: everything from
+                                the scaled S_J to A_J (replaces chol + subst)  */
 } nolsm_profile;
 int nolsm_profile_last(const nolsm_plan *plan, nolsm_profile *out);
 

@@ -15,6 +15,7 @@ FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
 BOUNDS_GERSHGORIN, BOUNDS_LEARNED = 0, 1
 SCHED_GRAPH, SCHED_STREAM, SCHED_PER_BUCKET, SCHED_PERSISTENT = 0, 1, 2, 3
+INV_CHOLESKY, INV_COUPLED_NS = 0, 1
 MLP_NFEAT = 12
 MLP_NPARAM = 5122
 
@@ -38,17 +39,20 @@ class SolveOpts(C.Structure):
                 ("mlp_safety", C.c_float), ("sched", C.c_int32), ("sync_errors", C.c_int32),
                 ("d_features", C.c_void_p), ("debug_scale_mult", C.c_double),
                 ("debug_poison_mol", C.c_int32), ("profile", C.c_int32),
-                ("ns_small_tile_mask", C.c_uint64), ("d_wcols", C.c_void_p)]
+                ("ns_small_tile_mask", C.c_uint64), ("d_wcols", C.c_void_p),
+                ("inverse", C.c_int32), ("inv_max_iter", C.c_int32)]
 
 
 class MolStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("iters_fp32", C.c_int32), ("fallback", C.c_int32),
                 ("status", C.c_int32), ("scale", C.c_double), ("resid", C.c_double),
-                ("trace_SD", C.c_double), ("energy_KD", C.c_double)]
+                ("trace_SD", C.c_double), ("energy_KD", C.c_double),
+                ("iters_inv", C.c_int32), ("reserved_", C.c_int32)]
 
 
 MOLSTATS_DTYPE = [("iters", "<i4"), ("iters_fp32", "<i4"), ("fallback", "<i4"), ("status", "<i4"),
-                  ("scale", "<f8"), ("resid", "<f8"), ("trace_SD", "<f8"), ("energy_KD", "<f8")]
+                  ("scale", "<f8"), ("resid", "<f8"), ("trace_SD", "<f8"), ("energy_KD", "<f8"),
+                  ("iters_inv", "<i4"), ("reserved_", "<i4")]
 
 
 class PlanSizes(C.Structure):
@@ -63,7 +67,7 @@ class Profile(C.Structure):
                 ("n_fin_launches", C.c_int32), ("ms_gather", C.c_double), ("ms_chol", C.c_double),
                 ("ms_subst", C.c_double), ("ms_bounds", C.c_double), ("ms_ns", C.c_double),
                 ("ms_finish", C.c_double), ("ms_extract", C.c_double), ("ms_total", C.c_double),
-                ("ms_wmat", C.c_double)]
+                ("ms_wmat", C.c_double), ("ms_inverse", C.c_double)]
 
 
 EXPORTED = ["nolsm_default_opts", "nolsm_build_submatrices", "nolsm_plan_info", "nolsm_plan_export",

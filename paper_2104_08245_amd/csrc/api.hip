@@ -62,6 +62,7 @@ static ChunkDev chunk_dev(const nolsm_plan *pl, const HostChunk &ch, char *ws) {
     cd.t_ns64 = (const uint32_t *)(base + ch.o_ns64);
     cd.t_rows = (const uint32_t *)(base + ch.o_rows);
     cd.ctl = (SubCtl *)(ws + ch.off_ctl);
+    cd.ictl = ch.off_ictl ? (InvCtl *)(ws + ch.off_ictl) : nullptr;
     cd.queues = (int32_t *)(ws + ch.off_q);
     cd.nqueue = pl->max_iter * 2 * 2 * 8;
     cd.nsub = (int32_t)ch.meta.size();
@@ -85,7 +86,7 @@ struct BatchArgs {
     void *dstats;
 };
 
-enum { PH_GATHER, PH_CHOL, PH_SUBST, PH_BOUNDS, PH_NS, PH_FINISH, PH_EXTRACT, PH_WMAT, PH_END };
+enum { PH_GATHER, PH_CHOL, PH_SUBST, PH_BOUNDS, PH_NS, PH_FINISH, PH_EXTRACT, PH_WMAT, PH_INV, PH_END };
 
 // HIP events recorded on the call's stream between phases
 struct PhaseEvents {
@@ -135,6 +136,11 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
     na.rmax = o.switch_rmax > 0 ? o.switch_rmax : 0.5;
     na.persistent = o.sched == NOLSM_SCHED_PERSISTENT;
     na.pgrid = pl->pgrid;
+    InvArgs ia;
+    ia.prec = o.prec;
+    ia.max_iter = o.inv_max_iter;
+    ia.theta = na.theta;
+    ia.rmax = na.rmax;
     FinishArgs fa;
     fa.prec = o.prec;
     fa.nfinal = (o.prec == NOLSM_FP16 || o.prec == NOLSM_BF16) ? o.n_final_fp32 : 0;
@@ -156,10 +162,15 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
         hipError_t e;
         if (prof) prof->mark(PH_GATHER);
         if ((e = launch_gather(cd, b.ws, ga, st)) != hipSuccess) return hip_fail(e, "gather launch");
-        if (prof) prof->mark(PH_CHOL);
-        if ((e = launch_chol(cd, b.ws, st)) != hipSuccess) return hip_fail(e, "Cholesky launch");
-        if (prof) prof->mark(PH_SUBST);
-        if ((e = launch_subst(cd, b.ws, st)) != hipSuccess) return hip_fail(e, "substitution launch");
+        if (o.inverse == NOLSM_INV_COUPLED_NS) {
+            if (prof) prof->mark(PH_INV);
+            if ((e = launch_inverse(cd, b.ws, ia, st)) != hipSuccess) return hip_fail(e, "inverse launch");
+        } else {
+            if (prof) prof->mark(PH_CHOL);
+            if ((e = launch_chol(cd, b.ws, st)) != hipSuccess) return hip_fail(e, "Cholesky launch");
+            if (prof) prof->mark(PH_SUBST);
+            if ((e = launch_subst(cd, b.ws, st)) != hipSuccess) return hip_fail(e, "substitution launch");
+        }
         if (prof) prof->mark(PH_BOUNDS);
         if ((e = launch_bounds(cd, b.ws, ba, o.prec, st)) != hipSuccess) return hip_fail(e, "bounds launch");
         if (prof) prof->mark(PH_NS);
@@ -196,7 +207,8 @@ extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const doub
         return NOLSM_E_ARG;
     }
     if (!pl->bound) { nolsm_set_last_error("sign_batch: plan not bound"); return NOLSM_E_STATE; }
-    if (opts->prec != pl->prec || opts->max_iter != pl->max_iter ||
+    if (opts->prec != pl->prec || opts->max_iter != pl->max_iter || opts->inverse != pl->inverse ||
+        (pl->inverse == NOLSM_INV_COUPLED_NS && opts->inv_max_iter != pl->inv_max_iter) ||
         ((opts->sched == NOLSM_SCHED_PER_BUCKET) != (pl->sched == NOLSM_SCHED_PER_BUCKET))) {
         nolsm_set_last_error("sign_batch: options differ from the configured ones");
         return NOLSM_E_STATE;
@@ -232,8 +244,8 @@ extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const doub
         hipError_t e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "profile sync");
         nolsm_profile p = {};
-        double *slot[] = {&p.ms_gather, &p.ms_chol,   &p.ms_subst,   &p.ms_bounds, &p.ms_ns,
-                          &p.ms_finish, &p.ms_extract, &p.ms_wmat};
+        double *slot[] = {&p.ms_gather, &p.ms_chol,   &p.ms_subst, &p.ms_bounds,  &p.ms_ns,
+                          &p.ms_finish, &p.ms_extract, &p.ms_wmat, &p.ms_inverse};
         for (size_t i = 0; i + 1 < pe.ev.size(); ++i) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, pe.ev[i], pe.ev[i + 1]) == hipSuccess && pe.ph[i] < PH_END) *slot[pe.ph[i]] += ms;

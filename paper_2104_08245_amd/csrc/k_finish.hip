@@ -144,7 +144,9 @@ hipError_t launch_finish(const ChunkDev &cd, char *ws, const FinishArgs &fa, hip
 struct MolStatsDev {
     int32_t iters, iters_fp32, fallback, status;
     double scale, resid, trace_SD, energy_KD;
+    int32_t iters_inv, reserved_;
 };
+static_assert(sizeof(MolStatsDev) == sizeof(nolsm_mol_stats), "stats layout");
 
 template <typename TV>
 __global__ __launch_bounds__(256) void k_extract(ChunkDev cd, char *ws, ExtractArgs ea) {
@@ -223,6 +225,8 @@ __global__ __launch_bounds__(256) void k_extract(ChunkDev cd, char *ws, ExtractA
         st->resid = ctl->resid;
         st->trace_SD = ok ? tr[0] : 0.0;
         st->energy_KD = ok ? tr[1] : 0.0;
+        st->iters_inv = cd.ictl ? cd.ictl[s].iters : 0;
+        st->reserved_ = 0;
     }
 }
 

@@ -32,6 +32,14 @@ struct NsArgs {
     int32_t pgrid;         // workgroups of a persistent launch
 };
 
+// Coupled Newton-Schulz inverse (Eq. inv1-inv3), stop rule as for the sign
+// iteration in 16 bits: stagnation r_k > theta r_{k-1} with r_k < rmax.
+struct InvArgs {
+    int32_t prec;          // NOLSM_FP16 or NOLSM_BF16
+    int32_t max_iter;      // iteration slots
+    double theta, rmax;
+};
+
 struct FinishArgs {
     int32_t prec;
     int32_t nfinal;        // 0, 1, 2 column-restricted finishing iterations
@@ -51,6 +59,7 @@ struct ExtractArgs {
 
 hipError_t launch_gather(const ChunkDev &cd, char *ws, const GatherArgs &ga, hipStream_t st);
 hipError_t launch_wcols(const ChunkDev &cd, char *ws, const ExtractArgs &ea, hipStream_t st);
+hipError_t launch_inverse(const ChunkDev &cd, char *ws, const InvArgs &ia, hipStream_t st);
 hipError_t launch_chol(const ChunkDev &cd, char *ws, hipStream_t st);
 hipError_t launch_subst(const ChunkDev &cd, char *ws, hipStream_t st);
 hipError_t launch_set_header(char *ws, double mu, hipStream_t st);

@@ -31,7 +31,10 @@ struct SubMeta {
     int64_t offX1;    // ldx*ldx elements of the NS precision: X buffer 1
     int64_t offB;     // ldx*ldx elements: R = I - X^2
     int64_t offVec;   // NOLSM_NVEC * np * 6 floats/doubles: finishing vectors
-    int64_t offRes;   // max_iter * ntile_ns doubles: residual partials
+    int64_t offRes;   // max(max_iter, inv_max_iter) * ntile_ns doubles: residual partials
+    // coupled Newton-Schulz inverse only (0 otherwise): ldx*ldx elements each
+    int64_t offY0, offY1;   // Y_k ping-pong; after convergence S^-1 and K in 16 bits
+    int64_t offZ0, offZ1;   // Z_k ping-pong
 };
 
 // Per-slot control state, written by kernels only.
@@ -45,6 +48,15 @@ struct SubCtl {
     double scale;       // c_J actually used
     double scale_g;     // Gershgorin scale 1/rho_G
     double resid;       // residual of the returned iterate
+    double rhist[NOLSM_MAX_ITER_CAP];
+};
+
+// Per-slot state of the coupled Newton-Schulz inverse, written by kernels only.
+struct InvCtl {
+    int32_t done;       // iteration finished (or failed)
+    int32_t iters;      // index K of the returned Z_K
+    int32_t pad_[2];
+    double scale;       // c = 1 / max row sum of |S_J|
     double rhist[NOLSM_MAX_ITER_CAP];
 };
 
@@ -72,6 +84,7 @@ struct ChunkDev {
     const uint32_t *t_ns64;    // FP16/BF16 slots that use 64x64 tiles
     const uint32_t *t_rows;    // (slot, 256-row block) for the skinny products
     SubCtl *ctl;               // in the workspace
+    InvCtl *ictl;              // in the workspace (coupled inverse), else null
     int32_t *queues;           // persistent launches: [max_iter][2][2][8] counters
     int32_t nqueue;            // number of counters
     int32_t nsub, n_subst, n_conv, n_ns, n_ns64, n_rows, max_m, max_np;

@@ -36,7 +36,7 @@ int nolsm_elem_for(int32_t prec) {
     }
 }
 
-size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_iter) {
+size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_iter, int32_t inverse) {
     const size_t n = (size_t)np;
     const size_t P = n / NOLSM_TILE;
     const size_t nt = (n + ns_tile - 1) / ns_tile;
@@ -51,6 +51,7 @@ size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_i
     b += align256(ldx * ldx * (size_t)elem);  // R
     b += align256((size_t)NOLSM_NVEC * n * 6 * 8);  // finishing vectors
     b += align256((size_t)max_iter * nt * nt * 8);  // residual partials
+    if (inverse == NOLSM_INV_COUPLED_NS) b += 4 * align256(ldx * ldx * (size_t)elem);  // Y, Z ping-pong
     return b;
 }
 
@@ -171,6 +172,8 @@ extern "C" void nolsm_default_opts(nolsm_solve_opts *o, int32_t prec) {
     o->sched = NOLSM_SCHED_GRAPH;
     o->debug_poison_mol = -1;
     o->ns_small_tile_mask = 0x5;   // 64 and 192 rows: 128-row tiles would waste work
+    o->inverse = NOLSM_INV_CHOLESKY;
+    o->inv_max_iter = 40;
 }
 
 extern "C" int nolsm_plan_info(const nolsm_plan *p, nolsm_plan_sizes *o) {
@@ -227,6 +230,17 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
     if (opts->prec < NOLSM_FP64 || opts->prec > NOLSM_BF16) { nolsm_set_last_error("bad precision"); return NOLSM_E_ARG; }
     if (opts->max_iter < 2 || opts->max_iter > NOLSM_MAX_ITER_CAP) { nolsm_set_last_error("max_iter must be 2..128"); return NOLSM_E_ARG; }
     if (opts->sched < NOLSM_SCHED_GRAPH || opts->sched > NOLSM_SCHED_PERSISTENT) { nolsm_set_last_error("bad schedule"); return NOLSM_E_ARG; }
+    if (opts->inverse != NOLSM_INV_CHOLESKY && opts->inverse != NOLSM_INV_COUPLED_NS) { nolsm_set_last_error("bad inverse"); return NOLSM_E_ARG; }
+    if (opts->inverse == NOLSM_INV_COUPLED_NS) {
+        if (opts->prec != NOLSM_FP16 && opts->prec != NOLSM_BF16) {
+            nolsm_set_last_error("the coupled Newton-Schulz inverse runs in FP16/BF16 only");
+            return NOLSM_E_ARG;
+        }
+        if (opts->inv_max_iter < 2 || opts->inv_max_iter > NOLSM_MAX_ITER_CAP) {
+            nolsm_set_last_error("inv_max_iter must be 2..128");
+            return NOLSM_E_ARG;
+        }
+    }
     try {
         pl->configured = false;
         pl->bound = false;
@@ -234,6 +248,10 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
         pl->prec = opts->prec;
         pl->sched = opts->sched;
         pl->max_iter = opts->max_iter;
+        pl->inverse = opts->inverse;
+        pl->inv_max_iter = opts->inverse == NOLSM_INV_COUPLED_NS ? opts->inv_max_iter : 0;
+        // residual partial slots serve both iterations, one after the other
+        const int32_t res_slots = std::max(pl->max_iter, pl->inv_max_iter);
         pl->elem = nolsm_elem_for(opts->prec);
         const int32_t nb = pl->nb, bs = pl->bs;
         auto np_of = [&](int32_t J) {
@@ -250,14 +268,15 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
         std::vector<int32_t> order(nb);
         for (int32_t J = 0; J < nb; ++J) order[J] = J;
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return np_of(a) > np_of(b); });
-        const size_t ctl_bytes = align256(sizeof(SubCtl));
+        const size_t ctl_bytes =
+            align256(sizeof(SubCtl)) + (pl->inverse == NOLSM_INV_COUPLED_NS ? align256(sizeof(InvCtl)) : 0);
         // queue counters of the persistent launches, per chunk
         const size_t nqueue = (size_t)pl->max_iter * 2 * 2 * 8;
         const size_t qbytes = align256(nqueue * sizeof(int32_t));
         pl->ws_min = 0;
         pl->ws_full = 0;
         for (int32_t J = 0; J < nb; ++J) {
-            const size_t sb = nolsm_slot_bytes(np_of(J), tile_of(J), pl->elem, pl->max_iter) + ctl_bytes;
+            const size_t sb = nolsm_slot_bytes(np_of(J), tile_of(J), pl->elem, res_slots, pl->inverse) + ctl_bytes;
             pl->ws_min = std::max(pl->ws_min, sb);
             pl->ws_full += sb;
         }
@@ -278,16 +297,22 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
             while (i < order.size() && js.size() < 65535) {
                 const int32_t J = order[i];
                 if (pl->sched == NOLSM_SCHED_PER_BUCKET && np_of(J) != bucket) break;
-                const size_t sb = nolsm_slot_bytes(np_of(J), tile_of(J), pl->elem, pl->max_iter) + ctl_bytes;
+                const size_t sb = nolsm_slot_bytes(np_of(J), tile_of(J), pl->elem, res_slots, pl->inverse) + ctl_bytes;
                 if (used + sb + 256 + qbytes > ws_bytes) break;
                 used += sb;
                 js.push_back(J);
                 ++i;
             }
             // layout: SubCtl array first, then the slots
-            // layout: workspace header, SubCtl array, queue counters, slots
+            // layout: workspace header, SubCtl array, InvCtl array (coupled
+            // inverse only), queue counters, slots
             ch.off_ctl = NOLSM_WS_HEADER;
+            ch.off_ictl = 0;
             ch.off_q = NOLSM_WS_HEADER + align256(js.size() * sizeof(SubCtl));
+            if (pl->inverse == NOLSM_INV_COUPLED_NS) {
+                ch.off_ictl = ch.off_q;
+                ch.off_q += align256(js.size() * sizeof(InvCtl));
+            }
             size_t off = ch.off_q + qbytes;
             for (size_t s = 0; s < js.size(); ++s) {
                 const int32_t J = js[s];
@@ -314,7 +339,13 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
                 m.offX1 = (int64_t)off; off += align256(ldx * ldx * pl->elem);
                 m.offB = (int64_t)off; off += align256(ldx * ldx * pl->elem);
                 m.offVec = (int64_t)off; off += align256((size_t)NOLSM_NVEC * n * 6 * 8);
-                m.offRes = (int64_t)off; off += align256((size_t)pl->max_iter * m.ntile_ns * 8);
+                m.offRes = (int64_t)off; off += align256((size_t)res_slots * m.ntile_ns * 8);
+                if (pl->inverse == NOLSM_INV_COUPLED_NS) {
+                    m.offY0 = (int64_t)off; off += align256(ldx * ldx * pl->elem);
+                    m.offY1 = (int64_t)off; off += align256(ldx * ldx * pl->elem);
+                    m.offZ0 = (int64_t)off; off += align256(ldx * ldx * pl->elem);
+                    m.offZ1 = (int64_t)off; off += align256(ldx * ldx * pl->elem);
+                }
                 ch.meta.push_back(m);
                 ch.max_m = std::max(ch.max_m, m.m);
                 ch.max_np = std::max(ch.max_np, m.np);

@@ -16,6 +16,7 @@ struct HostChunk {
     size_t n_ns_real = 0, n_ns64_real = 0;   // task counts before padding
     size_t ws_used = 0;       // bytes of the workspace this chunk uses
     size_t off_ctl = 0;       // workspace offset of the SubCtl array
+    size_t off_ictl = 0;      // workspace offset of the InvCtl array (0: none)
     size_t off_q = 0;         // workspace offset of the queue counters
     // metadata image offsets (bytes from d_meta)
     size_t o_meta = 0, o_subst = 0, o_conv = 0, o_ns = 0, o_ns64 = 0, o_rows = 0;
@@ -32,6 +33,7 @@ struct nolsm_plan {
     bool configured = false;
     bool bound = false;
     int32_t prec = -1, sched = -1, max_iter = 0, ns_tile = 0, elem = 0;
+    int32_t inverse = 0, inv_max_iter = 0;
     size_t ws_bytes = 0, ws_min = 0, ws_full = 0;
     std::vector<HostChunk> chunks;
     std::vector<char> image;              // metadata image uploaded by bind
@@ -50,7 +52,7 @@ struct nolsm_plan {
 };
 
 // Internal helpers implemented in plan.cpp
-size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_iter);
+size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_iter, int32_t inverse);
 int nolsm_ns_tile_for(int32_t prec, int32_t np, uint64_t small_mask);
 int nolsm_elem_for(int32_t prec);
 void nolsm_set_last_error(const std::string &s);

@@ -146,7 +146,9 @@ def test_bad_options_rejected(L, config1):
     from paper_2104_08245_amd import Plan, NolsmError
     s = config1
     p = Plan(s.K.nb, s.K.bs, s.K.row_ptr, s.K.col_idx)
-    for kw in (dict(prec=7), dict(max_iter=1), dict(max_iter=500), dict(sched=9)):
+    for kw in (dict(prec=7), dict(max_iter=1), dict(max_iter=500), dict(sched=9), dict(inverse=5),
+               dict(inverse=L.INV_COUPLED_NS),                       # FP64: 16-bit route only
+               dict(prec=L.PREC["fp16"], inverse=L.INV_COUPLED_NS, inv_max_iter=1)):
         opts = L.default_opts("fp64")
         for k, v in kw.items():
             setattr(opts, k, v)
