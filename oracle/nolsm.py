@@ -325,6 +325,70 @@ def nolsm(system, mu=None, tol=1e-10, max_iter=100, molecules=None, keep_x=False
     return res
 
 
+def nolsm_groups(system, groups, mu=None, tol=1e-10, max_iter=100):
+    """NOLSM on combined submatrices (Sec. III-B, submatrix combination):
+    `groups` = (grp_ptr, grp_blk, own_ptr, own_J) as from
+    oracle.combine.combine_groups. Each group's submatrix T_g is built on
+    its row blocks R_g; one sign iteration serves every molecule J it owns,
+    whose columns are T_g(D)[:, cJ] = (Y_J - X Y_J) / 2 with
+    Y_J = T_g(S)^-1 E_cJ. Only the rows N(J) are written back, so D keeps
+    the merged pattern of K and S. Returns a BatchResult (Dcols per
+    molecule on N(J); iters/resid/scale repeated for every owned molecule)."""
+    K, S = system.K, system.S
+    nb, bs = K.nb, K.bs
+    mu = system.mu if mu is None else mu
+    plan = plan_arrays(nb, K.row_ptr, K.col_idx, S.row_ptr, S.col_idx)
+    sub_ptr, sub_blk = plan["sub_ptr"], plan["sub_blk"]
+    grp_ptr, grp_blk, own_ptr, own_J = groups
+    Dcols = [None] * nb
+    D_val = np.zeros((plan["D_col_idx"].shape[0], bs, bs))
+    status = np.full(nb, -1, dtype=np.int64)
+    iters = np.zeros(nb, dtype=np.int64)
+    resid = np.full(nb, np.nan)
+    scale = np.full(nb, np.nan)
+    N = np.full(nb, np.nan)
+    E = np.full(nb, np.nan)
+    for g in range(len(grp_ptr) - 1):
+        rows = grp_blk[grp_ptr[g]:grp_ptr[g + 1]]
+        where = {int(b): a for a, b in enumerate(rows)}
+        KG = gather(rows, bs, K.row_ptr, K.col_idx, K.val)
+        SG = gather(rows, bs, S.row_ptr, S.col_idx, S.val)
+        n = KG.shape[0]
+        owned = own_J[own_ptr[g]:own_ptr[g + 1]]
+        try:
+            L = np.linalg.cholesky(SG)
+            ok = bool(np.all(np.diag(L) > 0))
+        except np.linalg.LinAlgError:
+            ok = False
+        if not ok:
+            for J in owned:
+                status[J] = NOT_SPD
+            continue
+        def s_inv(B):
+            W = sla.solve_triangular(L, B, lower=True)
+            return sla.solve_triangular(L.T, W, lower=False)
+        A = s_inv(KG) - mu * np.eye(n)
+        c = 1.0 / np.abs(A).sum(axis=1).max()
+        X, it, r, conv = newton_schulz_sign(A, c, tol, max_iter)
+        for J in owned:
+            J = int(J)
+            q = where[J]
+            Ec = np.zeros((n, bs))
+            Ec[q * bs:(q + 1) * bs, :] = np.eye(bs)
+            Y = s_inv(Ec)
+            Dfull = 0.5 * (Y - X @ Y)
+            idx = sub_blk[sub_ptr[J]:sub_ptr[J + 1]]
+            sel = np.concatenate([np.arange(where[int(I)] * bs, where[int(I)] * bs + bs) for I in idx])
+            Dcols[J] = Dfull[sel, :]
+            qrows = slice(q * bs, (q + 1) * bs)
+            N[J] = float(np.trace(SG[qrows, :] @ Dfull))
+            E[J] = float(np.trace(KG[qrows, :] @ Dfull))
+            status[J], iters[J], resid[J], scale[J] = (OK if conv else NOCONV), it, r, c
+            for a in range(len(idx)):
+                D_val[plan["scatter_pos"][sub_ptr[J] + a]] = Dcols[J][a * bs:(a + 1) * bs, :]
+    return BatchResult(plan, Dcols, D_val, status, iters, resid, scale, N, E)
+
+
 def neighbour_lists(system):
     """N(J) lists and p_J of a system, merged once and cached on it."""
     cache = getattr(system, "_oracle_lists", None)
