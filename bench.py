@@ -183,6 +183,8 @@ def main():
                          "iteration in the NS precision (16-bit only)")
     ap.add_argument("--want-w", action="store_true",
                     help="also compute the energy-weighted density matrix columns each step")
+    ap.add_argument("--combine", action="store_true",
+                    help="combine submatrices (cubic criterion) before solving")
     ap.add_argument("--bounds-eval", action="store_true",
                     help="instead of the throughput line: NS iteration counts with learned vs "
                          "Gershgorin bounds over the 10-frame trajectory (FP16)")
@@ -224,11 +226,12 @@ def main():
     dev = torch.device("cuda:0")
     inv = L.INV_COUPLED_NS if args.inverse == "coupled_ns" else L.INV_CHOLESKY
     sv = Solver(system, prec=args.prec, device=dev, ws_budget=int(args.ws_gb * (1 << 30)), sched=sched,
-                inverse=inv)
+                inverse=inv, combine=args.combine)
     if args.want_w:
         sv.want_w()
     info = sv.plan.info()
-    log(f"plan: {info['nchunks']} chunks, workspace {sv.ws_bytes / 2**30:.1f} GiB")
+    log(f"plan: {info['nchunks']} chunks, {info['ngroups']} submatrices, "
+        f"workspace {sv.ws_bytes / 2**30:.1f} GiB")
     stream = torch.cuda.Stream(device=dev)
     if args.copy_calib_mib:
         src = torch.ones(args.copy_calib_mib << 18, dtype=torch.float32, device=dev)
@@ -252,17 +255,22 @@ def main():
     log(f"timed {args.steps} steps: {ms:.1f} ms/step")
 
     st = sv.host_stats()
-    ex = sv.plan.export()
-    n = 6 * np.diff(ex["sub_ptr"]).astype(np.float64)
-    ok = st["status"] == 0
-    it = st["iters"].astype(np.float64)
+    # per solved submatrix (one per molecule, or one per group when combined):
+    # its rows n, and the iteration counts of its first owned molecule
+    grp_ptr, _, own_ptr, own_J = sv.plan.groups()
+    n = 6 * np.diff(grp_ptr).astype(np.float64)
+    first = own_J[own_ptr[:-1]]
+    ok = np.array([np.all(st["status"][own_J[own_ptr[g]:own_ptr[g + 1]]] == 0) for g in range(len(n))])
+    it = st["iters"][first].astype(np.float64)
     gemm_flops = float(((2 * it + 1) * 2.0 * n ** 3)[ok].sum())
     # coupled Newton-Schulz inverse: K+1 residual GEMMs, 2K updates, Z^2 and
     # S^-1 K, each 2 n^3 like every counted GEMM
-    iti = st["iters_inv"].astype(np.float64)
+    iti = st["iters_inv"][first].astype(np.float64)
     inv_flops = float(((3 * iti + 3) * 2.0 * n ** 3)[ok].sum()) if args.inverse == "coupled_ns" else 0.0
-    nfin = st["iters_fp32"].astype(np.float64)
-    fin_flops = float((np.where(nfin == 2, 9, np.where(nfin == 1, 3, 1)) * 12.0 * n ** 2)[ok].sum())
+    # finishing: skinny products on the bs columns of every owned molecule
+    nfin = st["iters_fp32"][first].astype(np.float64)
+    nown = np.diff(own_ptr).astype(np.float64)
+    fin_flops = float((nown * np.where(nfin == 2, 9, np.where(nfin == 1, 3, 1)) * 12.0 * n ** 2)[ok].sum())
     tflops = (gemm_flops + inv_flops + fin_flops) / (ms / 1e3) / 1e12
 
     # one profiled step (direct launches, HIP events between phases)
@@ -313,19 +321,21 @@ def main():
         "config": {"workload": WORKLOAD.get(args.config, str(args.config)), "molecules": system.nmol,
                    "submatrix_rows": [int(n.min()), int(round(n.mean())), int(n.max())],
                    "precision": args.prec, "schedule": args.sched, "inverse": args.inverse,
+                   "combined": bool(args.combine), "submatrices": int(len(n)),
                    "parallelism": "single GPU"},
         "submatrices_per_s": round(system.nmol / (ms / 1e3), 1),
         "ns_iters": [int(it.min()), round(float(it.mean()), 2), int(it.max())],
         **({"inverse_iters": [int(iti.min()), round(float(iti.mean()), 2), int(iti.max())]}
            if args.inverse == "coupled_ns" else {}),
-        "status_ok": int(ok.sum()),
+        "status_ok": int((st["status"] == 0).sum()),
         "phases_ms": phases,
         "roofline": roofline,
         "composite_bound": composite,
     }
     if args.want_w:
-        # T_J(W) columns: reads A_J (8 n^2 B) and Dcols_J, writes Wcols_J
-        wbytes = float((8.0 * n ** 2 + 96.0 * n).sum())
+        # T_J(W) columns: reads A_J (8 n^2 B) and Dcols_J, writes Wcols_J,
+        # once per owned molecule
+        wbytes = float((nown * (8.0 * n ** 2 + 96.0 * n)).sum())
         out["w_matrix"] = {"ms": round(prof["ms_wmat"], 3),
                            "GB_per_s": round(wbytes / (prof["ms_wmat"] / 1e3) / 1e9, 1) if prof["ms_wmat"] > 0 else None,
                            "bytes": wbytes}

@@ -184,16 +184,38 @@ typedef struct {
     size_t meta_bytes;       /* device metadata bytes needed by nolsm_plan_bind   */
     size_t ws_min_bytes;     /* smallest workspace that holds the largest J       */
     size_t ws_full_bytes;    /* workspace holding the whole batch in one chunk    */
+    int32_t ngroups;         /* submatrices after combination (= nb without it)   */
+    int32_t g_m_max;         /* blocks of the largest submatrix                   */
+    int64_t sum_gm;          /* sum over submatrices of their blocks              */
+    double sum_gn3;          /* sum over submatrices of n^3 (n = bs blocks)       */
 } nolsm_plan_sizes;
 
 /* ------------------------------------------------------------- the path -- */
+
+/* Flags of nolsm_build_submatrices. */
+#define NOLSM_PLAN_COMBINE 1   /* combine submatrices (Sec. III-B, submatrix
+                                  combination heuristic, Eq.
+                                  combination_criterion): groups of molecules
+                                  share one submatrix on the union R of their
+                                  N(J) when (m_i + m_j - m_ij)^3 < m_i^3 + m_j^3
+                                  (m in blocks, m_ij = common blocks); candidates
+                                  of group i are the groups owning a block of
+                                  R_i, merged one at a time in increasing order
+                                  of the blocks one side adds to the other
+                                  (ties: larger cubic drop, then lower group
+                                  ids; the merged group keeps the lower id), at
+                                  most floor(64 / bs) molecules per group. D
+                                  keeps the merged pattern: only the rows N(J)
+                                  of each owned molecule are written back.     */
 
 /* Plan / index build (Sec. III-B.2 NOLSM generation step; Fig. 2 b-c).
  * Validates both patterns, merges them (block row I is in the submatrix of
  * column block J iff K_IJ or S_IJ is stored), and builds N(J) sorted
  * ascending, p_J = position of J in N(J), the pattern of D (= the merged
- * pattern) and the scatter positions. Host work only.
- * Errors: E_ARG (null, nb<1, bs outside 1..6, K/S disagree), E_PATTERN, E_NOMEM.
+ * pattern) and the scatter positions; with NOLSM_PLAN_COMBINE also the
+ * groups (otherwise every molecule is its own group). Host work only.
+ * Errors: E_ARG (null, nb<1, bs outside 1..6, K/S disagree, unknown flag),
+ * E_PATTERN, E_NOMEM.
  * On success *plan is owned by the caller (nolsm_plan_destroy). */
 int nolsm_build_submatrices(const nolsm_pattern *K, const nolsm_pattern *S,
                             int32_t flags, nolsm_plan **plan);
@@ -208,6 +230,13 @@ int nolsm_plan_info(const nolsm_plan *plan, nolsm_plan_sizes *out);
 int nolsm_plan_export(const nolsm_plan *plan, int32_t *sub_ptr, int32_t *sub_blk,
                       int32_t *self_pos, int32_t *D_row_ptr, int32_t *D_col_idx,
                       int32_t *scatter_pos);
+
+/* Copies the submatrix groups to host buffers (any may be NULL):
+ * grp_ptr[ngroups+1], grp_blk[sum_gm] (row blocks R_g, sorted),
+ * own_ptr[ngroups+1], own_J[nb] (molecules owned by group g, sorted; groups
+ * ordered by their smallest molecule). Sizes from nolsm_plan_info. */
+int nolsm_plan_groups(const nolsm_plan *plan, int32_t *grp_ptr, int32_t *grp_blk,
+                      int32_t *own_ptr, int32_t *own_J);
 
 /* Chooses the schedule for `opts` and a workspace of ws_bytes: submatrices
  * grouped into chunks that fit the workspace, tile lists per chunk. Reports

@@ -16,6 +16,7 @@ PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
 BOUNDS_GERSHGORIN, BOUNDS_LEARNED = 0, 1
 SCHED_GRAPH, SCHED_STREAM, SCHED_PER_BUCKET, SCHED_PERSISTENT = 0, 1, 2, 3
 INV_CHOLESKY, INV_COUPLED_NS = 0, 1
+PLAN_COMBINE = 1
 MLP_NFEAT = 12
 MLP_NPARAM = 5122
 
@@ -59,7 +60,9 @@ class PlanSizes(C.Structure):
     _fields_ = [("nb", C.c_int32), ("bs", C.c_int32), ("sum_m", C.c_int64),
                 ("m_min", C.c_int32), ("m_max", C.c_int32), ("sum_n3", C.c_double),
                 ("nchunks", C.c_int32), ("meta_bytes", C.c_size_t),
-                ("ws_min_bytes", C.c_size_t), ("ws_full_bytes", C.c_size_t)]
+                ("ws_min_bytes", C.c_size_t), ("ws_full_bytes", C.c_size_t),
+                ("ngroups", C.c_int32), ("g_m_max", C.c_int32), ("sum_gm", C.c_int64),
+                ("sum_gn3", C.c_double)]
 
 
 class Profile(C.Structure):
@@ -73,7 +76,8 @@ class Profile(C.Structure):
 EXPORTED = ["nolsm_default_opts", "nolsm_build_submatrices", "nolsm_plan_info", "nolsm_plan_export",
             "nolsm_plan_configure", "nolsm_plan_bind", "nolsm_sign_batch", "nolsm_assemble_D",
             "nolsm_plan_destroy", "nolsm_strerror", "nolsm_mlp_forward", "nolsm_mlp_loss_grad",
-            "nolsm_mlp_adam", "nolsm_profile_last", "nolsm_trace_sums", "nolsm_mu_bisect"]
+            "nolsm_mlp_adam", "nolsm_profile_last", "nolsm_trace_sums", "nolsm_mu_bisect",
+            "nolsm_plan_groups"]
 
 _lib = None
 
@@ -93,6 +97,7 @@ def lib():
     L.nolsm_build_submatrices.argtypes = [C.POINTER(Pattern), C.POINTER(Pattern), i32, C.POINTER(vp)]
     L.nolsm_plan_info.argtypes = [vp, C.POINTER(PlanSizes)]
     L.nolsm_plan_export.argtypes = [vp, p_i32, p_i32, p_i32, p_i32, p_i32, p_i32]
+    L.nolsm_plan_groups.argtypes = [vp, p_i32, p_i32, p_i32, p_i32]
     L.nolsm_plan_configure.argtypes = [vp, C.POINTER(SolveOpts), sz, C.POINTER(sz)]
     L.nolsm_plan_bind.argtypes = [vp, vp, sz, vp]
     L.nolsm_sign_batch.argtypes = [vp, vp, vp, dbl, C.POINTER(SolveOpts), vp, sz, vp, vp, vp, vp]

@@ -74,6 +74,7 @@ static ChunkDev chunk_dev(const nolsm_plan *pl, const HostChunk &ch, char *ws) {
     cd.n_rows = (int32_t)ch.t_rows.size();
     cd.max_m = ch.max_m;
     cd.max_np = ch.max_np;
+    cd.max_own = ch.max_own;
     return cd;
 }
 
@@ -114,7 +115,9 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
     ga.Kci = (const int32_t *)(base + pl->o_Kci);
     ga.Srp = (const int32_t *)(base + pl->o_Srp);
     ga.Sci = (const int32_t *)(base + pl->o_Sci);
-    ga.sub_blk = (const int32_t *)(base + pl->o_sub_blk);
+    ga.grp_blk = (const int32_t *)(base + pl->o_grp_blk);
+    ga.own_pos = (const int32_t *)(base + pl->o_own_pos);
+    ga.own_J = (const int32_t *)(base + pl->o_own_J);
     ga.Kval = b.dK;
     ga.Sval = b.dS;
     ga.bs = pl->bs;
@@ -123,6 +126,7 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
     ba.d_mlp = o.d_mlp;
     ba.d_norm = o.d_mlp_norm;
     ba.d_features = o.d_features;
+    ba.own_J = (const int32_t *)(base + pl->o_own_J);
     ba.safety = o.mlp_safety > 0 ? o.mlp_safety : 1.05f;
     ba.learned = o.bounds == NOLSM_BOUNDS_LEARNED;
     ba.scale_mult = o.debug_scale_mult;
@@ -141,12 +145,19 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
     ia.max_iter = o.inv_max_iter;
     ia.theta = na.theta;
     ia.rmax = na.rmax;
+    ia.own_pos = ga.own_pos;
+    ia.bs = pl->bs;
     FinishArgs fa;
     fa.prec = o.prec;
     fa.nfinal = (o.prec == NOLSM_FP16 || o.prec == NOLSM_BF16) ? o.n_final_fp32 : 0;
     ExtractArgs ea;
     ea.Krp = ga.Krp; ea.Kci = ga.Kci; ea.Srp = ga.Srp; ea.Sci = ga.Sci;
-    ea.sub_blk = ga.sub_blk;
+    ea.sub_blk = (const int32_t *)(base + pl->o_sub_blk);
+    ea.sub_ptr = (const int32_t *)(base + pl->o_sub_ptr);
+    ea.rowpos = (const int32_t *)(base + pl->o_rowpos);
+    ea.own_J = (const int32_t *)(base + pl->o_own_J);
+    ea.own_pos = ga.own_pos;
+    ea.grp_blk = ga.grp_blk;
     ea.scatter_pos = (const int32_t *)(base + pl->o_scatter);
     ea.Kval = b.dK;
     ea.Sval = b.dS;

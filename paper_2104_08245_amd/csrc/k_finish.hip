@@ -35,13 +35,16 @@ template <> struct Dec<BF16> {
 
 #define BSMAX 6
 
+// Input block of the products for owned molecule o: Y_J (its bs columns of
+// the K buffer) or a combination of its stored vectors.
 template <typename TV>
-__device__ __forceinline__ TV vec_in(const SkinnyArgs &a, const SubMeta &M, const char *ws, int row, int j) {
+__device__ __forceinline__ TV vec_in(const SkinnyArgs &a, const SubMeta &M, const char *ws, int o, int bs, int row,
+                                     int j) {
     const int np = M.np;
-    const TV *V = (const TV *)(ws + M.offVec);
     const int64_t vs = (int64_t)np * 6 * 8 / sizeof(TV);   // stride between vectors
+    const TV *V = (const TV *)(ws + M.offVec) + (int64_t)o * NOLSM_NVEC * vs;
     auto get = [&](int idx) -> TV {
-        if (idx == -1) return (TV)((const double *)(ws + M.offK))[(int64_t)row * (np + 64) + np + j];
+        if (idx == -1) return (TV)((const double *)(ws + M.offK))[(int64_t)row * (np + 64) + np + o * bs + j];
         return V[(int64_t)idx * vs + (int64_t)row * 6 + j];
     };
     TV v = (TV)a.alpha * get(a.ina);
@@ -62,18 +65,18 @@ __global__ __launch_bounds__(256) void k_skinny(ChunkDev cd, char *ws, SkinnyArg
     TV *vin = (TV *)skm;
     const uint32_t task = xcd_task(cd.t_rows);
     if (task == NOLSM_TASK_NONE) return;
-    const int s = task_slot(task), rq = task_a(task);
+    const int s = task_slot(task), rq = task_a(task), o = blockIdx.y;
     const SubMeta M = cd.meta[s];
     const SubCtl *ctl = cd.ctl + s;
-    if (ctl->status == NOLSM_MOL_NOT_SPD) return;
+    if (ctl->status == NOLSM_MOL_NOT_SPD || o >= M.nown) return;
     const int np = M.np, t = threadIdx.x;
     const int K = ctl->iters;
     const ST *P = (const ST *)(ws + ((K & 1) ? M.offX1 : M.offL));
-    TV *V = (TV *)(ws + M.offVec);
     const int64_t vs = (int64_t)np * 6 * 8 / sizeof(TV);
+    TV *V = (TV *)(ws + M.offVec) + (int64_t)o * NOLSM_NVEC * vs;
     for (int f = t; f < np * 6; f += 256) {
         const int r = f / 6, j = f - r * 6;
-        vin[f] = (j < bs) ? vec_in<TV>(sa, M, ws, r, j) : (TV)0;
+        vin[f] = (j < bs) ? vec_in<TV>(sa, M, ws, o, bs, r, j) : (TV)0;
     }
     __syncthreads();
     const int row = rq * 256 + t;
@@ -105,8 +108,8 @@ template <typename TP, typename TV>
 static hipError_t run_finish(const ChunkDev &cd, char *ws, int nfinal, int bs, hipStream_t st) {
     auto L = [&](int ina, int inb, double al, double be, int out, int save) {
         SkinnyArgs a{ina, inb, al, be, out, save};
-        hipLaunchKernelGGL((k_skinny<TP, TV>), dim3(cd.n_rows), dim3(256), (size_t)cd.max_np * 6 * sizeof(TV), st, cd,
-                           ws, a, bs);
+        hipLaunchKernelGGL((k_skinny<TP, TV>), dim3(cd.n_rows, cd.max_own), dim3(256),
+                           (size_t)cd.max_np * 6 * sizeof(TV), st, cd, ws, a, bs);
         return hipGetLastError();
     };
     hipError_t e;
@@ -156,77 +159,88 @@ __global__ __launch_bounds__(256) void k_extract(ChunkDev cd, char *ws, ExtractA
     if (s >= cd.nsub) return;
     const SubMeta M = cd.meta[s];
     const SubCtl *ctl = cd.ctl + s;
-    const int bs = ea.bs, n = M.n, np = M.np, J = M.J, t = threadIdx.x;
-    double *Dc = smem;                                    // n x bs
-    int *list = (int *)(smem + (size_t)cd.max_np * bs);
-    for (int i = t; i < M.m; i += 256) list[i] = ea.sub_blk[M.sub_off + i];
+    const int bs = ea.bs, n = M.n, np = M.np, t = threadIdx.x;
+    double *Df = smem;                                    // np x bs: whole-submatrix column block
+    int *rows = (int *)(smem + (size_t)cd.max_np * bs);   // row blocks of the submatrix
+    for (int i = t; i < M.m; i += 256) rows[i] = ea.grp_blk[M.sub_off + i];
     const bool ok = ctl->status != NOLSM_MOL_NOT_SPD;
     const double *Kb = (const double *)(ws + M.offK);
-    const TV *V = (const TV *)(ws + M.offVec);
     const int64_t vs = (int64_t)np * 6 * 8 / sizeof(TV);
-    double *Dout = ea.Dcols + (int64_t)bs * bs * M.sub_off;
-    for (int f = t; f < n * bs; f += 256) {
-        const int r = f / bs, c = f % bs;
-        double v = 0.0;
-        if (ok) {
-            const double y = Kb[(int64_t)r * (np + 64) + np + c];
-            const int64_t o = (int64_t)r * 6 + c;
-            double z;
-            if (ea.nfinal == 0)
-                z = (double)V[o];
-            else if (ea.nfinal == 1)
-                z = 1.5 * (double)V[o] - 0.5 * (double)V[2 * vs + o];
-            else
-                z = 1.5 * (double)V[3 * vs + o] - 0.75 * (double)V[8 * vs + o] + 0.25 * (double)V[10 * vs + o];
-            v = 0.5 * (y - z);
-        }
-        Dc[f] = v;
-        Dout[f] = v;
-    }
-    __syncthreads();
-    // traces over row J of S and of K
-    double tr[2];
-    for (int which = 0; which < 2; ++which) {
-        const int *rp = which ? ea.Krp : ea.Srp;
-        const int *ci = which ? ea.Kci : ea.Sci;
-        const double *val = which ? ea.Kval : ea.Sval;
-        const int lo = rp[J], hi = rp[J + 1];
-        const int nel = (hi - lo) * bs * bs;
-        double part = 0.0;
-        for (int f = t; f < nel; f += 256) {
-            const int e = lo + f / (bs * bs), rc = f % (bs * bs);
-            const int c = rc / bs, d = rc % bs;
-            const int C = ci[e];
-            int l = 0, h = M.m - 1, b = -1;
-            while (l <= h) {
-                const int mid = (l + h) >> 1;
-                const int v = list[mid];
-                if (v == C) { b = mid; break; }
-                if (v < C) l = mid + 1; else h = mid - 1;
+    for (int o = 0; o < M.nown; ++o) {
+        const int J = ea.own_J[M.own_off + o];
+        const int so = ea.sub_ptr[J], mJ = ea.sub_ptr[J + 1] - so;
+        const TV *V = (const TV *)(ws + M.offVec) + (int64_t)o * NOLSM_NVEC * vs;
+        __syncthreads();   // Df of the previous molecule is no longer read
+        for (int f = t; f < np * bs; f += 256) {
+            const int r = f / bs, c = f % bs;
+            double v = 0.0;
+            if (ok && r < n) {
+                const double y = Kb[(int64_t)r * (np + 64) + np + o * bs + c];
+                const int64_t q = (int64_t)r * 6 + c;
+                double z;
+                if (ea.nfinal == 0)
+                    z = (double)V[q];
+                else if (ea.nfinal == 1)
+                    z = 1.5 * (double)V[q] - 0.5 * (double)V[2 * vs + q];
+                else
+                    z = 1.5 * (double)V[3 * vs + q] - 0.75 * (double)V[8 * vs + q] + 0.25 * (double)V[10 * vs + q];
+                v = 0.5 * (y - z);
             }
-            if (b >= 0) part += val[(int64_t)e * bs * bs + rc] * Dc[(b * bs + d) * bs + c];
+            Df[f] = v;
         }
-        tr[which] = block_sum(part, red);
-    }
-    if (ea.Dval) {
-        for (int f = t; f < M.m * bs * bs; f += 256) {
+        __syncthreads();
+        // the owned columns on the rows N(J) (the pattern of D), through
+        // the row positions of N(J) in this submatrix
+        double *Dout = ea.Dcols + (int64_t)bs * bs * so;
+        for (int f = t; f < mJ * bs * bs; f += 256) {
             const int a = f / (bs * bs), rc = f % (bs * bs);
-            const int64_t pos = ea.scatter_pos[M.sub_off + a];
-            ea.Dval[pos * bs * bs + rc] = Dc[(int64_t)a * bs * bs + rc];
+            const double v = Df[(ea.rowpos[so + a] * bs) * bs + rc];
+            Dout[f] = v;
+            if (ea.Dval) ea.Dval[(int64_t)ea.scatter_pos[so + a] * bs * bs + rc] = v;
         }
-    }
-    if (t == 0) {
-        MolStatsDev *st = (MolStatsDev *)ea.stats + J;
-        st->iters = ctl->iters;
-        st->iters_fp32 = (ok && (ea.prec == NOLSM_FP16 || ea.prec == NOLSM_BF16)) ? ea.nfinal : 0;
-        st->fallback = ctl->fallback;
-        st->status = ctl->status;
-        st->scale = ctl->scale;
-        st->resid = ctl->resid;
-        st->trace_SD = ok ? tr[0] : 0.0;
-        st->energy_KD = ok ? tr[1] : 0.0;
-        st->iters_inv = cd.ictl ? cd.ictl[s].iters : 0;
-        st->reserved_ = 0;
+        // the whole column block is kept for the W columns
+        if (ea.Wcols) {
+            double *Wk = (double *)(ws + M.offVec) + (int64_t)(o * NOLSM_NVEC + NOLSM_NVEC - 1) * np * 6;
+            for (int f = t; f < np * bs; f += 256) Wk[(f / bs) * 6 + f % bs] = Df[f];
+        }
+        // traces over row J of S and of K: every stored column block C of
+        // row J lies in N(J), hence in the submatrix rows
+        double tr[2];
+        for (int which = 0; which < 2; ++which) {
+            const int *rp = which ? ea.Krp : ea.Srp;
+            const int *ci = which ? ea.Kci : ea.Sci;
+            const double *val = which ? ea.Kval : ea.Sval;
+            const int lo = rp[J], hi = rp[J + 1];
+            const int nel = (hi - lo) * bs * bs;
+            double part = 0.0;
+            for (int f = t; f < nel; f += 256) {
+                const int e = lo + f / (bs * bs), rc = f % (bs * bs);
+                const int c = rc / bs, d = rc % bs;
+                const int C = ci[e];
+                int l = 0, h = M.m - 1, b = -1;
+                while (l <= h) {
+                    const int mid = (l + h) >> 1;
+                    const int v = rows[mid];
+                    if (v == C) { b = mid; break; }
+                    if (v < C) l = mid + 1; else h = mid - 1;
+                }
+                if (b >= 0) part += val[(int64_t)e * bs * bs + rc] * Df[(b * bs + d) * bs + c];
+            }
+            tr[which] = block_sum(part, red);
+        }
+        if (t == 0) {
+            MolStatsDev *st = (MolStatsDev *)ea.stats + J;
+            st->iters = ctl->iters;
+            st->iters_fp32 = (ok && (ea.prec == NOLSM_FP16 || ea.prec == NOLSM_BF16)) ? ea.nfinal : 0;
+            st->fallback = ctl->fallback;
+            st->status = ctl->status;
+            st->scale = ctl->scale;
+            st->resid = ctl->resid;
+            st->trace_SD = ok ? tr[0] : 0.0;
+            st->energy_KD = ok ? tr[1] : 0.0;
+            st->iters_inv = cd.ictl ? cd.ictl[s].iters : 0;
+            st->reserved_ = 0;
+        }
     }
 }
 
@@ -236,29 +250,36 @@ __global__ __launch_bounds__(256) void k_extract(ChunkDev cd, char *ws, ExtractA
 // With T_J(D) = P T_J(S)^-1, P = (I - sign A_J)/2 a projector that commutes
 // with A_J = T_J(S)^-1 T_J(K) - mu I, this is P (A_J + mu I) P Y_J =
 // (A_J + mu I) Dcols_J: one n x n by n x bs product with the FP64 A_J still in
-// the workspace. One row per lane, 256 rows per workgroup; Dcols_J staged in
+// the workspace, on the whole submatrix column block of the molecule (kept by
+// the extraction) and written back on the rows N(J). One row per lane, 256
+// rows per workgroup, grid.y = owned molecule; the column block is staged in
 // LDS (max_np x bs doubles). NOT_SPD molecules get zeros.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_wcols(ChunkDev cd, char *ws, ExtractArgs ea) {
     extern __shared__ __attribute__((aligned(16))) double dcs[];
     const uint32_t task = xcd_task(cd.t_rows);
     if (task == NOLSM_TASK_NONE) return;
-    const int s = task_slot(task), rq = task_a(task);
+    const int s = task_slot(task), rq = task_a(task), o = blockIdx.y;
     const SubMeta M = cd.meta[s];
+    if (o >= M.nown) return;
     const int n = M.n, np = M.np, bs = ea.bs, t = threadIdx.x;
+    const int J = ea.own_J[M.own_off + o];
+    const int so = ea.sub_ptr[J], mJ = ea.sub_ptr[J + 1] - so;
     const double mu = ((const WsHeader *)ws)->mu;
     const bool ok = cd.ctl[s].status != NOLSM_MOL_NOT_SPD;
-    const double *Dc = ea.Dcols + (int64_t)bs * bs * M.sub_off;
-    double *Wc = ea.Wcols + (int64_t)bs * bs * M.sub_off;
-    for (int f = t; f < n * bs; f += 256) dcs[f] = Dc[f];
+    // whole-submatrix column block of molecule J, kept by the extraction
+    const double *Df = (const double *)(ws + M.offVec) + (int64_t)(o * NOLSM_NVEC + NOLSM_NVEC - 1) * np * 6;
+    double *Wc = ea.Wcols + (int64_t)bs * bs * so;
+    for (int f = t; f < n * bs; f += 256) dcs[f] = Df[(f / bs) * 6 + f % bs];
     __syncthreads();
-    const int row = rq * 256 + t;
-    if (row >= n) return;
+    const int row = rq * 256 + t;   // row of W_J on N(J)
+    if (row >= mJ * bs) return;
+    const int gr = ea.rowpos[so + row / bs] * bs + row % bs;   // its submatrix row
     double acc[BSMAX];
 #pragma unroll
     for (int j = 0; j < BSMAX; ++j) acc[j] = 0.0;
     if (ok) {
-        const double *arow = (const double *)(ws + M.offK) + (int64_t)row * (np + 64);
+        const double *arow = (const double *)(ws + M.offK) + (int64_t)gr * (np + 64);
 #pragma unroll 4
         for (int k = 0; k < n; k += 2) {   // n = bs m is even for bs = 6
             const double2 a = *(const double2 *)(arow + k);
@@ -268,7 +289,7 @@ __global__ __launch_bounds__(256) void k_wcols(ChunkDev cd, char *ws, ExtractArg
         }
 #pragma unroll
         for (int j = 0; j < BSMAX; ++j)
-            if (j < bs) acc[j] += mu * dcs[row * bs + j];
+            if (j < bs) acc[j] += mu * dcs[gr * bs + j];
     }
 #pragma unroll
     for (int j = 0; j < BSMAX; ++j)
@@ -277,7 +298,8 @@ __global__ __launch_bounds__(256) void k_wcols(ChunkDev cd, char *ws, ExtractArg
 
 hipError_t launch_wcols(const ChunkDev &cd, char *ws, const ExtractArgs &ea, hipStream_t st) {
     if (ea.bs & 1) return hipErrorInvalidValue;   // the row loop takes k in pairs
-    hipLaunchKernelGGL(k_wcols, dim3(cd.n_rows), dim3(256), (size_t)cd.max_np * ea.bs * 8, st, cd, ws, ea);
+    hipLaunchKernelGGL(k_wcols, dim3(cd.n_rows, cd.max_own), dim3(256), (size_t)cd.max_np * ea.bs * 8, st, cd, ws,
+                       ea);
     return hipGetLastError();
 }
 

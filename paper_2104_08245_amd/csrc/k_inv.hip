@@ -172,24 +172,30 @@ __device__ __forceinline__ void inv_tile(const ChunkDev &cd, uint32_t task, char
                                                           eo, INV_EOFF(i, j, e), 0);
             }
     } else if (mode == IM_SQ) {
-        // S^-1 = c Z_K^2 in 16 bits for the A GEMM; the owned columns
-        // p bs .. p bs + bs - 1 also go, from the FP32 accumulators, to the
-        // FP64 Y_J columns np .. np + bs - 1 of the K buffer
+        // S^-1 = c Z_K^2 in 16 bits for the A GEMM; the columns of every
+        // owned molecule o (block position q_o) also go, from the FP32
+        // accumulators, to its FP64 Y columns np + o bs .. of the K buffer
         const double c = ic->scale;
         const __amdgpu_buffer_rsrc_t rsS = __builtin_amdgcn_make_buffer_rsrc((void *)Sinv, (short)0, nrec, 0x00020000);
         double *Kb = (double *)(ws + M.offK);
-        const int c0 = M.p * 6, ldk = np + 64;
+        const int ldk = np + 64, bs = ia.bs;
 #pragma unroll
-        for (int i = 0; i < NB; ++i)
+        for (int j = 0; j < NB; ++j) {
+            // the output column of this lane in block column j, and its owner
+            const int gc = ec0 + j * 32, qb = gc / bs;
+            int yc = -1;
+            for (int o = 0; o < M.nown; ++o)
+                if (ia.own_pos[M.own_off + o] == qb) yc = np + o * bs + (gc - qb * bs);
 #pragma unroll
-            for (int j = 0; j < NB; ++j)
+            for (int i = 0; i < NB; ++i)
 #pragma unroll
                 for (int e = 0; e < 16; ++e) {
                     const float v = (float)c * acc[i][j][e];
                     __builtin_amdgcn_raw_buffer_store_b16(Lp<T>::enc(v), rsS, eo, INV_EOFF(i, j, e), 0);
-                    const int gr = INV_ROW(i, e), gc = ec0 + j * 32;
-                    if (gr < np && gc >= c0 && gc < c0 + 6) Kb[(int64_t)gr * ldk + np + (gc - c0)] = c * (double)acc[i][j][e];
+                    const int gr = INV_ROW(i, e);
+                    if (gr < np && gc < np && yc >= 0) Kb[(int64_t)gr * ldk + yc] = c * (double)acc[i][j][e];
                 }
+        }
     } else {
         // A_J = S^-1 K_J - mu I, FP64, rows and columns < np only (columns
         // np.. of the K buffer hold Y_J)

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
     int *list = gsm;                 // N(J)
     int *posK = gsm + cd.max_m;      // block column b -> CSR entry in K's row I, or -1
     int *posS = gsm + 2 * cd.max_m;  // the same for S
-    const int *nlist = ga.sub_blk + M.sub_off;
+    const int *nlist = ga.grp_blk + M.sub_off;
     for (int i = t; i < m; i += 256) {
         list[i] = nlist[i];
         posK[i] = -1;
@@ -60,7 +60,10 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
     double *Sd = (double *)(ws + M.offL);
     const int64_t ldk = np + 64, lds = np;
     const int bb = bs * bs;
-    const bool poison = (M.J == ga.poison_J && a == 0);
+    // debug: a negative pivot in the submatrix that owns poison_J
+    bool poison = false;
+    for (int o = 0; o < M.nown; ++o)
+        poison |= (a == 0 && ga.own_J[M.own_off + o] == ga.poison_J);
     for (int i = t; i < bs * np; i += 256) {
         const int r = i / np, c = i - r * np;
         double vk = 0.0, vs = 0.0;
@@ -74,10 +77,14 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
         Kd[(int64_t)(a * bs + r) * ldk + c] = vk;
         Sd[(int64_t)(a * bs + r) * lds + c] = vs;
     }
-    // E tile: columns np..np+63 of the K buffer
+    // E tile: columns np..np+63 of the K buffer; owned molecule o (block
+    // position q_o in the rows) has its unit columns at o bs .. o bs + bs - 1
+    int own_here = -1;
+    for (int o = 0; o < M.nown; ++o)
+        if (ga.own_pos[M.own_off + o] == a) own_here = o;
     for (int i = t; i < bs * 64; i += 256) {
         const int r = i / 64, c = i % 64;
-        Kd[(int64_t)(a * bs + r) * ldk + np + c] = (a == M.p && c == r) ? 1.0 : 0.0;
+        Kd[(int64_t)(a * bs + r) * ldk + np + c] = (own_here >= 0 && c == own_here * bs + r) ? 1.0 : 0.0;
     }
     // padding rows (one workgroup per submatrix does it)
     if (a == 0 && np > n) {
@@ -373,7 +380,10 @@ __global__ __launch_bounds__(256) void k_bounds(ChunkDev cd, char *ws, BoundsArg
                                  rsum / n, rmax, rlo, rhi, clo, chi, sqrt(fr / n)};
         for (int i = 0; i < NOLSM_NFEAT; ++i) feat[i] = (float)f[i];
         if (ba.d_features)
-            for (int i = 0; i < NOLSM_NFEAT; ++i) ba.d_features[(int64_t)M.J * NOLSM_NFEAT + i] = (float)f[i];
+            for (int o = 0; o < M.nown; ++o) {
+                const int64_t Jo = ba.own_J[M.own_off + o];
+                for (int i = 0; i < NOLSM_NFEAT; ++i) ba.d_features[Jo * NOLSM_NFEAT + i] = (float)f[i];
+            }
     }
     __syncthreads();
     double c = cg;

@@ -5,7 +5,10 @@
 #include "nolsm_internal.h"
 
 struct GatherArgs {
-    const int32_t *Krp, *Kci, *Srp, *Sci, *sub_blk;
+    const int32_t *Krp, *Kci, *Srp, *Sci;
+    const int32_t *grp_blk;   // row blocks of every submatrix (SubMeta::sub_off)
+    const int32_t *own_pos;   // position of each owned molecule in its rows (SubMeta::own_off)
+    const int32_t *own_J;     // the owned molecules themselves (SubMeta::own_off)
     const double *Kval, *Sval;
     int32_t bs;
     int32_t poison_J;
@@ -15,6 +18,7 @@ struct BoundsArgs {
     const float *d_mlp;
     const float *d_norm;
     float *d_features;
+    const int32_t *own_J;     // molecules owned by each submatrix (SubMeta::own_off)
     float safety;
     int32_t learned;
     double scale_mult;
@@ -38,6 +42,8 @@ struct InvArgs {
     int32_t prec;          // NOLSM_FP16 or NOLSM_BF16
     int32_t max_iter;      // iteration slots
     double theta, rmax;
+    const int32_t *own_pos;   // block position of each owned molecule (SubMeta::own_off)
+    int32_t bs;
 };
 
 struct FinishArgs {
@@ -47,6 +53,10 @@ struct FinishArgs {
 
 struct ExtractArgs {
     const int32_t *Krp, *Kci, *Srp, *Sci, *sub_blk, *scatter_pos;
+    const int32_t *sub_ptr;   // N(J) of molecule J: sub_blk[sub_ptr[J] ..)
+    const int32_t *rowpos;    // position of N(J)_a in the rows of J's submatrix
+    const int32_t *own_J, *own_pos;
+    const int32_t *grp_blk;   // submatrix row blocks (SubMeta::sub_off)
     const double *Kval, *Sval;
     double *Dcols;         // [36 * sum_m] for bs = 6
     double *Dval;          // optional

@@ -12,17 +12,19 @@
 
 // One submatrix slot of a chunk. Byte offsets are into the workspace.
 struct SubMeta {
-    int32_t J;        // column block (molecule)
-    int32_t m;        // blocks in N(J)
+    int32_t J;        // first owned column block (molecule)
+    int32_t m;        // row blocks of the submatrix (N(J), or the union over a group)
     int32_t n;        // bs * m
     int32_t np;       // n rounded up to NOLSM_TILE
-    int32_t p;        // position of J in N(J)
+    int32_t p;        // position of J's block in the submatrix rows
     int32_t P;        // np / NOLSM_TILE
-    int32_t sub_off;  // sub_ptr[J]
+    int32_t sub_off;  // offset of the submatrix rows in the group row list
     int32_t ntile_ns; // NS GEMM tiles of this slot (for residual partials)
     int32_t ldx;      // leading dimension of the X / R buffers: np rounded up
                       // to the NS tile, so tile loads never leave the buffer
-    int32_t pad_;
+    int32_t nown;     // molecules owned by this submatrix (1 unless combined)
+    int32_t own_off;  // their offset in the owned-molecule list
+    int32_t pad2_;
     int64_t offL;     // np*np doubles: S -> L; later X buffer 0
     int64_t offK;     // np*(np+64) doubles: K -> W -> [A | Y]
     int64_t offDinv;  // P*64*64 doubles: inverses of the diagonal tiles of L
@@ -30,7 +32,7 @@ struct SubMeta {
     int64_t offCol;   // np doubles col sums of |A|, then 64 more: P frob partials
     int64_t offX1;    // ldx*ldx elements of the NS precision: X buffer 1
     int64_t offB;     // ldx*ldx elements: R = I - X^2
-    int64_t offVec;   // NOLSM_NVEC * np * 6 floats/doubles: finishing vectors
+    int64_t offVec;   // nown * NOLSM_NVEC * np * 6 floats/doubles: finishing vectors
     int64_t offRes;   // max(max_iter, inv_max_iter) * ntile_ns doubles: residual partials
     // coupled Newton-Schulz inverse only (0 otherwise): ldx*ldx elements each
     int64_t offY0, offY1;   // Y_k ping-pong; after convergence S^-1 and K in 16 bits
@@ -87,5 +89,5 @@ struct ChunkDev {
     InvCtl *ictl;              // in the workspace (coupled inverse), else null
     int32_t *queues;           // persistent launches: [max_iter][2][2][8] counters
     int32_t nqueue;            // number of counters
-    int32_t nsub, n_subst, n_conv, n_ns, n_ns64, n_rows, max_m, max_np;
+    int32_t nsub, n_subst, n_conv, n_ns, n_ns64, n_rows, max_m, max_np, max_own;
 };

@@ -7,6 +7,7 @@
 // matrix D keeps the merged pattern (the submatrix approximation has the
 // sparsity of its input).
 #include <algorithm>
+#include <queue>
 #include <iterator>
 #include <cstring>
 #include <mutex>
@@ -36,7 +37,8 @@ int nolsm_elem_for(int32_t prec) {
     }
 }
 
-size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_iter, int32_t inverse) {
+size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_iter, int32_t inverse,
+                        int32_t nown) {
     const size_t n = (size_t)np;
     const size_t P = n / NOLSM_TILE;
     const size_t nt = (n + ns_tile - 1) / ns_tile;
@@ -49,7 +51,7 @@ size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_i
     const size_t ldx = nt * (size_t)ns_tile;   // X0 (in the L buffer) also fits: ldx <= np + 64
     b += align256(ldx * ldx * (size_t)elem);  // X1
     b += align256(ldx * ldx * (size_t)elem);  // R
-    b += align256((size_t)NOLSM_NVEC * n * 6 * 8);  // finishing vectors
+    b += align256((size_t)NOLSM_NVEC * n * 6 * 8 * nown);  // finishing vectors per owned molecule
     b += align256((size_t)max_iter * nt * nt * 8);  // residual partials
     if (inverse == NOLSM_INV_COUPLED_NS) b += 4 * align256(ldx * ldx * (size_t)elem);  // Y, Z ping-pong
     return b;
@@ -91,10 +93,133 @@ static int validate(const nolsm_pattern *p, const char *name) {
     return NOLSM_OK;
 }
 
+// Submatrix combination (Sec. III-B, Eq. combination_criterion), greedy:
+// the valid pair with the fewest blocks added to one side is merged first
+// (ties: larger cubic drop, then lower ids); stale queue entries are skipped
+// by version. Candidates of group a are the groups owning a block of R_a
+// (patterns are symmetric, so the relation is too).
+namespace {
+struct PairKey {
+    int64_t add, neg_drop;
+    int32_t a, b;
+    uint32_t va, vb;
+    bool operator>(const PairKey &o) const {
+        if (add != o.add) return add > o.add;
+        if (neg_drop != o.neg_drop) return neg_drop > o.neg_drop;
+        if (a != o.a) return a > o.a;
+        return b > o.b;
+    }
+};
+
+static int64_t common_blocks(const std::vector<int32_t> &x, const std::vector<int32_t> &y) {
+    int64_t c = 0;
+    size_t i = 0, j = 0;
+    while (i < x.size() && j < y.size()) {
+        if (x[i] < y[j]) ++i;
+        else if (y[j] < x[i]) ++j;
+        else { ++c; ++i; ++j; }
+    }
+    return c;
+}
+
+static void combine_groups(nolsm_plan *pl, int32_t max_own) {
+    const int32_t nb = pl->nb;
+    std::vector<std::vector<int32_t>> rows(nb), owned(nb);
+    std::vector<int32_t> owner(nb);
+    std::vector<uint32_t> ver(nb, 0);
+    std::vector<char> alive(nb, 1);
+    for (int32_t J = 0; J < nb; ++J) {
+        rows[J].assign(pl->sub_blk.begin() + pl->sub_ptr[J], pl->sub_blk.begin() + pl->sub_ptr[J + 1]);
+        owned[J].assign(1, J);
+        owner[J] = J;
+    }
+    std::priority_queue<PairKey, std::vector<PairKey>, std::greater<PairKey>> q;
+    auto consider = [&](int32_t a, int32_t b) {   // a < b, both alive
+        if ((int32_t)(owned[a].size() + owned[b].size()) > max_own) return;
+        const int64_t mi = (int64_t)rows[a].size(), mj = (int64_t)rows[b].size();
+        const int64_t mij = common_blocks(rows[a], rows[b]);
+        const int64_t mu = mi + mj - mij;
+        const int64_t drop = mi * mi * mi + mj * mj * mj - mu * mu * mu;
+        if (drop <= 0) return;
+        q.push(PairKey{std::min(mj - mij, mi - mij), -drop, a, b, ver[a], ver[b]});
+    };
+    std::vector<int32_t> cand;
+    auto candidates = [&](int32_t a) {
+        cand.clear();
+        for (int32_t blk : rows[a]) {
+            const int32_t g = owner[blk];
+            if (g != a) cand.push_back(g);
+        }
+        std::sort(cand.begin(), cand.end());
+        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    };
+    for (int32_t a = 0; a < nb; ++a) {
+        candidates(a);
+        for (int32_t b : cand)
+            if (b > a) consider(a, b);
+    }
+    while (!q.empty()) {
+        const PairKey k = q.top();
+        q.pop();
+        if (!alive[k.a] || !alive[k.b] || ver[k.a] != k.va || ver[k.b] != k.vb) continue;
+        const int32_t a = k.a, b = k.b;
+        std::vector<int32_t> u;
+        u.reserve(rows[a].size() + rows[b].size());
+        std::set_union(rows[a].begin(), rows[a].end(), rows[b].begin(), rows[b].end(), std::back_inserter(u));
+        rows[a].swap(u);
+        std::vector<int32_t>().swap(rows[b]);
+        std::vector<int32_t> o;
+        std::merge(owned[a].begin(), owned[a].end(), owned[b].begin(), owned[b].end(), std::back_inserter(o));
+        owned[a].swap(o);
+        for (int32_t J : owned[a]) owner[J] = a;
+        std::vector<int32_t>().swap(owned[b]);
+        alive[b] = 0;
+        ++ver[a];
+        candidates(a);
+        for (int32_t c : cand) consider(std::min(a, c), std::max(a, c));
+    }
+    // groups ordered by their smallest molecule (= their id)
+    pl->grp_ptr.assign(1, 0);
+    pl->own_ptr.assign(1, 0);
+    pl->grp_blk.clear();
+    pl->own_J.clear();
+    for (int32_t g = 0; g < nb; ++g) {
+        if (!alive[g]) continue;
+        pl->grp_blk.insert(pl->grp_blk.end(), rows[g].begin(), rows[g].end());
+        pl->grp_ptr.push_back((int32_t)pl->grp_blk.size());
+        pl->own_J.insert(pl->own_J.end(), owned[g].begin(), owned[g].end());
+        pl->own_ptr.push_back((int32_t)pl->own_J.size());
+    }
+}
+}  // namespace
+
+// Positions of owned molecules and of their N(J) rows inside their groups,
+// and the group size statistics.
+static void finish_groups(nolsm_plan *pl) {
+    const int32_t ng = (int32_t)pl->grp_ptr.size() - 1;
+    pl->own_pos.assign(pl->own_J.size(), -1);
+    pl->rowpos.assign(pl->sub_blk.size(), -1);
+    pl->g_m_max = 0;
+    pl->sum_gn3 = 0.0;
+    for (int32_t g = 0; g < ng; ++g) {
+        const int32_t *lb = pl->grp_blk.data() + pl->grp_ptr[g], *le = pl->grp_blk.data() + pl->grp_ptr[g + 1];
+        const int32_t m = (int32_t)(le - lb);
+        pl->g_m_max = std::max(pl->g_m_max, m);
+        const double n = (double)m * pl->bs;
+        pl->sum_gn3 += n * n * n;
+        for (int32_t o = pl->own_ptr[g]; o < pl->own_ptr[g + 1]; ++o) {
+            const int32_t J = pl->own_J[o];
+            pl->own_pos[o] = (int32_t)(std::lower_bound(lb, le, J) - lb);
+            for (int32_t e = pl->sub_ptr[J]; e < pl->sub_ptr[J + 1]; ++e)
+                pl->rowpos[e] = (int32_t)(std::lower_bound(lb, le, pl->sub_blk[e]) - lb);
+        }
+    }
+}
+
 extern "C" int nolsm_build_submatrices(const nolsm_pattern *K, const nolsm_pattern *S,
                                        int32_t flags, nolsm_plan **out) {
-    (void)flags;
     if (!out) { nolsm_set_last_error("plan out-pointer is null"); return NOLSM_E_ARG; }
+    if (flags & ~NOLSM_PLAN_COMBINE) { nolsm_set_last_error("unknown plan flag"); return NOLSM_E_ARG; }
     *out = nullptr;
     if (!K || !S) { nolsm_set_last_error("null pattern"); return NOLSM_E_ARG; }
     if (K->nb != S->nb || K->bs != S->bs) { nolsm_set_last_error("K and S disagree on nb/bs"); return NOLSM_E_ARG; }
@@ -149,6 +274,17 @@ extern "C" int nolsm_build_submatrices(const nolsm_pattern *K, const nolsm_patte
                 pl->scatter_pos[pl->sub_ptr[J] + a] = (int32_t)(q - pl->sub_blk.data());
             }
         }
+        if (flags & NOLSM_PLAN_COMBINE) {
+            combine_groups(pl, 64 / pl->bs);
+        } else {
+            pl->grp_ptr = pl->sub_ptr;
+            pl->grp_blk = pl->sub_blk;
+            pl->own_ptr.resize(nb + 1);
+            pl->own_J.resize(nb);
+            for (int32_t J = 0; J <= nb; ++J) pl->own_ptr[J] = J;
+            for (int32_t J = 0; J < nb; ++J) pl->own_J[J] = J;
+        }
+        finish_groups(pl);
     } catch (...) {
         delete pl;
         return NOLSM_E_NOMEM;
@@ -191,6 +327,20 @@ extern "C" int nolsm_plan_info(const nolsm_plan *p, nolsm_plan_sizes *o) {
         o->ws_min_bytes = p->ws_min;
         o->ws_full_bytes = p->ws_full;
     }
+    o->ngroups = (int32_t)p->grp_ptr.size() - 1;
+    o->g_m_max = p->g_m_max;
+    o->sum_gm = (int64_t)p->grp_blk.size();
+    o->sum_gn3 = p->sum_gn3;
+    return NOLSM_OK;
+}
+
+extern "C" int nolsm_plan_groups(const nolsm_plan *p, int32_t *grp_ptr, int32_t *grp_blk, int32_t *own_ptr,
+                                 int32_t *own_J) {
+    if (!p) return NOLSM_E_ARG;
+    if (grp_ptr) std::memcpy(grp_ptr, p->grp_ptr.data(), p->grp_ptr.size() * 4);
+    if (grp_blk) std::memcpy(grp_blk, p->grp_blk.data(), p->grp_blk.size() * 4);
+    if (own_ptr) std::memcpy(own_ptr, p->own_ptr.data(), p->own_ptr.size() * 4);
+    if (own_J) std::memcpy(own_J, p->own_J.data(), p->own_J.size() * 4);
     return NOLSM_OK;
 }
 
@@ -253,20 +403,22 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
         // residual partial slots serve both iterations, one after the other
         const int32_t res_slots = std::max(pl->max_iter, pl->inv_max_iter);
         pl->elem = nolsm_elem_for(opts->prec);
-        const int32_t nb = pl->nb, bs = pl->bs;
-        auto np_of = [&](int32_t J) {
-            const int32_t n = bs * (pl->sub_ptr[J + 1] - pl->sub_ptr[J]);
+        // slots are submatrices: groups of molecules (one per molecule
+        // unless the plan was built with NOLSM_PLAN_COMBINE)
+        const int32_t bs = pl->bs, ng = (int32_t)pl->grp_ptr.size() - 1;
+        auto np_of = [&](int32_t g) {
+            const int32_t n = bs * (pl->grp_ptr[g + 1] - pl->grp_ptr[g]);
             return (n + NOLSM_TILE - 1) / NOLSM_TILE * NOLSM_TILE;
         };
         const uint64_t mask = opts->ns_small_tile_mask;
         auto tile_of = [&](int32_t J) { return nolsm_ns_tile_for(opts->prec, np_of(J), mask); };
-        if ((size_t)pl->m_max * bs > 4032) {
+        if ((size_t)pl->g_m_max * bs > 4032) {
             nolsm_set_last_error("submatrices above 4032 rows are not supported");
             return NOLSM_E_ARG;
         }
         // order: decreasing np (largest-first keeps the tail short), then J
-        std::vector<int32_t> order(nb);
-        for (int32_t J = 0; J < nb; ++J) order[J] = J;
+        std::vector<int32_t> order(ng);
+        for (int32_t g = 0; g < ng; ++g) order[g] = g;
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return np_of(a) > np_of(b); });
         const size_t ctl_bytes =
             align256(sizeof(SubCtl)) + (pl->inverse == NOLSM_INV_COUPLED_NS ? align256(sizeof(InvCtl)) : 0);
@@ -275,8 +427,12 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
         const size_t qbytes = align256(nqueue * sizeof(int32_t));
         pl->ws_min = 0;
         pl->ws_full = 0;
-        for (int32_t J = 0; J < nb; ++J) {
-            const size_t sb = nolsm_slot_bytes(np_of(J), tile_of(J), pl->elem, res_slots, pl->inverse) + ctl_bytes;
+        auto slot_bytes = [&](int32_t g) {
+            return nolsm_slot_bytes(np_of(g), tile_of(g), pl->elem, res_slots, pl->inverse,
+                                    pl->own_ptr[g + 1] - pl->own_ptr[g]) + ctl_bytes;
+        };
+        for (int32_t J = 0; J < ng; ++J) {
+            const size_t sb = slot_bytes(J);
             pl->ws_min = std::max(pl->ws_min, sb);
             pl->ws_full += sb;
         }
@@ -297,7 +453,7 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
             while (i < order.size() && js.size() < 65535) {
                 const int32_t J = order[i];
                 if (pl->sched == NOLSM_SCHED_PER_BUCKET && np_of(J) != bucket) break;
-                const size_t sb = nolsm_slot_bytes(np_of(J), tile_of(J), pl->elem, res_slots, pl->inverse) + ctl_bytes;
+                const size_t sb = slot_bytes(J);
                 if (used + sb + 256 + qbytes > ws_bytes) break;
                 used += sb;
                 js.push_back(J);
@@ -315,17 +471,19 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
             }
             size_t off = ch.off_q + qbytes;
             for (size_t s = 0; s < js.size(); ++s) {
-                const int32_t J = js[s];
+                const int32_t g = js[s];
                 SubMeta m;
                 std::memset(&m, 0, sizeof(m));
-                m.J = J;
-                m.m = pl->sub_ptr[J + 1] - pl->sub_ptr[J];
+                m.J = pl->own_J[pl->own_ptr[g]];
+                m.m = pl->grp_ptr[g + 1] - pl->grp_ptr[g];
                 m.n = bs * m.m;
-                m.np = np_of(J);
-                m.p = pl->self_pos[J];
+                m.np = np_of(g);
+                m.p = pl->own_pos[pl->own_ptr[g]];
                 m.P = m.np / NOLSM_TILE;
-                m.sub_off = pl->sub_ptr[J];
-                const int32_t T = tile_of(J);
+                m.sub_off = pl->grp_ptr[g];
+                m.own_off = pl->own_ptr[g];
+                m.nown = pl->own_ptr[g + 1] - pl->own_ptr[g];
+                const int32_t T = tile_of(g);
                 const int32_t nt = (m.np + T - 1) / T;
                 m.ntile_ns = nt * nt;
                 const size_t n = (size_t)m.np;
@@ -338,7 +496,7 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
                 const size_t ldx = (size_t)m.ldx;
                 m.offX1 = (int64_t)off; off += align256(ldx * ldx * pl->elem);
                 m.offB = (int64_t)off; off += align256(ldx * ldx * pl->elem);
-                m.offVec = (int64_t)off; off += align256((size_t)NOLSM_NVEC * n * 6 * 8);
+                m.offVec = (int64_t)off; off += align256((size_t)NOLSM_NVEC * n * 6 * 8 * m.nown);
                 m.offRes = (int64_t)off; off += align256((size_t)res_slots * m.ntile_ns * 8);
                 if (pl->inverse == NOLSM_INV_COUPLED_NS) {
                     m.offY0 = (int64_t)off; off += align256(ldx * ldx * pl->elem);
@@ -349,6 +507,7 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
                 ch.meta.push_back(m);
                 ch.max_m = std::max(ch.max_m, m.m);
                 ch.max_np = std::max(ch.max_np, m.np);
+                ch.max_own = std::max(ch.max_own, m.nown);
                 for (int32_t c = 0; c <= m.P; ++c) ch.t_subst.push_back(NOLSM_TASK(s, c, 0));
                 for (int32_t a = 0; a < m.P; ++a)
                     for (int32_t b = 0; b < m.P; ++b) ch.t_conv.push_back(NOLSM_TASK(s, a, b));
@@ -379,6 +538,10 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
         pl->o_sub_blk = put(pl->image, pl->sub_blk.data(), pl->sub_blk.size());
         pl->o_self = put(pl->image, pl->self_pos.data(), pl->self_pos.size());
         pl->o_scatter = put(pl->image, pl->scatter_pos.data(), pl->scatter_pos.size());
+        pl->o_grp_blk = put(pl->image, pl->grp_blk.data(), pl->grp_blk.size());
+        pl->o_own_J = put(pl->image, pl->own_J.data(), pl->own_J.size());
+        pl->o_own_pos = put(pl->image, pl->own_pos.data(), pl->own_pos.size());
+        pl->o_rowpos = put(pl->image, pl->rowpos.data(), pl->rowpos.size());
         for (auto &ch : pl->chunks) {
             ch.o_meta = put(pl->image, ch.meta.data(), ch.meta.size());
             ch.o_subst = put(pl->image, ch.t_subst.data(), ch.t_subst.size());

@@ -12,7 +12,7 @@
 struct HostChunk {
     std::vector<SubMeta> meta;
     std::vector<uint32_t> t_subst, t_conv, t_ns, t_ns64, t_rows;
-    int32_t max_m = 0, max_np = 0;
+    int32_t max_m = 0, max_np = 0, max_own = 1;
     size_t n_ns_real = 0, n_ns64_real = 0;   // task counts before padding
     size_t ws_used = 0;       // bytes of the workspace this chunk uses
     size_t off_ctl = 0;       // workspace offset of the SubCtl array
@@ -28,6 +28,13 @@ struct nolsm_plan {
     std::vector<int32_t> sub_ptr, sub_blk, self_pos, scatter_pos;
     int32_t m_min = 0, m_max = 0;
     double sum_n3 = 0.0;
+    // submatrices: groups of molecules (one per molecule unless combined).
+    // Group g: row blocks grp_blk[grp_ptr[g] ..) and owned molecules
+    // own_J[own_ptr[g] ..); own_pos: position of each owned molecule's block
+    // in its group's rows; rowpos[sub_ptr[J] + a]: position of N(J)_a there.
+    std::vector<int32_t> grp_ptr, grp_blk, own_ptr, own_J, own_pos, rowpos;
+    int32_t g_m_max = 0;
+    double sum_gn3 = 0.0;
 
     // configuration
     bool configured = false;
@@ -38,7 +45,7 @@ struct nolsm_plan {
     std::vector<HostChunk> chunks;
     std::vector<char> image;              // metadata image uploaded by bind
     size_t o_Krp = 0, o_Kci = 0, o_Srp = 0, o_Sci = 0, o_sub_ptr = 0, o_sub_blk = 0,
-           o_self = 0, o_scatter = 0;
+           o_self = 0, o_scatter = 0, o_grp_blk = 0, o_own_J = 0, o_own_pos = 0, o_rowpos = 0;
     void *d_meta = nullptr;
     int device = -1;
     int32_t pgrid = 512;      // persistent-launch grid (2 x CUs), set by bind
@@ -52,7 +59,8 @@ struct nolsm_plan {
 };
 
 // Internal helpers implemented in plan.cpp
-size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_iter, int32_t inverse);
+size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_iter, int32_t inverse,
+                        int32_t nown);
 int nolsm_ns_tile_for(int32_t prec, int32_t np, uint64_t small_mask);
 int nolsm_elem_for(int32_t prec);
 void nolsm_set_last_error(const std::string &s);

@@ -58,6 +58,16 @@ class Plan:
                                                      "D_col_idx", "scatter_pos")]))
         return out
 
+    def groups(self):
+        """(grp_ptr, grp_blk, own_ptr, own_J): the submatrices and the
+        molecules each one owns (one per molecule unless combined)."""
+        inf = self.info()
+        ng = inf["ngroups"]
+        out = (np.zeros(ng + 1, np.int32), np.zeros(inf["sum_gm"], np.int32),
+               np.zeros(ng + 1, np.int32), np.zeros(self.nb, np.int32))
+        L.check(L.lib().nolsm_plan_groups(self.h, *[L.i32_ptr(a) for a in out]))
+        return out
+
     def configure(self, opts, ws_bytes):
         mb = C.c_size_t(0)
         L.check(L.lib().nolsm_plan_configure(self.h, C.byref(opts), int(ws_bytes), C.byref(mb)))
@@ -86,12 +96,13 @@ class Solver:
     workspace, metadata and outputs as torch tensors, runs nolsm_sign_batch."""
 
     def __init__(self, system, prec="fp64", device="cuda:0", ws_bytes=None, ws_budget=48 << 30,
-                 **opt_kw):
+                 combine=False, **opt_kw):
         torch = _torch()
         K, S = system.K, system.S
         self.device = torch.device(device)
         self.nb, self.bs = K.nb, K.bs
-        self.plan = Plan(K.nb, K.bs, K.row_ptr, K.col_idx, S.row_ptr, S.col_idx)
+        self.plan = Plan(K.nb, K.bs, K.row_ptr, K.col_idx, S.row_ptr, S.col_idx,
+                         flags=L.PLAN_COMBINE if combine else 0)
         self.opts = L.default_opts(prec, **opt_kw)
         full = self.plan.info()
         # first configure with the budget to learn the full size

@@ -155,3 +155,38 @@ def test_bad_options_rejected(L, config1):
         with pytest.raises(NolsmError) as e:
             p.configure(opts, 1 << 40)
         assert e.value.code == L.E_ARG
+
+
+def _chain_pattern(nb):
+    ptr, idx = [0], []
+    for J in range(nb):
+        idx.extend(I for I in (J - 1, J, J + 1) if 0 <= I < nb)
+        ptr.append(len(idx))
+    return np.array(ptr, np.int32), np.array(idx, np.int32)
+
+
+def test_combination_equals_oracle(L, config1):
+    # integer work: the library's groups must equal the oracle's exactly
+    import synth
+    from oracle import combine as cb
+    from paper_2104_08245_amd import Plan
+    cases = [("chain", 5, *_chain_pattern(5)), ("blockdiag", 8, np.arange(9, dtype=np.int32),
+                                                  np.arange(8, dtype=np.int32))]
+    slab = synth.water_slab(config_id=104, r_c=0.9, n_dense=96, n_dilute=96,
+                            box=np.array([2.0, 2.0, 6.0]), z_split=1.4)
+    for name, s in (("config1", config1), ("slab", slab)):
+        cases.append((name, s.K.nb, s.K.row_ptr, s.K.col_idx))
+    for name, nb, rp, ci in cases:
+        p = Plan(nb, 6, rp, ci, flags=L.PLAN_COMBINE)
+        got = p.groups()
+        ex = p.export()
+        want = cb.combine_groups(nb, ex["sub_ptr"], ex["sub_blk"])
+        for a, b in zip(got, want):
+            assert np.array_equal(a, b), name
+        inf = p.info()
+        assert inf["ngroups"] == len(want[0]) - 1
+        assert inf["sum_gn3"] == cb.cubic_cost(want[0]) * 216.0
+    # without the flag every molecule is its own submatrix
+    p = Plan(config1.K.nb, 6, config1.K.row_ptr, config1.K.col_idx)
+    g = p.groups()
+    assert np.array_equal(g[2], np.arange(config1.K.nb + 1)) and np.array_equal(g[3], np.arange(config1.K.nb))
