@@ -52,10 +52,12 @@ __device__ __forceinline__ TV vec_in(const SkinnyArgs &a, const SubMeta &M, cons
     return v;
 }
 
-// out = P * in for 256 rows per workgroup, one row per lane. The input block
-// (n x bs, formed from up to two stored vectors) is staged once per
-// workgroup in LDS and read as a broadcast; each lane streams its row of P
-// with 16-byte loads, so the kernel is a plain HBM stream of P.
+// out = P * in for 256 rows per workgroup, one row per lane, one workgroup
+// per (row block, owned molecule). The input block (n x bs, formed from up to
+// two stored vectors) is staged once per workgroup in LDS and read as a
+// broadcast; each lane streams its row of P with 16-byte loads, so the kernel
+// is a plain HBM stream of P. The owned molecules of one row block are
+// adjacent in the task list and share P through the L2 of their XCD.
 // Dynamic LDS: max_np x 6 values of TV.
 template <typename TP, typename TV>
 __global__ __launch_bounds__(256) void k_skinny(ChunkDev cd, char *ws, SkinnyArgs sa, int bs) {
@@ -65,10 +67,10 @@ __global__ __launch_bounds__(256) void k_skinny(ChunkDev cd, char *ws, SkinnyArg
     TV *vin = (TV *)skm;
     const uint32_t task = xcd_task(cd.t_rows);
     if (task == NOLSM_TASK_NONE) return;
-    const int s = task_slot(task), rq = task_a(task), o = blockIdx.y;
+    const int s = task_slot(task), rq = task_a(task), o = task_b(task);
     const SubMeta M = cd.meta[s];
     const SubCtl *ctl = cd.ctl + s;
-    if (ctl->status == NOLSM_MOL_NOT_SPD || o >= M.nown) return;
+    if (ctl->status == NOLSM_MOL_NOT_SPD) return;
     const int np = M.np, t = threadIdx.x;
     const int K = ctl->iters;
     const ST *P = (const ST *)(ws + ((K & 1) ? M.offX1 : M.offL));
@@ -108,7 +110,7 @@ template <typename TP, typename TV>
 static hipError_t run_finish(const ChunkDev &cd, char *ws, int nfinal, int bs, hipStream_t st) {
     auto L = [&](int ina, int inb, double al, double be, int out, int save) {
         SkinnyArgs a{ina, inb, al, be, out, save};
-        hipLaunchKernelGGL((k_skinny<TP, TV>), dim3(cd.n_rows, cd.max_own), dim3(256),
+        hipLaunchKernelGGL((k_skinny<TP, TV>), dim3(cd.n_rows), dim3(256),
                            (size_t)cd.max_np * 6 * sizeof(TV), st, cd, ws, a, bs);
         return hipGetLastError();
     };
@@ -252,16 +254,16 @@ __global__ __launch_bounds__(256) void k_extract(ChunkDev cd, char *ws, ExtractA
 // (A_J + mu I) Dcols_J: one n x n by n x bs product with the FP64 A_J still in
 // the workspace, on the whole submatrix column block of the molecule (kept by
 // the extraction) and written back on the rows N(J). One row per lane, 256
-// rows per workgroup, grid.y = owned molecule; the column block is staged in
-// LDS (max_np x bs doubles). NOT_SPD molecules get zeros.
+// rows per workgroup, one workgroup per (row block, owned molecule); the
+// column block is staged in LDS (max_np x bs doubles). NOT_SPD molecules get
+// zeros.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_wcols(ChunkDev cd, char *ws, ExtractArgs ea) {
     extern __shared__ __attribute__((aligned(16))) double dcs[];
     const uint32_t task = xcd_task(cd.t_rows);
     if (task == NOLSM_TASK_NONE) return;
-    const int s = task_slot(task), rq = task_a(task), o = blockIdx.y;
+    const int s = task_slot(task), rq = task_a(task), o = task_b(task);
     const SubMeta M = cd.meta[s];
-    if (o >= M.nown) return;
     const int n = M.n, np = M.np, bs = ea.bs, t = threadIdx.x;
     const int J = ea.own_J[M.own_off + o];
     const int so = ea.sub_ptr[J], mJ = ea.sub_ptr[J + 1] - so;
@@ -298,7 +300,7 @@ __global__ __launch_bounds__(256) void k_wcols(ChunkDev cd, char *ws, ExtractArg
 
 hipError_t launch_wcols(const ChunkDev &cd, char *ws, const ExtractArgs &ea, hipStream_t st) {
     if (ea.bs & 1) return hipErrorInvalidValue;   // the row loop takes k in pairs
-    hipLaunchKernelGGL(k_wcols, dim3(cd.n_rows, cd.max_own), dim3(256), (size_t)cd.max_np * ea.bs * 8, st, cd, ws,
+    hipLaunchKernelGGL(k_wcols, dim3(cd.n_rows), dim3(256), (size_t)cd.max_np * ea.bs * 8, st, cd, ws,
                        ea);
     return hipGetLastError();
 }

@@ -84,7 +84,7 @@ struct ChunkDev {
     const uint32_t *t_conv;    // (slot, 64x64 tile i, j) for X_0
     const uint32_t *t_ns;      // (slot, NS tile i, j): 64x64 (FP64/FP32) or 128x128 (FP16/BF16) tiles
     const uint32_t *t_ns64;    // FP16/BF16 slots that use 64x64 tiles
-    const uint32_t *t_rows;    // (slot, 256-row block) for the skinny products
+    const uint32_t *t_rows;    // (slot, 256-row block, owned molecule) for the skinny products
     SubCtl *ctl;               // in the workspace
     InvCtl *ictl;              // in the workspace (coupled inverse), else null
     int32_t *queues;           // persistent launches: [max_iter][2][2][8] counters

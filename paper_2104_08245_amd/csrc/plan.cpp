@@ -516,7 +516,11 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
                     (T == 64 && (pl->prec == NOLSM_FP16 || pl->prec == NOLSM_BF16)) ? ch.t_ns64 : ch.t_ns;
                 for (int32_t a = 0; a < nt; ++a)
                     for (int32_t b = 0; b < nt; ++b) tl.push_back(NOLSM_TASK(s, a, b));
-                for (int32_t a = 0; a < (m.P + 3) / 4; ++a) ch.t_rows.push_back(NOLSM_TASK(s, a, 0));
+                // (slot, 256-row block, owned molecule): the molecules of one row
+                // block are adjacent, so they run together on one XCD and share
+                // the streamed rows through its L2
+                for (int32_t a = 0; a < (m.P + 3) / 4; ++a)
+                    for (int32_t o = 0; o < m.nown; ++o) ch.t_rows.push_back(NOLSM_TASK(s, a, o));
             }
             ch.ws_used = off;
             ch.n_ns_real = ch.t_ns.size();
