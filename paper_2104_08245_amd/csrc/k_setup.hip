@@ -105,52 +105,96 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
 // submatrix. Also stores the inverses of the diagonal tiles (used as GEMMs
 // by the substitution). A non-positive pivot marks the molecule NOT_SPD.
 // ---------------------------------------------------------------------------
-__device__ void potrf64_lds(double (*D)[LDP], int *fail) {
-    const int t = threadIdx.x;
+// Cholesky of the 64x64 diagonal tile in LDS (lower part read), right-looking
+// by columns with the entries in registers: thread t holds column q = t % 64,
+// rows r = w + 4i (w = t / 64, i = 0..15). After step c the owners of column
+// c + 1 publish it (updated through step c) in cb[(c + 1) % 2], so one
+// barrier per column suffices: a buffer is rewritten only after every thread
+// has passed the barrier that follows its last read. The factor L (zeros
+// above the diagonal) is written back to D. A non-positive pivot sets *fail.
+__device__ void potrf64_reg(double (*D)[LDP], double (*cb)[64], int *fail) {
+    const int t = threadIdx.x, q = t & 63, w = t >> 6;
+    double v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = D[w + 4 * i][q];
+    if (q == 0)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) cb[0][w + 4 * i] = v[i];
+    __syncthreads();
     for (int c = 0; c < 64; ++c) {
-        if (t == 0) {
-            const double d = D[c][c];
-            if (!(d > 0.0)) *fail = 1;
-            D[c][c] = sqrt(fmax(d, 1e-300));
+        const double *col = cb[c & 1];
+        const double d = col[c];
+        if (t == 0 && !(d > 0.0)) *fail = 1;
+        const double piv = sqrt(fmax(d, 1e-300));
+        const double rp = 1.0 / piv;
+        const double lq = col[q] * rp;   // L[q][c] for q > c
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = w + 4 * i;
+            const double lr = col[r] * rp;
+            if (q == c) {
+                if (r > c) v[i] = lr;
+                else if (r == c) v[i] = piv;
+            } else if (q > c && r >= q) {
+                v[i] -= lr * lq;
+            }
         }
-        __syncthreads();
-        const double piv = D[c][c];
-        for (int r = c + 1 + t; r < 64; r += 256) D[r][c] /= piv;
-        __syncthreads();
-        // trailing lower update
-        const int rem = 63 - c;
-        for (int f = t; f < rem * rem; f += 256) {
-            const int r = c + 1 + f / rem, q = c + 1 + f % rem;
-            if (q <= r) D[r][q] -= D[r][c] * D[q][c];
-        }
+        if (q == c + 1)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) cb[(c + 1) & 1][w + 4 * i] = v[i];
         __syncthreads();
     }
-    for (int f = t; f < 64 * 64; f += 256) {
-        const int r = f >> 6, q = f & 63;
-        if (q > r) D[r][q] = 0.0;
-    }
-    __syncthreads();
-}
-
-// Dinv = L^-1 for a lower-triangular 64x64 L in LDS; thread c < 64 solves column c.
-__device__ void trinv64_lds(const double (*Lt)[LDP], double (*Di)[LDP]) {
-    const int c = threadIdx.x;
-    if (c < 64) {
-        for (int r = 0; r < c; ++r) Di[r][c] = 0.0;
-        Di[c][c] = 1.0 / Lt[c][c];
-        for (int r = c + 1; r < 64; ++r) {
-            double acc = 0.0;
-            for (int q = c; q < r; ++q) acc += Lt[r][q] * Di[q][c];
-            Di[r][c] = -acc / Lt[r][r];
-        }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int r = w + 4 * i;
+        D[r][q] = (q <= r) ? v[i] : 0.0;
     }
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_chol(ChunkDev cd, char *ws) {
+// Di = L^-1 for the lower-triangular 64x64 L in LDS: forward substitution
+// against the identity, all 64 columns at once, by pivot rows q. Thread t
+// holds column c = t % 64, rows r = w + 4i of the right-hand side B; at step q
+// the owners of row q scale it by 1/L[q][q] (final row q of Di) and publish
+// it, then every row r > q takes off L[r][q] times it. Entries above the
+// diagonal stay exact zeros. rd: 64 doubles of LDS, xb: 2 x 64.
+__device__ void trinv64_reg(const double (*Lt)[LDP], double (*Di)[LDP], double *rd, double (*xb)[64]) {
+    const int t = threadIdx.x, c = t & 63, w = t >> 6;
+    if (t < 64) rd[t] = 1.0 / Lt[t][t];
+    double b[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) b[i] = (w + 4 * i == c) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int q = 0; q < 64; ++q) {
+        const int iq = q >> 2;
+        if (w == (q & 3)) {
+            const double s = rd[q];
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (i == iq) {
+                    b[i] *= s;
+                    xb[q & 1][c] = b[i];
+                }
+        }
+        __syncthreads();
+        const double xq = xb[q & 1][c];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = w + 4 * i;
+            if (r > q) b[i] -= Lt[r][q] * xq;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Di[w + 4 * i][c] = b[i];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256, 2) void k_chol(ChunkDev cd, char *ws) {
+    // two tiles (66.6 KB) plus small buffers: two workgroups fit one CU
     __shared__ double sA[64][LDP];
     __shared__ double sB[64][LDP];
-    __shared__ double sI[64][LDP];
+    __shared__ double cb[2][64];
+    __shared__ double rd[64];
     __shared__ int fail;
     const int s = blockIdx.x;
     if (s >= cd.nsub) return;
@@ -178,19 +222,21 @@ __global__ __launch_bounds__(256) void k_chol(ChunkDev cd, char *ws) {
             if (i == j) {
                 acc2s(sA, acc);
                 __syncthreads();
-                potrf64_lds(sA, &fail);
+                potrf64_reg(sA, cb, &fail);
                 if (fail) break;
-                trinv64_lds(sA, sI);
+                trinv64_reg(sA, sB, rd, cb);
                 s2g_tile(L + (int64_t)(j * 64) * ld + j * 64, ld, sA);
-                s2g_tile(Dinv + (int64_t)j * 4096, 64, sI);
+                s2g_tile(Dinv + (int64_t)j * 4096, 64, sB);
                 __syncthreads();
             } else {
-                // L_ij = acc * L_jj^-T
+                // L_ij = acc * L_jj^-T, with L_jj^-1 read back from the
+                // workspace (written by this workgroup above)
                 acc2s(sA, acc);
+                g2s_tile(sB, Dinv + (int64_t)j * 4096, 64);
                 __syncthreads();
                 Acc64 o;
                 acc_zero(o);
-                mma64<false, true>(o, sA, sI);
+                mma64<false, true>(o, sA, sB);
                 __syncthreads();
                 acc2s(sB, o);
                 __syncthreads();
@@ -209,7 +255,8 @@ __global__ __launch_bounds__(256) void k_chol(ChunkDev cd, char *ws) {
 // ---------------------------------------------------------------------------
 // Substitution for one 64-column tile cc of [K | E]: W = L^-1 B (forward),
 // then [A | Y] = L^-T W (backward), in place in the K buffer; mu is taken
-// off A's diagonal. For cc < P it also emits the |A| row sums of the tile,
+// off A's diagonal once the column tile is complete (the backward recursion
+// needs the unshifted rows). For cc < P it also emits the |A| row sums of the tile,
 // the complete |A| column sums and a partial Frobenius sum (bounds inputs).
 // Task list: (slot, cc), cc = 0..P (P is the E tile).
 // ---------------------------------------------------------------------------
@@ -280,27 +327,28 @@ __global__ __launch_bounds__(256) void k_subst(ChunkDev cd, char *ws) {
         acc2s(sB, o);
         __syncthreads();
         if (cc < P) {
-            if (i == cc && threadIdx.x < 64) sB[threadIdx.x][threadIdx.x] -= mu;
-            __syncthreads();
+            // bounds inputs of A_J - mu I; the tile itself is stored without
+            // the shift, since the rows above still substitute with it
+            auto a = [&](int r, int c) { return sB[r][c] - ((i == cc && r == c) ? mu : 0.0); };
             const int t = threadIdx.x;
             if (t < 64) {
                 const int gr = i * 64 + t;
                 double rs = 0.0;
                 for (int c = 0; c < 64; ++c)
-                    if (cc * 64 + c < n) rs += fabs(sB[t][c]);
+                    if (cc * 64 + c < n) rs += fabs(a(t, c));
                 double *rowp = (double *)(ws + M.offRow);
                 rowp[(int64_t)cc * np + gr] = (gr < n) ? rs : 0.0;
             } else if (t < 128) {
                 const int c = t - 64;
                 for (int r = 0; r < 64; ++r)
-                    if (i * 64 + r < n) colsum += fabs(sB[r][c]);
+                    if (i * 64 + r < n) colsum += fabs(a(r, c));
             }
             {
                 // Frobenius partial: 16 entries per thread
                 double fs = 0.0;
                 for (int f = t; f < 4096; f += 256) {
                     const int r = f >> 6, c = f & 63;
-                    if (i * 64 + r < n && cc * 64 + c < n) fs += sB[r][c] * sB[r][c];
+                    if (i * 64 + r < n && cc * 64 + c < n) fs += a(r, c) * a(r, c);
                 }
                 frob += fs;
             }
@@ -309,6 +357,8 @@ __global__ __launch_bounds__(256) void k_subst(ChunkDev cd, char *ws) {
         __syncthreads();
     }
     if (cc < P) {
+        // the whole column tile is final: take mu off the diagonal of A_J
+        if (threadIdx.x < 64) Kb[(int64_t)(cc * 64 + threadIdx.x) * ldk + cc * 64 + threadIdx.x] -= mu;
         double *colp = (double *)(ws + M.offCol);
         const int t = threadIdx.x;
         if (t >= 64 && t < 128) {

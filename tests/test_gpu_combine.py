@@ -160,3 +160,15 @@ def test_not_spd_marks_every_owned_molecule(torch, config1):
     say(f"poisoned molecule 5 sits in a group owning {sorted(owned)}")
     for J in range(config1.nmol):
         assert (st["status"][J] != 0) == (J in owned)
+
+
+def test_fp64_combined_nonzero_mu(torch, config1):
+    sv = solve(config1, "fp64")
+    g = sv.plan.groups()
+    ref = o.nolsm_groups(config1, g, mu=0.25)
+    sv.run(mu=0.25)
+    torch.cuda.synchronize()
+    dc = sv.host_dcols()
+    worst = max(rel(dc[J], ref.Dcols[J]) for J in range(config1.nmol))
+    say("fp64 combined mu=0.25 worst rel-F", worst)
+    assert worst <= 1e-10

@@ -91,3 +91,16 @@ def test_coupled_inverse_flags_indefinite_overlap(torch, config1):
     assert st["status"][3] != 0
     ok = np.arange(config1.nmol) != 3
     assert np.all(st["status"][ok] == 0)
+
+
+def test_coupled_inverse_route_nonzero_mu(torch, config1):
+    from paper_2104_08245_amd import Solver, _lib as L
+    ref = o.nolsm(config1, mu=0.25)
+    sv = Solver(config1, prec="fp16", device="cuda:0", inverse=L.INV_COUPLED_NS)
+    sv.run(mu=0.25)
+    torch.cuda.synchronize()
+    assert np.all(sv.host_stats()["status"] == 0)
+    dc = sv.host_dcols()
+    errs = np.array([rel(dc[J], ref.Dcols[J]) for J in range(config1.nmol)])
+    say(f"fp16 coupled-NS mu=0.25: Dcols rel-F max {errs.max():.3e}")
+    assert errs.max() <= BOUNDS["fp16"]

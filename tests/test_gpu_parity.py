@@ -283,3 +283,38 @@ def test_config2_sample_fp64(torch):
     # properties that hold for every molecule at full size
     assert np.all(st["resid"] < 1e-10)
     assert abs(st["trace_SD"].sum() / s.nmol - 4.0) < 0.05
+
+
+@pytest.mark.parametrize("mu", [0.25, -0.15])
+def test_fp64_nonzero_mu_matches_oracle(torch, config1, mu):
+    # mu inside the gap but away from 0: A_J - mu I differs from A_J on the
+    # diagonal of every column tile, which the substitution must apply only
+    # after the rows above have used the unshifted tile
+    ref = o.nolsm(config1, mu=mu)
+    sv = solve(config1, "fp64")
+    sv.run(mu=mu)
+    torch.cuda.synchronize()
+    st = sv.host_stats()
+    assert np.all(st["status"] == 0)
+    dc = sv.host_dcols()
+    worst = max(rel(dc[J], ref.Dcols[J]) for J in range(config1.nmol))
+    say(f"fp64 mu={mu} worst rel-F", worst)
+    assert worst <= 1e-10
+    assert rel(sv.host_D(), ref.D_val) <= 1e-10
+    assert np.allclose(st["trace_SD"], ref.N, rtol=0, atol=1e-10)
+    assert np.allclose(st["energy_KD"], ref.E, rtol=0, atol=1e-10)
+
+
+def test_fp16_nonzero_mu_within_stated_error(torch, config1):
+    ref = o.nolsm(config1, mu=0.25)
+    sv = solve(config1, "fp16")
+    sv.run(mu=0.25)
+    torch.cuda.synchronize()
+    st = sv.host_stats()
+    assert np.all(st["status"] == 0)
+    dc = sv.host_dcols()
+    errs = np.array([rel(dc[J], ref.Dcols[J]) for J in range(config1.nmol)])
+    de = np.abs(st["energy_KD"] - ref.E)
+    say(f"fp16 mu=0.25: Dcols rel-F max {errs.max():.3e}; |dE_J| max {de.max():.3e}")
+    assert errs.max() <= MIXED["fp16"]["dcols"]
+    assert de.max() <= MIXED["fp16"]["energy"]

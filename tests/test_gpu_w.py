@@ -95,3 +95,17 @@ def test_w_not_spd_molecule_is_zero(torch, config1):
     wc = sv.host_dcols("W")
     assert np.all(wc[3] == 0.0)
     assert np.all(np.isfinite(np.concatenate([w.ravel() for w in wc])))
+
+
+def test_w_fp64_nonzero_mu(torch, config1):
+    # W = (A_J + mu I) Dcols_J: the shift enters twice (in A_J and added back)
+    ref = o.nolsm(config1, mu=0.25, want_w=True)
+    from paper_2104_08245_amd import Solver
+    sv = Solver(config1, prec="fp64", device="cuda:0")
+    sv.want_w()
+    sv.run(mu=0.25)
+    torch.cuda.synchronize()
+    wc = sv.host_dcols("W")
+    worst = max(rel(wc[J], ref.Wcols[J]) for J in range(config1.nmol))
+    say("W fp64 mu=0.25 worst rel-F", worst)
+    assert worst <= 1e-9
