@@ -125,6 +125,16 @@ __device__ __forceinline__ void s2acc(Acc64 &a, const double (*s)[LDP]) {
             for (int e = 0; e < 4; ++e) a.c[i][j][e] = s[acc_row(i, e)][acc_col(j)];
 }
 
+// global tile (ld doubles per row) straight into the accumulator layout
+__device__ __forceinline__ void g2acc(Acc64 &a, const double *g, int64_t ld) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) a.c[i][j][e] = g[(int64_t)acc_row(i, e) * ld + acc_col(j)];
+}
+
 // deterministic block reductions (256 threads); `red` is LDS scratch of 256
 __device__ __forceinline__ double block_sum(double v, double *red) {
     const int t = threadIdx.x;

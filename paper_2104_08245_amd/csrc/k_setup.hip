@@ -256,11 +256,17 @@ __global__ __launch_bounds__(256, 2) void k_chol(ChunkDev cd, char *ws) {
 // Substitution for one 64-column tile cc of [K | E]: W = L^-1 B (forward),
 // then [A | Y] = L^-T W (backward), in place in the K buffer; mu is taken
 // off A's diagonal once the column tile is complete (the backward recursion
-// needs the unshifted rows). For cc < P it also emits the |A| row sums of the tile,
-// the complete |A| column sums and a partial Frobenius sum (bounds inputs).
-// Task list: (slot, cc), cc = 0..P (P is the E tile).
+// needs the unshifted rows). For cc < P it also emits the |A| row sums of the
+// tile, the complete |A| column sums and a partial Frobenius sum (bounds
+// inputs). Task list: (slot, cc), cc = 0..P (P is the E tile).
+// SUBST_R row tiles are solved per pass with their accumulators in registers,
+// so each finished tile of the column is read back once per pass rather than
+// once per row tile below it (the L tiles are shared through L2 by the P + 1
+// column tasks of a submatrix, which are adjacent in the task list).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_subst(ChunkDev cd, char *ws) {
+#define SUBST_R 4
+
+__global__ __launch_bounds__(256, 2) void k_subst(ChunkDev cd, char *ws) {
     const double mu = ((const WsHeader *)ws)->mu;
     __shared__ double sA[64][LDP];
     __shared__ double sB[64][LDP];
@@ -276,85 +282,126 @@ __global__ __launch_bounds__(256) void k_subst(ChunkDev cd, char *ws) {
     const double *Dinv = (const double *)(ws + M.offDinv);
     double *Kb = (double *)(ws + M.offK);
     const int col0 = (cc < P) ? cc * 64 : np;
+    auto Lt = [&](int r, int c) { return L + (int64_t)(r * 64) * ldl + c * 64; };
+    auto Bt = [&](int r) { return Kb + (int64_t)(r * 64) * ldk + col0; };
     // forward: W_i = Dinv_i (B_i - sum_{k<i} L_ik W_k)
-    for (int i = 0; i < P; ++i) {
-        Acc64 acc;
-        g2s_tile(sA, Kb + (int64_t)(i * 64) * ldk + col0, ldk);
-        __syncthreads();
-        s2acc(acc, sA);
-        __syncthreads();
-        for (int k = 0; k < i; ++k) {
-            g2s_tile(sA, L + (int64_t)(i * 64) * ldl + k * 64, ldl);
-            g2s_tile(sB, Kb + (int64_t)(k * 64) * ldk + col0, ldk);
-            __syncthreads();
-            mma64<false, false>(acc, sA, sB, -1.0);
-            __syncthreads();
-        }
-        acc2s(sB, acc);
-        g2s_tile(sA, Dinv + (int64_t)i * 4096, 64);
-        __syncthreads();
-        Acc64 o;
-        acc_zero(o);
-        mma64<false, false>(o, sA, sB);
-        __syncthreads();
-        acc2s(sB, o);
-        __syncthreads();
-        s2g_tile(Kb + (int64_t)(i * 64) * ldk + col0, ldk, sB);
-        __syncthreads();
-    }
-    // backward: A_i = Dinv_i^T (W_i - sum_{k>i} L_ki^T A_k)
-    double colsum = 0.0, frob = 0.0;
-    for (int i = P - 1; i >= 0; --i) {
-        Acc64 acc;
-        g2s_tile(sA, Kb + (int64_t)(i * 64) * ldk + col0, ldk);
-        __syncthreads();
-        s2acc(acc, sA);
-        __syncthreads();
-        for (int k = i + 1; k < P; ++k) {
-            g2s_tile(sA, L + (int64_t)(k * 64) * ldl + i * 64, ldl);
-            g2s_tile(sB, Kb + (int64_t)(k * 64) * ldk + col0, ldk);
-            __syncthreads();
-            mma64<true, false>(acc, sA, sB, -1.0);
-            __syncthreads();
-        }
-        acc2s(sB, acc);
-        g2s_tile(sA, Dinv + (int64_t)i * 4096, 64);
-        __syncthreads();
-        Acc64 o;
-        acc_zero(o);
-        mma64<true, false>(o, sA, sB);
-        __syncthreads();
-        acc2s(sB, o);
-        __syncthreads();
-        if (cc < P) {
-            // bounds inputs of A_J - mu I; the tile itself is stored without
-            // the shift, since the rows above still substitute with it
-            auto a = [&](int r, int c) { return sB[r][c] - ((i == cc && r == c) ? mu : 0.0); };
-            const int t = threadIdx.x;
-            if (t < 64) {
-                const int gr = i * 64 + t;
-                double rs = 0.0;
-                for (int c = 0; c < 64; ++c)
-                    if (cc * 64 + c < n) rs += fabs(a(t, c));
-                double *rowp = (double *)(ws + M.offRow);
-                rowp[(int64_t)cc * np + gr] = (gr < n) ? rs : 0.0;
-            } else if (t < 128) {
-                const int c = t - 64;
-                for (int r = 0; r < 64; ++r)
-                    if (i * 64 + r < n) colsum += fabs(a(r, c));
-            }
-            {
-                // Frobenius partial: 16 entries per thread
-                double fs = 0.0;
-                for (int f = t; f < 4096; f += 256) {
-                    const int r = f >> 6, c = f & 63;
-                    if (i * 64 + r < n && cc * 64 + c < n) fs += a(r, c) * a(r, c);
+    for (int i0 = 0; i0 < P; i0 += SUBST_R) {
+        const int nr = min(SUBST_R, P - i0);
+        Acc64 acc[SUBST_R];
+#pragma unroll
+        for (int r = 0; r < SUBST_R; ++r)
+            if (r < nr) g2acc(acc[r], Bt(i0 + r), ldk);
+        for (int k = 0; k < i0; ++k) {
+            g2s_tile(sB, Bt(k), ldk);
+#pragma unroll
+            for (int r = 0; r < SUBST_R; ++r) {
+                if (r < nr) {
+                    g2s_tile(sA, Lt(i0 + r, k), ldl);
+                    __syncthreads();
+                    mma64<false, false>(acc[r], sA, sB, -1.0);
+                    __syncthreads();
                 }
-                frob += fs;
             }
         }
-        s2g_tile(Kb + (int64_t)(i * 64) * ldk + col0, ldk, sB);
-        __syncthreads();
+        // the diagonal block of the pass, in order
+#pragma unroll
+        for (int r = 0; r < SUBST_R; ++r) {
+            if (r < nr) {
+                const int i = i0 + r;
+                acc2s(sB, acc[r]);
+                g2s_tile(sA, Dinv + (int64_t)i * 4096, 64);
+                __syncthreads();
+                Acc64 o;
+                acc_zero(o);
+                mma64<false, false>(o, sA, sB);
+                __syncthreads();
+                acc2s(sB, o);
+                __syncthreads();
+                s2g_tile(Bt(i), ldk, sB);   // W_i, kept in sB for the rows below
+#pragma unroll
+                for (int r2 = r + 1; r2 < SUBST_R; ++r2) {
+                    if (r2 < nr) {
+                        g2s_tile(sA, Lt(i0 + r2, i), ldl);
+                        __syncthreads();
+                        mma64<false, false>(acc[r2], sA, sB, -1.0);
+                        __syncthreads();
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    // backward: A_i = Dinv_i^T (W_i - sum_{k>i} L_ki^T A_k), passes from the bottom
+    double colsum = 0.0, frob = 0.0;
+    for (int i1 = P - 1; i1 >= 0; i1 -= SUBST_R) {
+        const int nr = min(SUBST_R, i1 + 1);   // rows i1 - r, r < nr
+        Acc64 acc[SUBST_R];
+#pragma unroll
+        for (int r = 0; r < SUBST_R; ++r)
+            if (r < nr) g2acc(acc[r], Bt(i1 - r), ldk);
+        for (int k = i1 + 1; k < P; ++k) {
+            g2s_tile(sB, Bt(k), ldk);   // A_k, unshifted
+#pragma unroll
+            for (int r = 0; r < SUBST_R; ++r) {
+                if (r < nr) {
+                    g2s_tile(sA, Lt(k, i1 - r), ldl);
+                    __syncthreads();
+                    mma64<true, false>(acc[r], sA, sB, -1.0);
+                    __syncthreads();
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < SUBST_R; ++r) {
+            if (r < nr) {
+                const int i = i1 - r;
+                acc2s(sB, acc[r]);
+                g2s_tile(sA, Dinv + (int64_t)i * 4096, 64);
+                __syncthreads();
+                Acc64 o;
+                acc_zero(o);
+                mma64<true, false>(o, sA, sB);
+                __syncthreads();
+                acc2s(sB, o);
+                __syncthreads();
+                if (cc < P) {
+                    // bounds inputs of A_J - mu I; the tile itself is stored
+                    // without the shift, since the rows above still use it
+                    auto a = [&](int rr, int c) { return sB[rr][c] - ((i == cc && rr == c) ? mu : 0.0); };
+                    const int t = threadIdx.x;
+                    if (t < 64) {
+                        const int gr = i * 64 + t;
+                        double rs = 0.0;
+                        for (int c = 0; c < 64; ++c)
+                            if (cc * 64 + c < n) rs += fabs(a(t, c));
+                        double *rowp = (double *)(ws + M.offRow);
+                        rowp[(int64_t)cc * np + gr] = (gr < n) ? rs : 0.0;
+                    } else if (t < 128) {
+                        const int c = t - 64;
+                        for (int rr = 0; rr < 64; ++rr)
+                            if (i * 64 + rr < n) colsum += fabs(a(rr, c));
+                    }
+                    // Frobenius partial: 16 entries per thread
+                    double fs = 0.0;
+                    for (int f = t; f < 4096; f += 256) {
+                        const int rr = f >> 6, c = f & 63;
+                        if (i * 64 + rr < n && cc * 64 + c < n) fs += a(rr, c) * a(rr, c);
+                    }
+                    frob += fs;
+                }
+                s2g_tile(Bt(i), ldk, sB);   // A_i, kept in sB for the rows above
+#pragma unroll
+                for (int r2 = r + 1; r2 < SUBST_R; ++r2) {
+                    if (r2 < nr) {
+                        g2s_tile(sA, Lt(i, i1 - r2), ldl);
+                        __syncthreads();
+                        mma64<true, false>(acc[r2], sA, sB, -1.0);
+                        __syncthreads();
+                    }
+                }
+                __syncthreads();
+            }
+        }
     }
     if (cc < P) {
         // the whole column tile is final: take mu off the diagonal of A_J
