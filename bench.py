@@ -178,8 +178,9 @@ def main():
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB "
                          "(reference for the FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--inverse", default="cholesky", choices=["cholesky", "coupled_ns"],
-                    help="route to T_J(S)^-1: FP64 Cholesky, or the coupled Newton-Schulz "
+    ap.add_argument("--inverse", default="auto", choices=["auto", "cholesky", "cholesky_fp32", "coupled_ns"],
+                    help="route to T_J(S)^-1: FP64 Cholesky, Cholesky with FP32 arithmetic "
+                         "(16-bit only; their default), or the coupled Newton-Schulz "
                          "iteration in the NS precision (16-bit only)")
     ap.add_argument("--want-w", action="store_true",
                     help="also compute the energy-weighted density matrix columns each step")
@@ -224,7 +225,10 @@ def main():
     sched = {"graph": L.SCHED_GRAPH, "stream": L.SCHED_STREAM, "bucket": L.SCHED_PER_BUCKET,
              "persistent": L.SCHED_PERSISTENT}[args.sched]
     dev = torch.device("cuda:0")
-    inv = L.INV_COUPLED_NS if args.inverse == "coupled_ns" else L.INV_CHOLESKY
+    if args.inverse == "auto":
+        args.inverse = "cholesky_fp32" if args.prec in ("fp16", "bf16") else "cholesky"
+    inv = {"cholesky": L.INV_CHOLESKY, "cholesky_fp32": L.INV_CHOLESKY_FP32,
+           "coupled_ns": L.INV_COUPLED_NS}[args.inverse]
     sv = Solver(system, prec=args.prec, device=dev, ws_budget=int(args.ws_gb * (1 << 30)), sched=sched,
                 inverse=inv, combine=args.combine)
     if args.want_w:
@@ -288,10 +292,11 @@ def main():
     phases = {k: round(v, 2) for k, v in prof.items()
               if k.startswith("ms_") and (k != "ms_wmat" or args.want_w)
               and (k != "ms_inverse" or args.inverse == "coupled_ns")
-              and (k not in ("ms_chol", "ms_subst") or args.inverse == "cholesky")}
+              and (k not in ("ms_chol", "ms_subst") or args.inverse != "coupled_ns")}
     # composite bound: each phase's algorithmic work at its own peak (NS GEMMs
     # on the MFMA peak of the precision, finishing products at the FP32 peak,
-    # the FP64 Cholesky + solves at the FP64 peak, the gather at 8 TB/s)
+    # the Cholesky + solves at the FP64 or FP32 peak of their route, the
+    # gather at 8 TB/s)
     m = n / 6.0
     setup_flops = float((n ** 3 / 3.0 + 2.0 * n ** 3 + 12.0 * n ** 2).sum())
     gather_bytes = float((576.0 * m ** 2 + 288.0 * m).sum())
@@ -299,6 +304,8 @@ def main():
              "gather_scatter": gather_bytes / 8e12}
     if args.inverse == "coupled_ns":
         terms["inverse"] = inv_flops / (peak * 1e12)
+    elif args.inverse == "cholesky_fp32":
+        terms["setup_fp32"] = setup_flops / 157.3e12
     else:
         terms["setup_fp64"] = setup_flops / 78.6e12
     t_bound = sum(terms.values())

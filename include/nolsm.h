@@ -98,8 +98,9 @@ typedef enum {
 /* How T_J(S)^-1 is applied when forming A_J = T_J(S)^-1 T_J(K) - mu I and
  * Y_J = T_J(S)^-1 E_cJ. */
 typedef enum {
-    NOLSM_INV_CHOLESKY = 0,        /* FP64 Cholesky factor and substitution      */
-    NOLSM_INV_COUPLED_NS = 1       /* FP16/BF16 only: the coupled Newton-Schulz
+    NOLSM_INV_CHOLESKY = 0,        /* FP64 Cholesky factor and substitution
+                                      (default for FP64 / FP32)                 */
+    NOLSM_INV_COUPLED_NS = 1,      /* FP16/BF16 only: the coupled Newton-Schulz
                                       iteration of Eq. inv1-inv3 on the matrix
                                       cores (FP32 accumulation): Y_0 = c S_J,
                                       Z_0 = I, R_k = I - Z_k Y_k,
@@ -112,6 +113,12 @@ typedef enum {
                                       S^-1 K_J - mu I by two more GEMMs, with
                                       c = 1 / max row sum of |S_J|. A diverging
                                       iteration marks the molecule NOT_SPD.   */
+    NOLSM_INV_CHOLESKY_FP32 = 2    /* FP16/BF16 only (their default): the same
+                                      Cholesky factor and substitution with FP32
+                                      arithmetic on the matrix cores, FP64
+                                      storage; its relative error, about
+                                      kappa(S_J) 2^-24, stays far below the
+                                      16-bit floor of the sign iteration.      */
 } nolsm_inverse;
 
 typedef struct {
@@ -150,7 +157,8 @@ typedef struct {
                                 P = (I - sign A_J)/2 a projector commuting with
                                 A_J. Zero for NOT_SPD molecules. Null: skipped.
                                 Assemble W with nolsm_assemble_D.                */
-    int32_t inverse;         /* nolsm_inverse (default NOLSM_INV_CHOLESKY)       */
+    int32_t inverse;         /* nolsm_inverse (default NOLSM_INV_CHOLESKY_FP32
+                                for FP16/BF16, NOLSM_INV_CHOLESKY otherwise)    */
     int32_t inv_max_iter;    /* coupled Newton-Schulz iteration slots, 2..128
                                 (default 40; used by configure)                  */
 } nolsm_solve_opts;

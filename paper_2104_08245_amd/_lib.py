@@ -15,7 +15,7 @@ FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
 BOUNDS_GERSHGORIN, BOUNDS_LEARNED = 0, 1
 SCHED_GRAPH, SCHED_STREAM, SCHED_PER_BUCKET, SCHED_PERSISTENT = 0, 1, 2, 3
-INV_CHOLESKY, INV_COUPLED_NS = 0, 1
+INV_CHOLESKY, INV_COUPLED_NS, INV_CHOLESKY_FP32 = 0, 1, 2
 PLAN_COMBINE = 1
 MLP_NFEAT = 12
 MLP_NPARAM = 5122

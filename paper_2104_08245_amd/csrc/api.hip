@@ -178,9 +178,10 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
             if ((e = launch_inverse(cd, b.ws, ia, st)) != hipSuccess) return hip_fail(e, "inverse launch");
         } else {
             if (prof) prof->mark(PH_CHOL);
-            if ((e = launch_chol(cd, b.ws, st)) != hipSuccess) return hip_fail(e, "Cholesky launch");
+            const bool fp32 = o.inverse == NOLSM_INV_CHOLESKY_FP32;
+            if ((e = launch_chol(cd, b.ws, fp32, st)) != hipSuccess) return hip_fail(e, "Cholesky launch");
             if (prof) prof->mark(PH_SUBST);
-            if ((e = launch_subst(cd, b.ws, st)) != hipSuccess) return hip_fail(e, "substitution launch");
+            if ((e = launch_subst(cd, b.ws, fp32, st)) != hipSuccess) return hip_fail(e, "substitution launch");
         }
         if (prof) prof->mark(PH_BOUNDS);
         if ((e = launch_bounds(cd, b.ws, ba, o.prec, st)) != hipSuccess) return hip_fail(e, "bounds launch");

@@ -24,30 +24,50 @@ __device__ __forceinline__ int task_a(uint32_t t) { return (int)((t >> 8) & 0xFF
 __device__ __forceinline__ int task_b(uint32_t t) { return (int)(t & 0xFF); }
 
 // ---------------------------------------------------------------------------
-// 64x64 FP64 tiles on the FP64 MFMA (v_mfma_f64_16x16x4_f64), 256 threads.
-// Wave w owns the 32x32 quadrant (w>>1, w&1) as 2x2 blocks of 16x16. In a
-// block, A[i][k] comes from lane i + 16k, B[k][j] from lane j + 16k, and
-// element e of lane l is D[l/16 + 4e][l%16] (measured on gfx950; the FP32
-// 16x16x4 instruction instead returns D[4(l/16) + e][l%16]).
-// LDS tiles are [64][LDP] doubles, LDP = 65 (one pad double per row).
+// 64x64 tiles on the matrix cores, 256 threads, in FP64
+// (v_mfma_f64_16x16x4_f64) or FP32 (v_mfma_f32_16x16x4_f32); the global
+// operands are FP64 either way and are rounded when staged. Wave w owns the
+// 32x32 quadrant (w>>1, w&1) as 2x2 blocks of 16x16. In a block, A[i][k]
+// comes from lane i + 16k and B[k][j] from lane j + 16k for both types;
+// element e of lane l is D[l/16 + 4e][l%16] in FP64 and D[4(l/16) + e][l%16]
+// in FP32 (both measured on gfx950). LDS tiles are [64][LDP] values,
+// LDP = 65 (one pad value per row).
 // ---------------------------------------------------------------------------
 #define LDP 65
 
-struct Acc64 {
-    v4d c[2][2];
+template <typename T> struct Mfma16;
+template <> struct Mfma16<double> {
+    typedef v4d acc_t;
+    static __device__ __forceinline__ v4d mma(double a, double b, v4d c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
 };
+template <> struct Mfma16<float> {
+    typedef v4f acc_t;
+    static __device__ __forceinline__ v4f mma(float a, float b, v4f c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <typename T> struct Same { typedef T type; };
 
-__device__ __forceinline__ void acc_zero(Acc64 &a) {
+template <typename T> struct AccT {
+    typename Mfma16<T>::acc_t c[2][2];
+};
+typedef AccT<double> Acc64;
+
+template <typename T> __device__ __forceinline__ void acc_zero(AccT<T> &a) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) a.c[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) a.c[i][j][e] = (T)0;
 }
 
 // row/col of element e of block (i, j) for this lane
-__device__ __forceinline__ int acc_row(int i, int e) {
+template <typename T> __device__ __forceinline__ int acc_row(int i, int e) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    return (w >> 1) * 32 + i * 16 + (l >> 4) + 4 * e;
+    return (w >> 1) * 32 + i * 16 + (sizeof(T) == 8 ? (l >> 4) + 4 * e : 4 * (l >> 4) + e);
 }
 __device__ __forceinline__ int acc_col(int j) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -57,16 +77,16 @@ __device__ __forceinline__ int acc_col(int j) {
 // acc += op(A) * op(B) with A, B 64x64 tiles in LDS.
 // TA = false: A[m][k] = sA[m][k];  TA = true: A[m][k] = sA[k][m].
 // TB = false: B[k][n] = sB[k][n];  TB = true: B[k][n] = sB[n][k].
-template <bool TA, bool TB>
-__device__ __forceinline__ void mma64(Acc64 &acc, const double (*sA)[LDP], const double (*sB)[LDP],
-                                      double sign = 1.0) {
+template <bool TA, bool TB, typename T>
+__device__ __forceinline__ void mma64(AccT<T> &acc, const T (*sA)[LDP], const T (*sB)[LDP],
+                                      typename Same<T>::type sign = (T)1) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
     const int li = l & 15, lk = l >> 4;
 #pragma unroll 4
     for (int k0 = 0; k0 < 64; k0 += 4) {
         const int k = k0 + lk;
-        double a[2], b[2];
+        T a[2], b[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int m = r0 + i * 16 + li;
@@ -80,13 +100,12 @@ __device__ __forceinline__ void mma64(Acc64 &acc, const double (*sA)[LDP], const
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                acc.c[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc.c[i][j], 0, 0, 0);
+            for (int j = 0; j < 2; ++j) acc.c[i][j] = Mfma16<T>::mma(a[i], b[j], acc.c[i][j]);
     }
 }
 
-// global (ld doubles per row) <-> LDS tile copies, 256 threads
-__device__ __forceinline__ void g2s_tile(double (*s)[LDP], const double *g, int64_t ld) {
+// global FP64 (ld doubles per row) <-> LDS tile copies, 256 threads
+template <typename T> __device__ __forceinline__ void g2s_tile(T (*s)[LDP], const double *g, int64_t ld) {
     const int t = threadIdx.x;
     const int c4 = (t & 15) * 4;
 #pragma unroll
@@ -94,45 +113,44 @@ __device__ __forceinline__ void g2s_tile(double (*s)[LDP], const double *g, int6
         const int r = i * 16 + (t >> 4);
         const double2 *p = (const double2 *)(g + (int64_t)r * ld + c4);
         const double2 x = p[0], y = p[1];
-        s[r][c4] = x.x; s[r][c4 + 1] = x.y; s[r][c4 + 2] = y.x; s[r][c4 + 3] = y.y;
+        s[r][c4] = (T)x.x; s[r][c4 + 1] = (T)x.y; s[r][c4 + 2] = (T)y.x; s[r][c4 + 3] = (T)y.y;
     }
 }
-__device__ __forceinline__ void s2g_tile(double *g, int64_t ld, const double (*s)[LDP]) {
+template <typename T> __device__ __forceinline__ void s2g_tile(double *g, int64_t ld, const T (*s)[LDP]) {
     const int t = threadIdx.x;
     const int c4 = (t & 15) * 4;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int r = i * 16 + (t >> 4);
         double2 *p = (double2 *)(g + (int64_t)r * ld + c4);
-        p[0] = make_double2(s[r][c4], s[r][c4 + 1]);
-        p[1] = make_double2(s[r][c4 + 2], s[r][c4 + 3]);
+        p[0] = make_double2((double)s[r][c4], (double)s[r][c4 + 1]);
+        p[1] = make_double2((double)s[r][c4 + 2], (double)s[r][c4 + 3]);
     }
 }
-__device__ __forceinline__ void acc2s(double (*s)[LDP], const Acc64 &a) {
+template <typename T> __device__ __forceinline__ void acc2s(T (*s)[LDP], const AccT<T> &a) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) s[acc_row(i, e)][acc_col(j)] = a.c[i][j][e];
+            for (int e = 0; e < 4; ++e) s[acc_row<T>(i, e)][acc_col(j)] = a.c[i][j][e];
 }
-__device__ __forceinline__ void s2acc(Acc64 &a, const double (*s)[LDP]) {
+template <typename T> __device__ __forceinline__ void s2acc(AccT<T> &a, const T (*s)[LDP]) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) a.c[i][j][e] = s[acc_row(i, e)][acc_col(j)];
+            for (int e = 0; e < 4; ++e) a.c[i][j][e] = s[acc_row<T>(i, e)][acc_col(j)];
 }
-
-// global tile (ld doubles per row) straight into the accumulator layout
-__device__ __forceinline__ void g2acc(Acc64 &a, const double *g, int64_t ld) {
+// global FP64 tile (ld doubles per row) straight into the accumulator layout
+template <typename T> __device__ __forceinline__ void g2acc(AccT<T> &a, const double *g, int64_t ld) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) a.c[i][j][e] = g[(int64_t)acc_row(i, e) * ld + acc_col(j)];
+            for (int e = 0; e < 4; ++e) a.c[i][j][e] = (T)g[(int64_t)acc_row<T>(i, e) * ld + acc_col(j)];
 }
 
 // deterministic block reductions (256 threads); `red` is LDS scratch of 256

@@ -112,9 +112,9 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
 // barrier per column suffices: a buffer is rewritten only after every thread
 // has passed the barrier that follows its last read. The factor L (zeros
 // above the diagonal) is written back to D. A non-positive pivot sets *fail.
-__device__ void potrf64_reg(double (*D)[LDP], double (*cb)[64], int *fail) {
+template <typename T> __device__ void potrf64_reg(T (*D)[LDP], T (*cb)[64], int *fail) {
     const int t = threadIdx.x, q = t & 63, w = t >> 6;
-    double v[16];
+    T v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = D[w + 4 * i][q];
     if (q == 0)
@@ -122,16 +122,16 @@ __device__ void potrf64_reg(double (*D)[LDP], double (*cb)[64], int *fail) {
         for (int i = 0; i < 16; ++i) cb[0][w + 4 * i] = v[i];
     __syncthreads();
     for (int c = 0; c < 64; ++c) {
-        const double *col = cb[c & 1];
-        const double d = col[c];
-        if (t == 0 && !(d > 0.0)) *fail = 1;
-        const double piv = sqrt(fmax(d, 1e-300));
-        const double rp = 1.0 / piv;
-        const double lq = col[q] * rp;   // L[q][c] for q > c
+        const T *col = cb[c & 1];
+        const T d = col[c];
+        if (t == 0 && !(d > (T)0)) *fail = 1;
+        const T piv = sqrt(fmax(d, (T)(sizeof(T) == 8 ? 1e-300 : 1e-30)));
+        const T rp = (T)1 / piv;
+        const T lq = col[q] * rp;   // L[q][c] for q > c
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int r = w + 4 * i;
-            const double lr = col[r] * rp;
+            const T lr = col[r] * rp;
             if (q == c) {
                 if (r > c) v[i] = lr;
                 else if (r == c) v[i] = piv;
@@ -147,7 +147,7 @@ __device__ void potrf64_reg(double (*D)[LDP], double (*cb)[64], int *fail) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int r = w + 4 * i;
-        D[r][q] = (q <= r) ? v[i] : 0.0;
+        D[r][q] = (q <= r) ? v[i] : (T)0;
     }
     __syncthreads();
 }
@@ -157,18 +157,18 @@ __device__ void potrf64_reg(double (*D)[LDP], double (*cb)[64], int *fail) {
 // holds column c = t % 64, rows r = w + 4i of the right-hand side B; at step q
 // the owners of row q scale it by 1/L[q][q] (final row q of Di) and publish
 // it, then every row r > q takes off L[r][q] times it. Entries above the
-// diagonal stay exact zeros. rd: 64 doubles of LDS, xb: 2 x 64.
-__device__ void trinv64_reg(const double (*Lt)[LDP], double (*Di)[LDP], double *rd, double (*xb)[64]) {
+// diagonal stay exact zeros. rd: 64 values of LDS, xb: 2 x 64.
+template <typename T> __device__ void trinv64_reg(const T (*Lt)[LDP], T (*Di)[LDP], T *rd, T (*xb)[64]) {
     const int t = threadIdx.x, c = t & 63, w = t >> 6;
-    if (t < 64) rd[t] = 1.0 / Lt[t][t];
-    double b[16];
+    if (t < 64) rd[t] = (T)1 / Lt[t][t];
+    T b[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) b[i] = (w + 4 * i == c) ? 1.0 : 0.0;
+    for (int i = 0; i < 16; ++i) b[i] = (w + 4 * i == c) ? (T)1 : (T)0;
     __syncthreads();
     for (int q = 0; q < 64; ++q) {
         const int iq = q >> 2;
         if (w == (q & 3)) {
-            const double s = rd[q];
+            const T s = rd[q];
 #pragma unroll
             for (int i = 0; i < 16; ++i)
                 if (i == iq) {
@@ -177,7 +177,7 @@ __device__ void trinv64_reg(const double (*Lt)[LDP], double (*Di)[LDP], double *
                 }
         }
         __syncthreads();
-        const double xq = xb[q & 1][c];
+        const T xq = xb[q & 1][c];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int r = w + 4 * i;
@@ -189,12 +189,13 @@ __device__ void trinv64_reg(const double (*Lt)[LDP], double (*Di)[LDP], double *
     __syncthreads();
 }
 
+template <typename T>
 __global__ __launch_bounds__(256, 2) void k_chol(ChunkDev cd, char *ws) {
-    // two tiles (66.6 KB) plus small buffers: two workgroups fit one CU
-    __shared__ double sA[64][LDP];
-    __shared__ double sB[64][LDP];
-    __shared__ double cb[2][64];
-    __shared__ double rd[64];
+    // two tiles (66.6 KB in FP64) plus small buffers: two workgroups fit one CU
+    __shared__ T sA[64][LDP];
+    __shared__ T sB[64][LDP];
+    __shared__ T cb[2][64];
+    __shared__ T rd[64];
     __shared__ int fail;
     const int s = blockIdx.x;
     if (s >= cd.nsub) return;
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(256, 2) void k_chol(ChunkDev cd, char *ws) {
     __syncthreads();
     for (int j = 0; j < P; ++j) {
         for (int i = j; i < P; ++i) {
-            Acc64 acc;
+            AccT<T> acc;
             g2s_tile(sA, L + (int64_t)(i * 64) * ld + j * 64, ld);
             __syncthreads();
             s2acc(acc, sA);
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(256, 2) void k_chol(ChunkDev cd, char *ws) {
                 acc2s(sA, acc);
                 g2s_tile(sB, Dinv + (int64_t)j * 4096, 64);
                 __syncthreads();
-                Acc64 o;
+                AccT<T> o;
                 acc_zero(o);
                 mma64<false, true>(o, sA, sB);
                 __syncthreads();
@@ -266,10 +267,11 @@ __global__ __launch_bounds__(256, 2) void k_chol(ChunkDev cd, char *ws) {
 // ---------------------------------------------------------------------------
 #define SUBST_R 4
 
+template <typename T>
 __global__ __launch_bounds__(256, 2) void k_subst(ChunkDev cd, char *ws) {
     const double mu = ((const WsHeader *)ws)->mu;
-    __shared__ double sA[64][LDP];
-    __shared__ double sB[64][LDP];
+    __shared__ T sA[64][LDP];
+    __shared__ T sB[64][LDP];
     __shared__ double red[256];
     const uint32_t task = xcd_task(cd.t_subst);
     if (task == NOLSM_TASK_NONE) return;
@@ -287,7 +289,7 @@ __global__ __launch_bounds__(256, 2) void k_subst(ChunkDev cd, char *ws) {
     // forward: W_i = Dinv_i (B_i - sum_{k<i} L_ik W_k)
     for (int i0 = 0; i0 < P; i0 += SUBST_R) {
         const int nr = min(SUBST_R, P - i0);
-        Acc64 acc[SUBST_R];
+        AccT<T> acc[SUBST_R];
 #pragma unroll
         for (int r = 0; r < SUBST_R; ++r)
             if (r < nr) g2acc(acc[r], Bt(i0 + r), ldk);
@@ -311,7 +313,7 @@ __global__ __launch_bounds__(256, 2) void k_subst(ChunkDev cd, char *ws) {
                 acc2s(sB, acc[r]);
                 g2s_tile(sA, Dinv + (int64_t)i * 4096, 64);
                 __syncthreads();
-                Acc64 o;
+                AccT<T> o;
                 acc_zero(o);
                 mma64<false, false>(o, sA, sB);
                 __syncthreads();
@@ -335,7 +337,7 @@ __global__ __launch_bounds__(256, 2) void k_subst(ChunkDev cd, char *ws) {
     double colsum = 0.0, frob = 0.0;
     for (int i1 = P - 1; i1 >= 0; i1 -= SUBST_R) {
         const int nr = min(SUBST_R, i1 + 1);   // rows i1 - r, r < nr
-        Acc64 acc[SUBST_R];
+        AccT<T> acc[SUBST_R];
 #pragma unroll
         for (int r = 0; r < SUBST_R; ++r)
             if (r < nr) g2acc(acc[r], Bt(i1 - r), ldk);
@@ -358,7 +360,7 @@ __global__ __launch_bounds__(256, 2) void k_subst(ChunkDev cd, char *ws) {
                 acc2s(sB, acc[r]);
                 g2s_tile(sA, Dinv + (int64_t)i * 4096, 64);
                 __syncthreads();
-                Acc64 o;
+                AccT<T> o;
                 acc_zero(o);
                 mma64<true, false>(o, sA, sB);
                 __syncthreads();
@@ -367,7 +369,7 @@ __global__ __launch_bounds__(256, 2) void k_subst(ChunkDev cd, char *ws) {
                 if (cc < P) {
                     // bounds inputs of A_J - mu I; the tile itself is stored
                     // without the shift, since the rows above still use it
-                    auto a = [&](int rr, int c) { return sB[rr][c] - ((i == cc && rr == c) ? mu : 0.0); };
+                    auto a = [&](int rr, int c) { return (double)sB[rr][c] - ((i == cc && rr == c) ? mu : 0.0); };
                     const int t = threadIdx.x;
                     if (t < 64) {
                         const int gr = i * 64 + t;
@@ -575,12 +577,14 @@ hipError_t launch_gather(const ChunkDev &cd, char *ws, const GatherArgs &ga, hip
     hipLaunchKernelGGL(k_gather, dim3(cd.max_m, cd.nsub), dim3(256), lds, st, cd, ws, ga);
     return hipGetLastError();
 }
-hipError_t launch_chol(const ChunkDev &cd, char *ws, hipStream_t st) {
-    hipLaunchKernelGGL(k_chol, dim3(cd.nsub), dim3(256), 0, st, cd, ws);
+hipError_t launch_chol(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st) {
+    if (fp32) hipLaunchKernelGGL(k_chol<float>, dim3(cd.nsub), dim3(256), 0, st, cd, ws);
+    else hipLaunchKernelGGL(k_chol<double>, dim3(cd.nsub), dim3(256), 0, st, cd, ws);
     return hipGetLastError();
 }
-hipError_t launch_subst(const ChunkDev &cd, char *ws, hipStream_t st) {
-    hipLaunchKernelGGL(k_subst, dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
+hipError_t launch_subst(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st) {
+    if (fp32) hipLaunchKernelGGL(k_subst<float>, dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
+    else hipLaunchKernelGGL(k_subst<double>, dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
     return hipGetLastError();
 }
 hipError_t launch_bounds(const ChunkDev &cd, char *ws, const BoundsArgs &ba, int prec, hipStream_t st) {

@@ -70,8 +70,9 @@ struct ExtractArgs {
 hipError_t launch_gather(const ChunkDev &cd, char *ws, const GatherArgs &ga, hipStream_t st);
 hipError_t launch_wcols(const ChunkDev &cd, char *ws, const ExtractArgs &ea, hipStream_t st);
 hipError_t launch_inverse(const ChunkDev &cd, char *ws, const InvArgs &ia, hipStream_t st);
-hipError_t launch_chol(const ChunkDev &cd, char *ws, hipStream_t st);
-hipError_t launch_subst(const ChunkDev &cd, char *ws, hipStream_t st);
+// fp32: arithmetic on the FP32 matrix cores (FP64 storage either way)
+hipError_t launch_chol(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st);
+hipError_t launch_subst(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st);
 hipError_t launch_set_header(char *ws, double mu, hipStream_t st);
 hipError_t launch_trace_sums(const void *stats, int32_t nb, char *ws, hipStream_t st);
 hipError_t launch_bounds(const ChunkDev &cd, char *ws, const BoundsArgs &ba, int prec, hipStream_t st);

@@ -308,7 +308,9 @@ extern "C" void nolsm_default_opts(nolsm_solve_opts *o, int32_t prec) {
     o->sched = NOLSM_SCHED_GRAPH;
     o->debug_poison_mol = -1;
     o->ns_small_tile_mask = 0x5;   // 64 and 192 rows: 128-row tiles would waste work
-    o->inverse = NOLSM_INV_CHOLESKY;
+    // 16-bit sign iterations: the FP32 factor's error (kappa(S_J) 2^-24) sits
+    // far below their own floor, and the FP32 matrix cores run 3x faster
+    o->inverse = (prec == NOLSM_FP16 || prec == NOLSM_BF16) ? NOLSM_INV_CHOLESKY_FP32 : NOLSM_INV_CHOLESKY;
     o->inv_max_iter = 40;
 }
 
@@ -380,7 +382,11 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
     if (opts->prec < NOLSM_FP64 || opts->prec > NOLSM_BF16) { nolsm_set_last_error("bad precision"); return NOLSM_E_ARG; }
     if (opts->max_iter < 2 || opts->max_iter > NOLSM_MAX_ITER_CAP) { nolsm_set_last_error("max_iter must be 2..128"); return NOLSM_E_ARG; }
     if (opts->sched < NOLSM_SCHED_GRAPH || opts->sched > NOLSM_SCHED_PERSISTENT) { nolsm_set_last_error("bad schedule"); return NOLSM_E_ARG; }
-    if (opts->inverse != NOLSM_INV_CHOLESKY && opts->inverse != NOLSM_INV_COUPLED_NS) { nolsm_set_last_error("bad inverse"); return NOLSM_E_ARG; }
+    if (opts->inverse < NOLSM_INV_CHOLESKY || opts->inverse > NOLSM_INV_CHOLESKY_FP32) { nolsm_set_last_error("bad inverse"); return NOLSM_E_ARG; }
+    if (opts->inverse == NOLSM_INV_CHOLESKY_FP32 && opts->prec != NOLSM_FP16 && opts->prec != NOLSM_BF16) {
+        nolsm_set_last_error("the FP32 Cholesky route serves the FP16/BF16 sign iterations only");
+        return NOLSM_E_ARG;
+    }
     if (opts->inverse == NOLSM_INV_COUPLED_NS) {
         if (opts->prec != NOLSM_FP16 && opts->prec != NOLSM_BF16) {
             nolsm_set_last_error("the coupled Newton-Schulz inverse runs in FP16/BF16 only");

@@ -148,6 +148,8 @@ def test_bad_options_rejected(L, config1):
     p = Plan(s.K.nb, s.K.bs, s.K.row_ptr, s.K.col_idx)
     for kw in (dict(prec=7), dict(max_iter=1), dict(max_iter=500), dict(sched=9), dict(inverse=5),
                dict(inverse=L.INV_COUPLED_NS),                       # FP64: 16-bit route only
+               dict(inverse=L.INV_CHOLESKY_FP32),                    # FP64: 16-bit route only
+               dict(prec=L.PREC["fp32"], inverse=L.INV_CHOLESKY_FP32),
                dict(prec=L.PREC["fp16"], inverse=L.INV_COUPLED_NS, inv_max_iter=1)):
         opts = L.default_opts("fp64")
         for k, v in kw.items():
@@ -190,3 +192,10 @@ def test_combination_equals_oracle(L, config1):
     p = Plan(config1.K.nb, 6, config1.K.row_ptr, config1.K.col_idx)
     g = p.groups()
     assert np.array_equal(g[2], np.arange(config1.K.nb + 1)) and np.array_equal(g[3], np.arange(config1.K.nb))
+
+
+def test_default_inverse_route_per_precision(L):
+    # the 16-bit sign iterations default to the FP32 Cholesky route
+    for prec, want in (("fp64", L.INV_CHOLESKY), ("fp32", L.INV_CHOLESKY),
+                       ("fp16", L.INV_CHOLESKY_FP32), ("bf16", L.INV_CHOLESKY_FP32)):
+        assert L.default_opts(prec).inverse == want

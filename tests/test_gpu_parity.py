@@ -318,3 +318,32 @@ def test_fp16_nonzero_mu_within_stated_error(torch, config1):
     say(f"fp16 mu=0.25: Dcols rel-F max {errs.max():.3e}; |dE_J| max {de.max():.3e}")
     assert errs.max() <= MIXED["fp16"]["dcols"]
     assert de.max() <= MIXED["fp16"]["energy"]
+
+
+def test_fp32_cholesky_route_features_match_fp64_route(torch, config1):
+    # the 12 features are sums and norms of A_J - mu I, so they expose the
+    # FP32 route's A_J directly: relative error about kappa(S_J) 2^-24 times a
+    # small growth factor (kappa ~ 60 here), held to 1e-4
+    from paper_2104_08245_amd import Solver, _lib as L
+    feats = {}
+    for inv in (L.INV_CHOLESKY, L.INV_CHOLESKY_FP32):
+        sv = Solver(config1, prec="fp16", device="cuda:0", inverse=inv)
+        sv.want_features()
+        sv.run()
+        torch.cuda.synchronize()
+        feats[inv] = sv.features.cpu().numpy().reshape(config1.nmol, -1).astype(np.float64)
+    a, b = feats[L.INV_CHOLESKY], feats[L.INV_CHOLESKY_FP32]
+    err = np.abs(b - a) / np.maximum(np.abs(a), 1e-3)
+    say(f"FP32 vs FP64 Cholesky route: feature rel diff max {err.max():.3e}")
+    assert err.max() <= 1e-4
+
+
+def test_fp16_on_fp64_cholesky_route_within_stated_error(torch, config1, ref1):
+    from paper_2104_08245_amd import _lib as L
+    sv = solve(config1, "fp16", inverse=L.INV_CHOLESKY)
+    st = sv.host_stats()
+    assert np.all(st["status"] == 0)
+    dc = sv.host_dcols()
+    errs = np.array([rel(dc[J], ref1.Dcols[J]) for J in range(config1.nmol)])
+    assert errs.max() <= MIXED["fp16"]["dcols"]
+    assert np.abs(st["energy_KD"] - ref1.E).max() <= MIXED["fp16"]["energy"]

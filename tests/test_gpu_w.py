@@ -37,11 +37,11 @@ def refw(config1):
     return o.nolsm(config1, want_w=True, keep_x=True)
 
 
-def solve_w(system, prec):
+def solve_w(system, prec, **kw):
     from paper_2104_08245_amd import Solver
     import torch
-    say(f"[gpu] W solve prec={prec} nmol={system.nmol}")
-    sv = Solver(system, prec=prec, device="cuda:0")
+    say(f"[gpu] W solve prec={prec} nmol={system.nmol} {kw}")
+    sv = Solver(system, prec=prec, device="cuda:0", **kw)
     sv.want_w()
     sv.run()
     sv.assemble_w()
@@ -66,8 +66,10 @@ def test_w_fp64_matches_oracle_config1(torch, config1, refw):
 
 def test_w_kernel_is_the_exact_product(torch, config1, refw):
     # isolates the W kernel: its output equals (A_J + mu I) Dcols_J formed on
-    # the CPU from the oracle's A_J and the GPU's own Dcols_J
-    sv = solve_w(config1, "fp16")
+    # the CPU from the oracle's A_J and the GPU's own Dcols_J; the FP64
+    # Cholesky route makes the GPU's A_J the oracle's to rounding
+    from paper_2104_08245_amd import _lib as L
+    sv = solve_w(config1, "fp16", inverse=L.INV_CHOLESKY)
     dc, wc = sv.host_dcols(), sv.host_dcols("W")
     for J in range(0, config1.nmol, 5):
         _, A = refw.xs[J]
