@@ -118,6 +118,7 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
     ga.grp_blk = (const int32_t *)(base + pl->o_grp_blk);
     ga.own_pos = (const int32_t *)(base + pl->o_own_pos);
     ga.own_J = (const int32_t *)(base + pl->o_own_J);
+    ga.s_fp32 = o.inverse == NOLSM_INV_CHOLESKY_FP32;
     ga.Kval = b.dK;
     ga.Sval = b.dS;
     ga.bs = pl->bs;

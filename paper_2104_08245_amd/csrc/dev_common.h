@@ -104,27 +104,37 @@ __device__ __forceinline__ void mma64(AccT<T> &acc, const T (*sA)[LDP], const T 
     }
 }
 
-// global FP64 (ld doubles per row) <-> LDS tile copies, 256 threads
-template <typename T> __device__ __forceinline__ void g2s_tile(T (*s)[LDP], const double *g, int64_t ld) {
+// global (ld values per row, FP64 or FP32) <-> LDS tile copies, 256 threads
+template <typename T, typename G> __device__ __forceinline__ void g2s_tile(T (*s)[LDP], const G *g, int64_t ld) {
     const int t = threadIdx.x;
     const int c4 = (t & 15) * 4;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int r = i * 16 + (t >> 4);
-        const double2 *p = (const double2 *)(g + (int64_t)r * ld + c4);
-        const double2 x = p[0], y = p[1];
-        s[r][c4] = (T)x.x; s[r][c4 + 1] = (T)x.y; s[r][c4 + 2] = (T)y.x; s[r][c4 + 3] = (T)y.y;
+        if constexpr (sizeof(G) == 8) {
+            const double2 *p = (const double2 *)(g + (int64_t)r * ld + c4);
+            const double2 x = p[0], y = p[1];
+            s[r][c4] = (T)x.x; s[r][c4 + 1] = (T)x.y; s[r][c4 + 2] = (T)y.x; s[r][c4 + 3] = (T)y.y;
+        } else {
+            const float4 x = *(const float4 *)(g + (int64_t)r * ld + c4);
+            s[r][c4] = (T)x.x; s[r][c4 + 1] = (T)x.y; s[r][c4 + 2] = (T)x.z; s[r][c4 + 3] = (T)x.w;
+        }
     }
 }
-template <typename T> __device__ __forceinline__ void s2g_tile(double *g, int64_t ld, const T (*s)[LDP]) {
+template <typename T, typename G> __device__ __forceinline__ void s2g_tile(G *g, int64_t ld, const T (*s)[LDP]) {
     const int t = threadIdx.x;
     const int c4 = (t & 15) * 4;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int r = i * 16 + (t >> 4);
-        double2 *p = (double2 *)(g + (int64_t)r * ld + c4);
-        p[0] = make_double2((double)s[r][c4], (double)s[r][c4 + 1]);
-        p[1] = make_double2((double)s[r][c4 + 2], (double)s[r][c4 + 3]);
+        if constexpr (sizeof(G) == 8) {
+            double2 *p = (double2 *)(g + (int64_t)r * ld + c4);
+            p[0] = make_double2((double)s[r][c4], (double)s[r][c4 + 1]);
+            p[1] = make_double2((double)s[r][c4 + 2], (double)s[r][c4 + 3]);
+        } else {
+            *(float4 *)(g + (int64_t)r * ld + c4) =
+                make_float4((float)s[r][c4], (float)s[r][c4 + 1], (float)s[r][c4 + 2], (float)s[r][c4 + 3]);
+        }
     }
 }
 template <typename T> __device__ __forceinline__ void acc2s(T (*s)[LDP], const AccT<T> &a) {
@@ -143,8 +153,8 @@ template <typename T> __device__ __forceinline__ void s2acc(AccT<T> &a, const T 
 #pragma unroll
             for (int e = 0; e < 4; ++e) a.c[i][j][e] = s[acc_row<T>(i, e)][acc_col(j)];
 }
-// global FP64 tile (ld doubles per row) straight into the accumulator layout
-template <typename T> __device__ __forceinline__ void g2acc(AccT<T> &a, const double *g, int64_t ld) {
+// global tile (ld values per row) straight into the accumulator layout
+template <typename T, typename G> __device__ __forceinline__ void g2acc(AccT<T> &a, const G *g, int64_t ld) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll

@@ -57,7 +57,12 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
     }
     __syncthreads();
     double *Kd = (double *)(ws + M.offK);
-    double *Sd = (double *)(ws + M.offL);
+    double *Sd = (double *)(ws + M.offL);   // T_J(S) in FP64, or
+    float *Sf = (float *)(ws + M.offL);     // in FP32 for the FP32 Cholesky route
+    auto put_s = [&](int64_t idx, double v) {
+        if (ga.s_fp32) Sf[idx] = (float)v;
+        else Sd[idx] = v;
+    };
     const int64_t ldk = np + 64, lds = np;
     const int bb = bs * bs;
     // debug: a negative pivot in the submatrix that owns poison_J
@@ -75,7 +80,7 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
         }
         if (poison && i == 0) vs = -1.0;
         Kd[(int64_t)(a * bs + r) * ldk + c] = vk;
-        Sd[(int64_t)(a * bs + r) * lds + c] = vs;
+        put_s((int64_t)(a * bs + r) * lds + c, vs);
     }
     // E tile: columns np..np+63 of the K buffer; owned molecule o (block
     // position q_o in the rows) has its unit columns at o bs .. o bs + bs - 1
@@ -91,7 +96,7 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
         const int rows = np - n;
         for (int i = t; i < rows * np; i += 256) {
             const int r = n + i / np, c = i % np;
-            Sd[(int64_t)r * np + c] = (r == c) ? 1.0 : 0.0;
+            put_s((int64_t)r * np + c, (r == c) ? 1.0 : 0.0);
         }
         for (int i = t; i < rows * (np + 64); i += 256) {
             const int r = n + i / (np + 64), c = i % (np + 64);
@@ -200,8 +205,8 @@ __global__ __launch_bounds__(256, 2) void k_chol(ChunkDev cd, char *ws) {
     const int s = blockIdx.x;
     if (s >= cd.nsub) return;
     const SubMeta M = cd.meta[s];
-    double *L = (double *)(ws + M.offL);
-    double *Dinv = (double *)(ws + M.offDinv);
+    T *L = (T *)(ws + M.offL);         // S, factored in place (FP32 route: FP32)
+    T *Dinv = (T *)(ws + M.offDinv);
     const int64_t ld = M.np;
     const int P = M.P;
     if (threadIdx.x == 0) fail = 0;
@@ -280,8 +285,8 @@ __global__ __launch_bounds__(256, 2) void k_subst(ChunkDev cd, char *ws) {
     if (cd.ctl[s].status != NOLSM_MOL_OK) return;
     const int P = M.P, np = M.np, n = M.n;
     const int64_t ldl = np, ldk = np + 64;
-    const double *L = (const double *)(ws + M.offL);
-    const double *Dinv = (const double *)(ws + M.offDinv);
+    const T *L = (const T *)(ws + M.offL);
+    const T *Dinv = (const T *)(ws + M.offDinv);
     double *Kb = (double *)(ws + M.offK);
     const int col0 = (cc < P) ? cc * 64 : np;
     auto Lt = [&](int r, int c) { return L + (int64_t)(r * 64) * ldl + c * 64; };

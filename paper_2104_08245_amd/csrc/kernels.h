@@ -10,6 +10,7 @@ struct GatherArgs {
     const int32_t *own_pos;   // position of each owned molecule in its rows (SubMeta::own_off)
     const int32_t *own_J;     // the owned molecules themselves (SubMeta::own_off)
     const double *Kval, *Sval;
+    int32_t s_fp32;           // write T_J(S) as FP32 (FP32 Cholesky route), else FP64
     int32_t bs;
     int32_t poison_J;
 };

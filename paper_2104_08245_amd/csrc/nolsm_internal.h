@@ -25,9 +25,9 @@ struct SubMeta {
     int32_t nown;     // molecules owned by this submatrix (1 unless combined)
     int32_t own_off;  // their offset in the owned-molecule list
     int32_t pad2_;
-    int64_t offL;     // np*np doubles: S -> L; later X buffer 0
+    int64_t offL;     // np*np doubles (FP32 Cholesky route: floats): S -> L; later X buffer 0
     int64_t offK;     // np*(np+64) doubles: K -> W -> [A | Y]
-    int64_t offDinv;  // P*64*64 doubles: inverses of the diagonal tiles of L
+    int64_t offDinv;  // P*64*64 doubles (or floats): inverses of the diagonal tiles of L
     int64_t offRow;   // (P+1)*np doubles: partial |A| row sums per column tile
     int64_t offCol;   // np doubles col sums of |A|, then 64 more: P frob partials
     int64_t offX1;    // ldx*ldx elements of the NS precision: X buffer 1
