@@ -259,78 +259,98 @@ __global__ __launch_bounds__(256, 2) void k_chol(ChunkDev cd, char *ws) {
 }
 
 // ---------------------------------------------------------------------------
-// Substitution for one 64-column tile cc of [K | E]: W = L^-1 B (forward),
-// then [A | Y] = L^-T W (backward), in place in the K buffer; mu is taken
-// off A's diagonal once the column tile is complete (the backward recursion
-// needs the unshifted rows). For cc < P it also emits the |A| row sums of the
+// Substitution for SC consecutive 64-column tiles cc .. cc + SC - 1 of
+// [K | E] (tile P is the E tile): W = L^-1 B (forward), then [A | Y] = L^-T W
+// (backward), in place in the K buffer; mu is taken off A's diagonal once
+// its column tile is complete (the backward recursion needs the unshifted
+// rows). For every column tile < P it also emits the |A| row sums of the
 // tile, the complete |A| column sums and a partial Frobenius sum (bounds
-// inputs). Task list: (slot, cc), cc = 0..P (P is the E tile).
-// SUBST_R row tiles are solved per pass with their accumulators in registers,
-// so each finished tile of the column is read back once per pass rather than
-// once per row tile below it (the L tiles are shared through L2 by the P + 1
-// column tasks of a submatrix, which are adjacent in the task list).
+// inputs). Task list: (slot, cc), cc = 0..P; tasks with cc % SC != 0 return.
+// SR row tiles are solved per pass with their accumulators in registers: each
+// L tile is read once per pass and task, and each finished tile of the
+// column once per pass (the tasks of a submatrix are adjacent in the task
+// list and share L through one XCD's L2 while they run together).
 // ---------------------------------------------------------------------------
-#define SUBST_R 4
-
-template <typename T>
-__global__ __launch_bounds__(256, 2) void k_subst(ChunkDev cd, char *ws) {
+template <typename T, int SR, int SC, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_subst(ChunkDev cd, char *ws) {
     const double mu = ((const WsHeader *)ws)->mu;
     __shared__ T sA[64][LDP];
-    __shared__ T sB[64][LDP];
+    __shared__ T sB[SC][64][LDP];
     __shared__ double red[256];
     const uint32_t task = xcd_task(cd.t_subst);
     if (task == NOLSM_TASK_NONE) return;
     const int s = task_slot(task), cc = task_a(task);
+    if (cc % SC) return;
     const SubMeta M = cd.meta[s];
     if (cd.ctl[s].status != NOLSM_MOL_OK) return;
     const int P = M.P, np = M.np, n = M.n;
+    const int nc = min(SC, P + 1 - cc);   // column tiles of this task
     const int64_t ldl = np, ldk = np + 64;
     const T *L = (const T *)(ws + M.offL);
     const T *Dinv = (const T *)(ws + M.offDinv);
     double *Kb = (double *)(ws + M.offK);
-    const int col0 = (cc < P) ? cc * 64 : np;
     auto Lt = [&](int r, int c) { return L + (int64_t)(r * 64) * ldl + c * 64; };
-    auto Bt = [&](int r) { return Kb + (int64_t)(r * 64) * ldk + col0; };
+    auto Bt = [&](int c, int r) {   // row tile r of this task's column c
+        const int col0 = (cc + c < P) ? (cc + c) * 64 : np;
+        return Kb + (int64_t)(r * 64) * ldk + col0;
+    };
     // forward: W_i = Dinv_i (B_i - sum_{k<i} L_ik W_k)
-    for (int i0 = 0; i0 < P; i0 += SUBST_R) {
-        const int nr = min(SUBST_R, P - i0);
-        AccT<T> acc[SUBST_R];
+    for (int i0 = 0; i0 < P; i0 += SR) {
+        const int nr = min(SR, P - i0);
+        AccT<T> acc[SR][SC];
 #pragma unroll
-        for (int r = 0; r < SUBST_R; ++r)
-            if (r < nr) g2acc(acc[r], Bt(i0 + r), ldk);
+        for (int r = 0; r < SR; ++r)
+#pragma unroll
+            for (int c = 0; c < SC; ++c)
+                if (r < nr && c < nc) g2acc(acc[r][c], Bt(c, i0 + r), ldk);
         for (int k = 0; k < i0; ++k) {
-            g2s_tile(sB, Bt(k), ldk);
 #pragma unroll
-            for (int r = 0; r < SUBST_R; ++r) {
+            for (int c = 0; c < SC; ++c)
+                if (c < nc) g2s_tile(sB[c], Bt(c, k), ldk);
+#pragma unroll
+            for (int r = 0; r < SR; ++r) {
                 if (r < nr) {
                     g2s_tile(sA, Lt(i0 + r, k), ldl);
                     __syncthreads();
-                    mma64<false, false>(acc[r], sA, sB, -1.0);
+#pragma unroll
+                    for (int c = 0; c < SC; ++c)
+                        if (c < nc) mma64<false, false>(acc[r][c], sA, sB[c], -1.0);
                     __syncthreads();
                 }
             }
         }
         // the diagonal block of the pass, in order
 #pragma unroll
-        for (int r = 0; r < SUBST_R; ++r) {
+        for (int r = 0; r < SR; ++r) {
             if (r < nr) {
                 const int i = i0 + r;
-                acc2s(sB, acc[r]);
                 g2s_tile(sA, Dinv + (int64_t)i * 4096, 64);
-                __syncthreads();
-                AccT<T> o;
-                acc_zero(o);
-                mma64<false, false>(o, sA, sB);
-                __syncthreads();
-                acc2s(sB, o);
-                __syncthreads();
-                s2g_tile(Bt(i), ldk, sB);   // W_i, kept in sB for the rows below
 #pragma unroll
-                for (int r2 = r + 1; r2 < SUBST_R; ++r2) {
+                for (int c = 0; c < SC; ++c)
+                    if (c < nc) acc2s(sB[c], acc[r][c]);
+                __syncthreads();
+#pragma unroll
+                for (int c = 0; c < SC; ++c) {
+                    if (c < nc) {
+                        AccT<T> o;
+                        acc_zero(o);
+                        mma64<false, false>(o, sA, sB[c]);
+                        __syncthreads();
+                        acc2s(sB[c], o);
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int c = 0; c < SC; ++c)
+                    if (c < nc) s2g_tile(Bt(c, i), ldk, sB[c]);   // W_i, kept in sB for the rows below
+#pragma unroll
+                for (int r2 = r + 1; r2 < SR; ++r2) {
                     if (r2 < nr) {
                         g2s_tile(sA, Lt(i0 + r2, i), ldl);
                         __syncthreads();
-                        mma64<false, false>(acc[r2], sA, sB, -1.0);
+#pragma unroll
+                        for (int c = 0; c < SC; ++c)
+                            if (c < nc) mma64<false, false>(acc[r2][c], sA, sB[c], -1.0);
                         __syncthreads();
                     }
                 }
@@ -339,70 +359,96 @@ __global__ __launch_bounds__(256, 2) void k_subst(ChunkDev cd, char *ws) {
         }
     }
     // backward: A_i = Dinv_i^T (W_i - sum_{k>i} L_ki^T A_k), passes from the bottom
-    double colsum = 0.0, frob = 0.0;
-    for (int i1 = P - 1; i1 >= 0; i1 -= SUBST_R) {
-        const int nr = min(SUBST_R, i1 + 1);   // rows i1 - r, r < nr
-        AccT<T> acc[SUBST_R];
+    double colsum[SC], frob[SC];
 #pragma unroll
-        for (int r = 0; r < SUBST_R; ++r)
-            if (r < nr) g2acc(acc[r], Bt(i1 - r), ldk);
+    for (int c = 0; c < SC; ++c) colsum[c] = frob[c] = 0.0;
+    for (int i1 = P - 1; i1 >= 0; i1 -= SR) {
+        const int nr = min(SR, i1 + 1);   // rows i1 - r, r < nr
+        AccT<T> acc[SR][SC];
+#pragma unroll
+        for (int r = 0; r < SR; ++r)
+#pragma unroll
+            for (int c = 0; c < SC; ++c)
+                if (r < nr && c < nc) g2acc(acc[r][c], Bt(c, i1 - r), ldk);
         for (int k = i1 + 1; k < P; ++k) {
-            g2s_tile(sB, Bt(k), ldk);   // A_k, unshifted
 #pragma unroll
-            for (int r = 0; r < SUBST_R; ++r) {
+            for (int c = 0; c < SC; ++c)
+                if (c < nc) g2s_tile(sB[c], Bt(c, k), ldk);   // A_k, unshifted
+#pragma unroll
+            for (int r = 0; r < SR; ++r) {
                 if (r < nr) {
                     g2s_tile(sA, Lt(k, i1 - r), ldl);
                     __syncthreads();
-                    mma64<true, false>(acc[r], sA, sB, -1.0);
+#pragma unroll
+                    for (int c = 0; c < SC; ++c)
+                        if (c < nc) mma64<true, false>(acc[r][c], sA, sB[c], -1.0);
                     __syncthreads();
                 }
             }
         }
 #pragma unroll
-        for (int r = 0; r < SUBST_R; ++r) {
+        for (int r = 0; r < SR; ++r) {
             if (r < nr) {
                 const int i = i1 - r;
-                acc2s(sB, acc[r]);
                 g2s_tile(sA, Dinv + (int64_t)i * 4096, 64);
-                __syncthreads();
-                AccT<T> o;
-                acc_zero(o);
-                mma64<true, false>(o, sA, sB);
-                __syncthreads();
-                acc2s(sB, o);
-                __syncthreads();
-                if (cc < P) {
-                    // bounds inputs of A_J - mu I; the tile itself is stored
-                    // without the shift, since the rows above still use it
-                    auto a = [&](int rr, int c) { return (double)sB[rr][c] - ((i == cc && rr == c) ? mu : 0.0); };
-                    const int t = threadIdx.x;
-                    if (t < 64) {
-                        const int gr = i * 64 + t;
-                        double rs = 0.0;
-                        for (int c = 0; c < 64; ++c)
-                            if (cc * 64 + c < n) rs += fabs(a(t, c));
-                        double *rowp = (double *)(ws + M.offRow);
-                        rowp[(int64_t)cc * np + gr] = (gr < n) ? rs : 0.0;
-                    } else if (t < 128) {
-                        const int c = t - 64;
-                        for (int rr = 0; rr < 64; ++rr)
-                            if (i * 64 + rr < n) colsum += fabs(a(rr, c));
-                    }
-                    // Frobenius partial: 16 entries per thread
-                    double fs = 0.0;
-                    for (int f = t; f < 4096; f += 256) {
-                        const int rr = f >> 6, c = f & 63;
-                        if (i * 64 + rr < n && cc * 64 + c < n) fs += a(rr, c) * a(rr, c);
-                    }
-                    frob += fs;
-                }
-                s2g_tile(Bt(i), ldk, sB);   // A_i, kept in sB for the rows above
 #pragma unroll
-                for (int r2 = r + 1; r2 < SUBST_R; ++r2) {
+                for (int c = 0; c < SC; ++c)
+                    if (c < nc) acc2s(sB[c], acc[r][c]);
+                __syncthreads();
+#pragma unroll
+                for (int c = 0; c < SC; ++c) {
+                    if (c < nc) {
+                        AccT<T> o;
+                        acc_zero(o);
+                        mma64<true, false>(o, sA, sB[c]);
+                        __syncthreads();
+                        acc2s(sB[c], o);
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int c = 0; c < SC; ++c) {
+                    const int ccol = cc + c;
+                    if (c < nc && ccol < P) {
+                        // bounds inputs of A_J - mu I; the tile itself is
+                        // stored without the shift, since the rows above
+                        // still use it
+                        auto a = [&](int rr, int q) {
+                            return (double)sB[c][rr][q] - ((i == ccol && rr == q) ? mu : 0.0);
+                        };
+                        const int t = threadIdx.x;
+                        if (t < 64) {
+                            const int gr = i * 64 + t;
+                            double rs = 0.0;
+                            for (int q = 0; q < 64; ++q)
+                                if (ccol * 64 + q < n) rs += fabs(a(t, q));
+                            double *rowp = (double *)(ws + M.offRow);
+                            rowp[(int64_t)ccol * np + gr] = (gr < n) ? rs : 0.0;
+                        } else if (t < 128) {
+                            const int q = t - 64;
+                            for (int rr = 0; rr < 64; ++rr)
+                                if (i * 64 + rr < n) colsum[c] += fabs(a(rr, q));
+                        }
+                        // Frobenius partial: 16 entries per thread
+                        double fs = 0.0;
+                        for (int f = t; f < 4096; f += 256) {
+                            const int rr = f >> 6, q = f & 63;
+                            if (i * 64 + rr < n && ccol * 64 + q < n) fs += a(rr, q) * a(rr, q);
+                        }
+                        frob[c] += fs;
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < SC; ++c)
+                    if (c < nc) s2g_tile(Bt(c, i), ldk, sB[c]);   // A_i, kept in sB for the rows above
+#pragma unroll
+                for (int r2 = r + 1; r2 < SR; ++r2) {
                     if (r2 < nr) {
                         g2s_tile(sA, Lt(i, i1 - r2), ldl);
                         __syncthreads();
-                        mma64<true, false>(acc[r2], sA, sB, -1.0);
+#pragma unroll
+                        for (int c = 0; c < SC; ++c)
+                            if (c < nc) mma64<true, false>(acc[r2][c], sA, sB[c], -1.0);
                         __syncthreads();
                     }
                 }
@@ -410,17 +456,21 @@ __global__ __launch_bounds__(256, 2) void k_subst(ChunkDev cd, char *ws) {
             }
         }
     }
-    if (cc < P) {
-        // the whole column tile is final: take mu off the diagonal of A_J
-        if (threadIdx.x < 64) Kb[(int64_t)(cc * 64 + threadIdx.x) * ldk + cc * 64 + threadIdx.x] -= mu;
-        double *colp = (double *)(ws + M.offCol);
-        const int t = threadIdx.x;
-        if (t >= 64 && t < 128) {
-            const int c = t - 64;
-            colp[cc * 64 + c] = (cc * 64 + c < n) ? colsum : 0.0;
+#pragma unroll
+    for (int c = 0; c < SC; ++c) {
+        const int ccol = cc + c;
+        if (c < nc && ccol < P) {
+            // the whole column tile is final: take mu off the diagonal of A_J
+            const int t = threadIdx.x;
+            if (t < 64) Kb[(int64_t)(ccol * 64 + t) * ldk + ccol * 64 + t] -= mu;
+            double *colp = (double *)(ws + M.offCol);
+            if (t >= 64 && t < 128) {
+                const int q = t - 64;
+                colp[ccol * 64 + q] = (ccol * 64 + q < n) ? colsum[c] : 0.0;
+            }
+            const double fsum = block_sum(frob[c], red);
+            if (t == 0) colp[np + ccol] = fsum;
         }
-        const double fsum = block_sum(frob, red);
-        if (t == 0) colp[np + cc] = fsum;
     }
 }
 
@@ -588,8 +638,11 @@ hipError_t launch_chol(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st) 
     return hipGetLastError();
 }
 hipError_t launch_subst(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st) {
-    if (fp32) hipLaunchKernelGGL(k_subst<float>, dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
-    else hipLaunchKernelGGL(k_subst<double>, dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
+    // one column tile per task keeps enough tasks in flight (two per task
+    // halved the concurrency and ran 1.7x slower); FP32 fits three
+    // workgroups per CU
+    if (fp32) hipLaunchKernelGGL((k_subst<float, 4, 1, 3>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
+    else hipLaunchKernelGGL((k_subst<double, 4, 1, 2>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
     return hipGetLastError();
 }
 hipError_t launch_bounds(const ChunkDev &cd, char *ws, const BoundsArgs &ba, int prec, hipStream_t st) {
