@@ -184,6 +184,10 @@ def main():
                          "iteration in the NS precision (16-bit only)")
     ap.add_argument("--want-w", action="store_true",
                     help="also compute the energy-weighted density matrix columns each step")
+    ap.add_argument("--sym", action=argparse.BooleanOptionalAction, default=True,
+                    help="run the 16-bit sign iteration on the symmetric similar matrix "
+                         "L^-1 K L^-T - mu I (upper GEMM tiles only, mirrored; default on, "
+                         "--no-sym iterates on A = S^-1 K - mu I)")
     ap.add_argument("--combine", action="store_true",
                     help="combine submatrices (cubic criterion) before solving")
     ap.add_argument("--bounds-eval", action="store_true",
@@ -226,11 +230,13 @@ def main():
              "persistent": L.SCHED_PERSISTENT}[args.sched]
     dev = torch.device("cuda:0")
     if args.inverse == "auto":
-        args.inverse = "cholesky_fp32" if args.prec in ("fp16", "bf16") else "cholesky"
+        args.inverse = "cholesky"
     inv = {"cholesky": L.INV_CHOLESKY, "cholesky_fp32": L.INV_CHOLESKY_FP32,
            "coupled_ns": L.INV_COUPLED_NS}[args.inverse]
+    sym = 1 if (args.sym and args.prec in ("fp16", "bf16") and args.inverse != "coupled_ns"
+                and not args.want_w) else 0
     sv = Solver(system, prec=args.prec, device=dev, ws_budget=int(args.ws_gb * (1 << 30)), sched=sched,
-                inverse=inv, combine=args.combine)
+                inverse=inv, combine=args.combine, sym_sign=sym)
     if args.want_w:
         sv.want_w()
     info = sv.plan.info()
@@ -266,7 +272,11 @@ def main():
     first = own_J[own_ptr[:-1]]
     ok = np.array([np.all(st["status"][own_J[own_ptr[g]:own_ptr[g + 1]]] == 0) for g in range(len(n))])
     it = st["iters"][first].astype(np.float64)
+    # the paper's count: 2 n^3 per matrix product of the sign iteration; the
+    # symmetric iteration executes only the unique half of each product,
+    # n^2 (n + 1) flops, which is what its kernel roofline is taken on
     gemm_flops = float(((2 * it + 1) * 2.0 * n ** 3)[ok].sum())
+    exec_gemm_flops = float(((2 * it + 1) * n ** 2 * (n + 1))[ok].sum()) if sym else gemm_flops
     # coupled Newton-Schulz inverse: K+1 residual GEMMs, 2K updates, Z^2 and
     # S^-1 K, each 2 n^3 like every counted GEMM
     iti = st["iters_inv"][first].astype(np.float64)
@@ -282,7 +292,7 @@ def main():
     sv.run(stream=stream)
     prof = sv.profile()
     sv.set_opts(profile=0)
-    ns_tf = gemm_flops / (prof["ms_ns"] / 1e3) / 1e12 if prof["ms_ns"] > 0 else 0.0
+    ns_tf = exec_gemm_flops / (prof["ms_ns"] / 1e3) / 1e12 if prof["ms_ns"] > 0 else 0.0
     peak = PEAK_TFLOPS[args.prec]
     roofline = {"bound": "mfma", "achieved": round(ns_tf, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(ns_tf / peak, 4), "traffic": measured_traffic(args.config, args.prec),
@@ -300,7 +310,7 @@ def main():
     m = n / 6.0
     setup_flops = float((n ** 3 / 3.0 + 2.0 * n ** 3 + 12.0 * n ** 2).sum())
     gather_bytes = float((576.0 * m ** 2 + 288.0 * m).sum())
-    terms = {"ns": gemm_flops / (peak * 1e12), "finish": fin_flops / 157.3e12,
+    terms = {"ns": exec_gemm_flops / (peak * 1e12), "finish": fin_flops / 157.3e12,
              "gather_scatter": gather_bytes / 8e12}
     if args.inverse == "coupled_ns":
         terms["inverse"] = inv_flops / (peak * 1e12)
@@ -328,12 +338,14 @@ def main():
         "config": {"workload": WORKLOAD.get(args.config, str(args.config)), "molecules": system.nmol,
                    "submatrix_rows": [int(n.min()), int(round(n.mean())), int(n.max())],
                    "precision": args.prec, "schedule": args.sched, "inverse": args.inverse,
-                   "combined": bool(args.combine), "submatrices": int(len(n)),
+                   "combined": bool(args.combine), "symmetric_sign": bool(sym), "submatrices": int(len(n)),
                    "parallelism": "single GPU"},
         "submatrices_per_s": round(system.nmol / (ms / 1e3), 1),
         "ns_iters": [int(it.min()), round(float(it.mean()), 2), int(it.max())],
         **({"inverse_iters": [int(iti.min()), round(float(iti.mean()), 2), int(iti.max())]}
            if args.inverse == "coupled_ns" else {}),
+        "flop_count": "2 n^3 per matrix product of the sign iteration (the paper's count)"
+                      + ("; the symmetric iteration executes n^2 (n + 1) of it, the roofline's count" if sym else ""),
         "status_ok": int((st["status"] == 0).sum()),
         "phases_ms": phases,
         "roofline": roofline,

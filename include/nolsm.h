@@ -99,7 +99,7 @@ typedef enum {
  * Y_J = T_J(S)^-1 E_cJ. */
 typedef enum {
     NOLSM_INV_CHOLESKY = 0,        /* FP64 Cholesky factor and substitution
-                                      (default for FP64 / FP32)                 */
+                                      (default)                                 */
     NOLSM_INV_COUPLED_NS = 1,      /* FP16/BF16 only: the coupled Newton-Schulz
                                       iteration of Eq. inv1-inv3 on the matrix
                                       cores (FP32 accumulation): Y_0 = c S_J,
@@ -113,7 +113,7 @@ typedef enum {
                                       S^-1 K_J - mu I by two more GEMMs, with
                                       c = 1 / max row sum of |S_J|. A diverging
                                       iteration marks the molecule NOT_SPD.   */
-    NOLSM_INV_CHOLESKY_FP32 = 2    /* FP16/BF16 only (their default): the same
+    NOLSM_INV_CHOLESKY_FP32 = 2    /* FP16/BF16 only: the same
                                       Cholesky factor and substitution with FP32
                                       arithmetic on the matrix cores, FP64
                                       storage; its relative error, about
@@ -157,10 +157,19 @@ typedef struct {
                                 P = (I - sign A_J)/2 a projector commuting with
                                 A_J. Zero for NOT_SPD molecules. Null: skipped.
                                 Assemble W with nolsm_assemble_D.                */
-    int32_t inverse;         /* nolsm_inverse (default NOLSM_INV_CHOLESKY_FP32
-                                for FP16/BF16, NOLSM_INV_CHOLESKY otherwise)    */
+    int32_t inverse;         /* nolsm_inverse (default NOLSM_INV_CHOLESKY)       */
     int32_t inv_max_iter;    /* coupled Newton-Schulz iteration slots, 2..128
                                 (default 40; used by configure)                  */
+    int32_t sym_sign;        /* FP16/BF16 with a Cholesky route: != 0 runs the
+                                sign iteration on the symmetric similar matrix
+                                L^-1 T_J(K) L^-T - mu I (same spectrum;
+                                sign(A_J) = L^-T sign(.) L^T), so each GEMM
+                                computes its upper tiles only and mirrors
+                                them; the owned columns are L^-T (y - sign(.) y)
+                                / 2 with y = L^-1 E_cJ, the same D. Not with
+                                d_wcols, d_features or learned bounds (defined
+                                on A_J). Default 0; used by configure.         */
+    int32_t reserved_;       /* 0                                                */
 } nolsm_solve_opts;
 
 /* Fills *o with the defaults above for precision `prec`. */

@@ -141,6 +141,8 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
     na.rmax = o.switch_rmax > 0 ? o.switch_rmax : 0.5;
     na.persistent = o.sched == NOLSM_SCHED_PERSISTENT;
     na.pgrid = pl->pgrid;
+    na.sym = o.sym_sign ? 1 : 0;
+    na.pad_ = 0;
     InvArgs ia;
     ia.prec = o.prec;
     ia.max_iter = o.inv_max_iter;
@@ -169,6 +171,8 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
     ea.bs = pl->bs;
     ea.prec = o.prec;
     ea.nfinal = fa.nfinal;
+    ea.sym = o.sym_sign ? 1 : 0;
+    ea.L_fp32 = o.inverse == NOLSM_INV_CHOLESKY_FP32;
     for (const HostChunk &ch : pl->chunks) {
         const ChunkDev cd = chunk_dev(pl, ch, b.ws);
         hipError_t e;
@@ -177,6 +181,12 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
         if (o.inverse == NOLSM_INV_COUPLED_NS) {
             if (prof) prof->mark(PH_INV);
             if ((e = launch_inverse(cd, b.ws, ia, st)) != hipSuccess) return hip_fail(e, "inverse launch");
+        } else if (o.sym_sign) {
+            const bool fp32 = o.inverse == NOLSM_INV_CHOLESKY_FP32;
+            if (prof) prof->mark(PH_CHOL);
+            if ((e = launch_chol(cd, b.ws, fp32, st)) != hipSuccess) return hip_fail(e, "Cholesky launch");
+            if (prof) prof->mark(PH_SUBST);
+            if ((e = launch_subst_sym(cd, b.ws, fp32, st)) != hipSuccess) return hip_fail(e, "substitution launch");
         } else {
             if (prof) prof->mark(PH_CHOL);
             const bool fp32 = o.inverse == NOLSM_INV_CHOLESKY_FP32;
@@ -221,6 +231,7 @@ extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const doub
     }
     if (!pl->bound) { nolsm_set_last_error("sign_batch: plan not bound"); return NOLSM_E_STATE; }
     if (opts->prec != pl->prec || opts->max_iter != pl->max_iter || opts->inverse != pl->inverse ||
+        (opts->sym_sign != 0) != (pl->sym != 0) ||
         (pl->inverse == NOLSM_INV_COUPLED_NS && opts->inv_max_iter != pl->inv_max_iter) ||
         ((opts->sched == NOLSM_SCHED_PER_BUCKET) != (pl->sched == NOLSM_SCHED_PER_BUCKET))) {
         nolsm_set_last_error("sign_batch: options differ from the configured ones");
@@ -228,6 +239,11 @@ extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const doub
     }
     if (opts->d_wcols && (pl->bs & 1)) {
         nolsm_set_last_error("sign_batch: the energy-weighted output needs an even block size");
+        return NOLSM_E_ARG;
+    }
+    if (opts->sym_sign && (opts->d_wcols || opts->d_features || opts->bounds == NOLSM_BOUNDS_LEARNED)) {
+        nolsm_set_last_error("sign_batch: W, features and learned bounds are defined on A_J: "
+                             "they need sym_sign = 0");
         return NOLSM_E_ARG;
     }
     if (opts->bounds == NOLSM_BOUNDS_LEARNED && (!opts->d_mlp || !opts->d_mlp_norm)) {

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_skinny(ChunkDev cd, char *ws, SkinnyArg
     if (ctl->status == NOLSM_MOL_NOT_SPD) return;
     const int np = M.np, t = threadIdx.x;
     const int K = ctl->iters;
-    const ST *P = (const ST *)(ws + ((K & 1) ? M.offX1 : M.offL));
+    const ST *P = (const ST *)(ws + ((K & 1) ? M.offX1 : M.offX0));
     const int64_t vs = (int64_t)np * 6 * 8 / sizeof(TV);
     TV *V = (TV *)(ws + M.offVec) + (int64_t)o * NOLSM_NVEC * vs;
     for (int f = t; f < np * 6; f += 256) {
@@ -153,10 +153,55 @@ struct MolStatsDev {
 };
 static_assert(sizeof(MolStatsDev) == sizeof(nolsm_mol_stats), "stats layout");
 
+// Symmetric sign iteration: Df (np x bs in LDS) holds (y - sign(A~) y) / 2
+// with y = L^-1 E; the column block of D is L^-T of it. Backward
+// substitution over 64-row blocks with the factor and its diagonal-tile
+// inverses (FP64 arithmetic). Per block, thread (g, r) (g = t / 64 of 4
+// groups, r = t % 64) sums rows g, g + 4, .. of column i 64 + r of L against
+// all bs columns of the solved part (lanes read consecutive r: coalesced),
+// and the 4 partial sums meet in LDS. tmp: 4 x 64 x BSMAX doubles of LDS.
+template <typename TL>
+__device__ void back_solve_lt(const TL *L, const TL *Dinv, const SubMeta &M, double *Df, double *tmp, int bs) {
+    const int t = threadIdx.x, np = M.np, r = t & 63, g = t >> 6;
+    for (int i = M.P - 1; i >= 0; --i) {
+        double a[BSMAX];
+#pragma unroll
+        for (int c = 0; c < BSMAX; ++c) a[c] = 0.0;
+        const TL *lc = L + i * 64 + r;   // column i 64 + r of L
+#pragma unroll 4
+        for (int row = (i + 1) * 64 + g; row < np; row += 4) {
+            const double lv = (double)lc[(int64_t)row * np];
+#pragma unroll
+            for (int c = 0; c < BSMAX; ++c)
+                if (c < bs) a[c] += lv * Df[row * bs + c];
+        }
+#pragma unroll
+        for (int c = 0; c < BSMAX; ++c) tmp[(g * 64 + r) * BSMAX + c] = a[c];
+        __syncthreads();
+        if (t < 64) {
+#pragma unroll
+            for (int c = 0; c < BSMAX; ++c)
+                if (c < bs)
+                    tmp[r * BSMAX + c] = Df[(i * 64 + r) * bs + c] - tmp[r * BSMAX + c] - tmp[(64 + r) * BSMAX + c] -
+                                         tmp[(128 + r) * BSMAX + c] - tmp[(192 + r) * BSMAX + c];
+        }
+        __syncthreads();
+        for (int p = t; p < 64 * bs; p += 256) {
+            const int rr = p & 63, c = p >> 6;
+            const TL *dc = Dinv + (int64_t)i * 4096 + rr;   // column rr of Dinv_i
+            double x = 0.0;
+            for (int q = 0; q < 64; ++q) x += (double)dc[q * 64] * tmp[q * BSMAX + c];
+            Df[(i * 64 + rr) * bs + c] = x;
+        }
+        __syncthreads();
+    }
+}
+
 template <typename TV>
 __global__ __launch_bounds__(256) void k_extract(ChunkDev cd, char *ws, ExtractArgs ea) {
     extern __shared__ double smem[];
     __shared__ double red[256];
+    __shared__ double tmp[4 * 64 * BSMAX];
     const int s = blockIdx.x;
     if (s >= cd.nsub) return;
     const SubMeta M = cd.meta[s];
@@ -191,6 +236,10 @@ __global__ __launch_bounds__(256) void k_extract(ChunkDev cd, char *ws, ExtractA
             Df[f] = v;
         }
         __syncthreads();
+        if (ea.sym && ok) {
+            if (ea.L_fp32) back_solve_lt((const float *)(ws + M.offL), (const float *)(ws + M.offDinv), M, Df, tmp, bs);
+            else back_solve_lt((const double *)(ws + M.offL), (const double *)(ws + M.offDinv), M, Df, tmp, bs);
+        }
         // the owned columns on the rows N(J) (the pattern of D), through
         // the row positions of N(J) in this submatrix
         double *Dout = ea.Dcols + (int64_t)bs * bs * so;

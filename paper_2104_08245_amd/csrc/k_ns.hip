@@ -75,17 +75,19 @@ template <> __device__ __forceinline__ double to_t<double>(float x) { return x; 
 template <> __device__ __forceinline__ float to_t<float>(float x) { return x; }
 template <typename T> __device__ __forceinline__ T to_t_d(double x) { return (T)x; }
 
-// X_{k+1} tile <- c_G A on [0,n)^2, identity on the padding (restart)
+// X_{k+1} tile <- c_G A on [0,n)^2, identity on the padding (restart);
+// sym: from the upper triangle of A, so that the restart is exactly symmetric
 template <typename T, typename Cvt>
 __device__ void restart_tile(const SubMeta &M, const SubCtl *ctl, const char *ws, T *Xn, int r0, int c0,
-                             int rows, int cols, Cvt cvt) {
+                             int rows, int cols, Cvt cvt, bool sym = false) {
     const double *A = (const double *)(ws + M.offK);
     const int64_t ldk = M.np + 64;
     const double c = ctl->scale_g;
     for (int f = threadIdx.x; f < rows * cols; f += blockDim.x) {
         const int r = r0 + f / cols, q = c0 + f % cols;
         if (r >= M.np || q >= M.np) continue;
-        const double v = (r < M.n && q < M.n) ? c * A[(int64_t)r * ldk + q] : (r == q ? 1.0 : 0.0);
+        const int ra = sym ? min(r, q) : r, qa = sym ? max(r, q) : q;
+        const double v = (r < M.n && q < M.n) ? c * A[(int64_t)ra * ldk + qa] : (r == q ? 1.0 : 0.0);
         Xn[(int64_t)r * M.ldx + q] = cvt(v);
     }
 }
@@ -136,8 +138,8 @@ __device__ __forceinline__ void ns64_tile(const ChunkDev &cd, uint32_t task, cha
     const SubMeta M = cd.meta[s];
     SubCtl *ctl = cd.ctl + s;
     const int np = M.np, nt = np / 64, tile = ti * nt + tj;
-    T *Xc = (T *)(ws + ((it & 1) ? M.offX1 : M.offL));
-    T *Xn = (T *)(ws + ((it & 1) ? M.offL : M.offX1));
+    T *Xc = (T *)(ws + ((it & 1) ? M.offX1 : M.offX0));
+    T *Xn = (T *)(ws + ((it & 1) ? M.offX0 : M.offX1));
     T *Bb = (T *)(ws + M.offB);
     // one thread reads the control state and decides for the whole workgroup
     if (threadIdx.x == 0) act_s = ctl->done ? ACT_STOP : (mode == 2 ? ns_decide(na, M, ctl, ws, it, tile) : ACT_UPDATE);
@@ -233,10 +235,72 @@ __global__ __launch_bounds__(256) void k_ns64_pq(ChunkDev cd, int ntask, int *q,
 }
 
 // ------------------------------------------------------------ FP16 / BF16
+// Symmetric sign iteration: the output tile (16-bit values) is staged
+// transposed in the operand LDS of lp_tile_product (free once it returns):
+// BM rows of BM values, 16-byte chunks swizzled by row, entry (r, c) of the
+// tile at row c, column r. Each lane holds 4 consecutive rows of one column
+// per group of 4 accumulator elements: one 8-byte store each.
+template <int BM> __device__ __forceinline__ int sym_idx(int row, int col) {
+    return row * BM + ((((col >> 3) ^ row) & (BM / 8 - 1)) << 3) + (col & 7);
+}
+template <int BM, typename Val> __device__ __forceinline__ void sym_stage(Val val) {
+    constexpr int WT = BM / 2, NB = WT / 32;
+    uint16_t *st = lp_lds<BM>();
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int rl = wm * WT + i * 32 + q * 8 + (l >> 5) * 4, cl = wn * WT + j * 32 + (l & 31);
+                const uint32_t lo = (uint32_t)val(i, j, 4 * q) | ((uint32_t)val(i, j, 4 * q + 1) << 16);
+                const uint32_t hi = (uint32_t)val(i, j, 4 * q + 2) | ((uint32_t)val(i, j, 4 * q + 3) << 16);
+                *(uint2 *)(st + sym_idx<BM>(cl, rl)) = make_uint2(lo, hi);
+            }
+}
+// off-diagonal tile (ti, tj): its transpose goes to tile (tj, ti), 16-byte
+// row stores from the staged copy
+template <int BM> __device__ __forceinline__ void sym_store_mirror(uint16_t *X, int ldx, int row0, int col0) {
+    constexpr int NCH = BM / 8;
+    const uint16_t *st = lp_lds<BM>();
+    for (int f = threadIdx.x; f < BM * NCH; f += 256) {
+        const int cl = f / NCH, ch = f % NCH;
+        *(uint4 *)(X + (int64_t)(col0 + cl) * ldx + row0 + ch * 8) = *(const uint4 *)(st + sym_idx<BM>(cl, ch * 8));
+    }
+}
+// diagonal tile: X R (and X X^T up to rounding) is symmetric only in exact
+// arithmetic, and an iteration whose B operand is read as rows (X^T) doubles
+// the skew part that anticommutes with the sign at every step. The tile is
+// written exactly symmetric, from its upper triangle: (r, c) takes T[r][c]
+// for r <= c and T[c][r] below (staged copy: T[r][c] at row c, column r).
+template <int BM> __device__ __forceinline__ void sym_store_diag(uint16_t *X, int ldx, int row0) {
+    constexpr int NCH = BM / 8;
+    const uint16_t *st = lp_lds<BM>();
+    for (int f = threadIdx.x; f < BM * NCH; f += 256) {
+        const int r = f / NCH, c0 = (f % NCH) * 8;
+        uint4 v;
+        if (c0 + 7 < r) {
+            v = *(const uint4 *)(st + sym_idx<BM>(r, c0));   // T[c][r], c < r: row r of the copy
+        } else {
+            uint16_t h[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int c = c0 + k;
+                h[k] = (r <= c) ? st[sym_idx<BM>(c, r)] : st[sym_idx<BM>(r, c)];
+            }
+            v = make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16), h[4] | ((uint32_t)h[5] << 16),
+                           h[6] | ((uint32_t)h[7] << 16));
+        }
+        *(uint4 *)(X + (int64_t)(row0 + r) * ldx + row0 + c0) = v;
+    }
+}
+
 // One BM x BM tile of a sign-iteration GEMM: mode 1 forms R = I - X_k^2 and
 // the tile's share of ||R||_F^2, mode 2 decides stop / continue / restart and
-// forms X_{k+1} = X_k + X_k R / 2.
-template <typename T, int BM>
+// forms X_{k+1} = X_k + X_k R / 2. SYM: X_k and R are symmetric, only tiles
+// ti <= tj are launched and each writes its mirror too.
+template <typename T, int BM, bool SYM>
 __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, char *ws, const NsArgs &na, int it,
                                            int mode) {
     __shared__ double red[256];
@@ -246,8 +310,8 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
     const SubMeta M = cd.meta[s];
     SubCtl *ctl = cd.ctl + s;
     const int np = M.np, nt = (np + BM - 1) / BM, tile = ti * nt + tj;
-    uint16_t *Xc = (uint16_t *)(ws + ((it & 1) ? M.offX1 : M.offL));
-    uint16_t *Xn = (uint16_t *)(ws + ((it & 1) ? M.offL : M.offX1));
+    uint16_t *Xc = (uint16_t *)(ws + ((it & 1) ? M.offX1 : M.offX0));
+    uint16_t *Xn = (uint16_t *)(ws + ((it & 1) ? M.offX0 : M.offX1));
     uint16_t *Bb = (uint16_t *)(ws + M.offB);
     // one thread reads the control state and decides for the whole workgroup
     if (threadIdx.x == 0) act_s = ctl->done ? ACT_STOP : (mode == 2 ? ns_decide(na, M, ctl, ws, it, tile) : ACT_UPDATE);
@@ -256,7 +320,11 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
         const int act = act_s;
         if (act == ACT_STOP) return;
         if (act == ACT_RESTART) {
-            restart_tile(M, ctl, ws, Xn, ti * BM, tj * BM, BM, BM, [](double v) { return Lp<T>::enc((float)v); });
+            restart_tile(M, ctl, ws, Xn, ti * BM, tj * BM, BM, BM, [](double v) { return Lp<T>::enc((float)v); },
+                         SYM);
+            if (SYM && ti != tj)
+                restart_tile(M, ctl, ws, Xn, tj * BM, ti * BM, BM, BM, [](double v) { return Lp<T>::enc((float)v); },
+                             SYM);
             return;
         }
     }
@@ -265,7 +333,7 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
     const int row0 = ti * BM, col0 = tj * BM, ldx = M.ldx;
     const int nrec = ldx * ldx * 2;
     v16f acc[NB][NB];
-    lp_tile_product<T, BM>(Xc, (mode == 1) ? Xc : Bb, ldx, np, row0, col0, acc);
+    lp_tile_product<T, BM, SYM>(Xc, (mode == 1) ? Xc : Bb, ldx, np, row0, col0, acc);
     // Epilogue over the whole tile, padding included: rows and columns in
     // [np, ldx) of R and X_{k+1} only ever feed outputs that are never used,
     // so the accesses need no bounds test and the X_k reads of the update
@@ -275,7 +343,61 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
     const int er0 = row0 + wm * WT + (l >> 5) * 4, ec0 = col0 + wn * WT + (l & 31);
     const uint32_t eo = (uint32_t)((er0 * ldx + ec0) * 2);
 #define NS_EOFF(i, j, e) ((((i) * 32 + ((e) >> 2) * 8 + ((e) & 3)) * ldx + (j) * 32) * 2)
-    if (mode == 1) {
+    if constexpr (SYM) {
+        // every value is formed first and staged in LDS behind one barrier,
+        // and all global stores come after it: a barrier behind stores
+        // would wait for them to complete
+        uint16_t *Out;
+        if (mode == 1) {
+            double part = 0.0;
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int gr = er0 + i * 32 + (e >> 2) * 8 + (e & 3), gc = ec0 + j * 32;
+                        acc[i][j][e] = (gr == gc ? 1.0f : 0.0f) - acc[i][j][e];   // R
+                        if (gr < np && gc < np) part += (double)acc[i][j][e] * (double)acc[i][j][e];
+                    }
+            const double sum = block_sum(part, red);
+            if (threadIdx.x == 0) {
+                double *res = (double *)(ws + M.offRes) + (int64_t)it * M.ntile_ns;
+                res[tile] = (ti != tj ? 2.0 : 1.0) * sum;   // the mirror tile is never launched
+                if (ti != tj) res[tj * nt + ti] = 0.0;
+            }
+            Out = Bb;
+        } else {
+            const __amdgpu_buffer_rsrc_t rsX = __builtin_amdgcn_make_buffer_rsrc((void *)Xc, (short)0, nrec, 0x00020000);
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    uint16_t xo[16];
+#pragma unroll
+                    for (int e = 0; e < 16; ++e)
+                        xo[e] = __builtin_amdgcn_raw_buffer_load_b16(rsX, eo, NS_EOFF(i, j, e), 0);
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) acc[i][j][e] = Lp<T>::dec(xo[e]) + 0.5f * acc[i][j][e];
+                }
+            Out = Xn;
+        }
+        sym_stage<BM>([&](int i, int j, int e) { return Lp<T>::enc(acc[i][j][e]); });
+        __syncthreads();
+        if (ti != tj) {
+            const __amdgpu_buffer_rsrc_t rsO = __builtin_amdgcn_make_buffer_rsrc((void *)Out, (short)0, nrec, 0x00020000);
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e)
+                        __builtin_amdgcn_raw_buffer_store_b16(Lp<T>::enc(acc[i][j][e]), rsO, eo, NS_EOFF(i, j, e), 0);
+            sym_store_mirror<BM>(Out, ldx, row0, col0);
+        } else {
+            sym_store_diag<BM>(Out, ldx, row0);
+        }
+    } else if (mode == 1) {
         const __amdgpu_buffer_rsrc_t rsR = __builtin_amdgcn_make_buffer_rsrc((void *)Bb, (short)0, nrec, 0x00020000);
         double part = 0.0;
 #pragma unroll
@@ -315,13 +437,13 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
 #undef NS_EOFF
 }
 
-template <typename T, int BM>
+template <typename T, int BM, bool SYM>
 __global__ __launch_bounds__(256, 3) void k_ns_lp(ChunkDev cd, const uint32_t *tasks, char *ws, NsArgs na, int it,
                                                int mode) {
-    ns_lp_tile<T, BM>(cd, xcd_task(tasks), ws, na, it, mode);
+    ns_lp_tile<T, BM, SYM>(cd, xcd_task(tasks), ws, na, it, mode);
 }
 
-template <typename T, int BM>
+template <typename T, int BM, bool SYM>
 __global__ __launch_bounds__(256, 3) void k_ns_lp_pq(ChunkDev cd, const uint32_t *tasks, int ntask, int *q, char *ws,
                                                   NsArgs na, int it, int mode) {
     __shared__ int idx_s;
@@ -329,7 +451,7 @@ __global__ __launch_bounds__(256, 3) void k_ns_lp_pq(ChunkDev cd, const uint32_t
     for (;;) {
         const int i = queue_pop(q + x, &idx_s);
         if (i >= seg) break;
-        ns_lp_tile<T, BM>(cd, tasks[x * seg + i], ws, na, it, mode);
+        ns_lp_tile<T, BM, SYM>(cd, tasks[x * seg + i], ws, na, it, mode);
     }
 }
 
@@ -343,21 +465,21 @@ static int persistent_grid(const NsArgs &na, int ntask) {
     return g < 8 ? 8 : g;
 }
 
-template <typename T>
+template <typename T, bool SYM>
 static void launch_lp(const ChunkDev &cd, char *ws, const NsArgs &na, int it, int mode, hipStream_t st) {
     if (na.persistent) {
         if (cd.n_ns > 0)
-            hipLaunchKernelGGL((k_ns_lp_pq<T, 128>), dim3(persistent_grid(na, cd.n_ns)), dim3(256), 0, st, cd, cd.t_ns,
-                               cd.n_ns, launch_queue(cd, it, mode, 0), ws, na, it, mode);
+            hipLaunchKernelGGL((k_ns_lp_pq<T, 128, SYM>), dim3(persistent_grid(na, cd.n_ns)), dim3(256), 0, st, cd,
+                               cd.t_ns, cd.n_ns, launch_queue(cd, it, mode, 0), ws, na, it, mode);
         if (cd.n_ns64 > 0)
-            hipLaunchKernelGGL((k_ns_lp_pq<T, 64>), dim3(persistent_grid(na, cd.n_ns64)), dim3(256), 0, st, cd,
+            hipLaunchKernelGGL((k_ns_lp_pq<T, 64, SYM>), dim3(persistent_grid(na, cd.n_ns64)), dim3(256), 0, st, cd,
                                cd.t_ns64, cd.n_ns64, launch_queue(cd, it, mode, 1), ws, na, it, mode);
         return;
     }
     if (cd.n_ns > 0)
-        hipLaunchKernelGGL((k_ns_lp<T, 128>), dim3(cd.n_ns), dim3(256), 0, st, cd, cd.t_ns, ws, na, it, mode);
+        hipLaunchKernelGGL((k_ns_lp<T, 128, SYM>), dim3(cd.n_ns), dim3(256), 0, st, cd, cd.t_ns, ws, na, it, mode);
     if (cd.n_ns64 > 0)
-        hipLaunchKernelGGL((k_ns_lp<T, 64>), dim3(cd.n_ns64), dim3(256), 0, st, cd, cd.t_ns64, ws, na, it, mode);
+        hipLaunchKernelGGL((k_ns_lp<T, 64, SYM>), dim3(cd.n_ns64), dim3(256), 0, st, cd, cd.t_ns64, ws, na, it, mode);
 }
 
 template <typename T>
@@ -375,8 +497,14 @@ hipError_t launch_ns_iter(const ChunkDev &cd, char *ws, const NsArgs &na, int it
         switch (na.prec) {
             case NOLSM_FP64: launch_64<double>(cd, ws, na, it, mode, st); break;
             case NOLSM_FP32: launch_64<float>(cd, ws, na, it, mode, st); break;
-            case NOLSM_FP16: launch_lp<_Float16>(cd, ws, na, it, mode, st); break;
-            default: launch_lp<__bf16>(cd, ws, na, it, mode, st); break;
+            case NOLSM_FP16:
+                if (na.sym) launch_lp<_Float16, true>(cd, ws, na, it, mode, st);
+                else launch_lp<_Float16, false>(cd, ws, na, it, mode, st);
+                break;
+            default:
+                if (na.sym) launch_lp<__bf16, true>(cd, ws, na, it, mode, st);
+                else launch_lp<__bf16, false>(cd, ws, na, it, mode, st);
+                break;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

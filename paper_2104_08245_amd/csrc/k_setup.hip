@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256, 2) void k_chol(ChunkDev cd, char *ws) {
 // column once per pass (the tasks of a submatrix are adjacent in the task
 // list and share L through one XCD's L2 while they run together).
 // ---------------------------------------------------------------------------
-template <typename T, int SR, int SC, int OCC>
+template <typename T, int SR, int SC, int OCC, bool FWD_ONLY>
 __global__ __launch_bounds__(256, OCC) void k_subst(ChunkDev cd, char *ws) {
     const double mu = ((const WsHeader *)ws)->mu;
     __shared__ T sA[64][LDP];
@@ -358,6 +358,8 @@ __global__ __launch_bounds__(256, OCC) void k_subst(ChunkDev cd, char *ws) {
             }
         }
     }
+    // symmetric route: [W | y] = L^-1 [K | E] is all this kernel forms
+    if constexpr (FWD_ONLY) return;
     // backward: A_i = Dinv_i^T (W_i - sum_{k>i} L_ki^T A_k), passes from the bottom
     double colsum[SC], frob[SC];
 #pragma unroll
@@ -472,6 +474,115 @@ __global__ __launch_bounds__(256, OCC) void k_subst(ChunkDev cd, char *ws) {
             if (t == 0) colp[np + ccol] = fsum;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric sign iteration, second half of the setup: with W = L^-1 K_J in the K
+// buffer (from the forward-only substitution), A~ = W L^-T = L^-1 K_J L^-T,
+// row block i per task, in place: X_ij = (W_ij - sum_{k<j} X_ik L_jk^T)
+// Dinv_j^T over the column tiles j in order. A row task owns its rows, so
+// the in-place update needs no other task. A~ - mu I has the spectrum of
+// A_J; being symmetric, its column sums are its row sums. Emits the bounds
+// inputs in the layout of k_subst (row sums per column tile, column sums,
+// Frobenius partials, here per row block) and takes mu off the diagonal once
+// the row block is complete. Task list: (slot, i) of k_subst; i = P returns.
+// RR column tiles per pass with their accumulators in registers.
+// ---------------------------------------------------------------------------
+template <typename T, int RR, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_rsolve(ChunkDev cd, char *ws) {
+    const double mu = ((const WsHeader *)ws)->mu;
+    __shared__ T sX[64][LDP];
+    __shared__ T sL[64][LDP];
+    __shared__ double red[256];
+    const uint32_t task = xcd_task(cd.t_subst);
+    if (task == NOLSM_TASK_NONE) return;
+    const int s = task_slot(task), i = task_a(task);
+    const SubMeta M = cd.meta[s];
+    if (cd.ctl[s].status != NOLSM_MOL_OK) return;
+    const int P = M.P, np = M.np, n = M.n;
+    if (i >= P) return;
+    const int64_t ldl = np, ldk = np + 64;
+    const T *L = (const T *)(ws + M.offL);
+    const T *Dinv = (const T *)(ws + M.offDinv);
+    double *Kb = (double *)(ws + M.offK);
+    auto Lt = [&](int r, int c) { return L + (int64_t)(r * 64) * ldl + c * 64; };
+    auto Xt = [&](int j) { return Kb + (int64_t)(i * 64) * ldk + j * 64; };   // tile (i, j)
+    const int t = threadIdx.x;
+    double rtot = 0.0, frob = 0.0;
+    for (int j0 = 0; j0 < P; j0 += RR) {
+        const int nr = min(RR, P - j0);
+        AccT<T> acc[RR];
+#pragma unroll
+        for (int r = 0; r < RR; ++r)
+            if (r < nr) g2acc(acc[r], Xt(j0 + r), ldk);
+        for (int k = 0; k < j0; ++k) {
+            g2s_tile(sX, Xt(k), ldk);
+#pragma unroll
+            for (int r = 0; r < RR; ++r) {
+                if (r < nr) {
+                    g2s_tile(sL, Lt(j0 + r, k), ldl);
+                    __syncthreads();
+                    mma64<false, true>(acc[r], sX, sL, -1.0);   // - X_ik L_jk^T
+                    __syncthreads();
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+            if (r < nr) {
+                const int j = j0 + r;
+                g2s_tile(sL, Dinv + (int64_t)j * 4096, 64);
+                acc2s(sX, acc[r]);
+                __syncthreads();
+                AccT<T> o;
+                acc_zero(o);
+                mma64<false, true>(o, sX, sL);   // acc Dinv_j^T
+                __syncthreads();
+                acc2s(sX, o);
+                __syncthreads();
+                {
+                    // bounds inputs of A~ - mu I (stored unshifted: later
+                    // tiles of this row block still use it)
+                    auto a = [&](int rr, int q) { return (double)sX[rr][q] - ((i == j && rr == q) ? mu : 0.0); };
+                    if (t < 64) {
+                        const int gr = i * 64 + t;
+                        double rs = 0.0;
+                        for (int q = 0; q < 64; ++q)
+                            if (j * 64 + q < n) rs += fabs(a(t, q));
+                        double *rowp = (double *)(ws + M.offRow);
+                        rowp[(int64_t)j * np + gr] = (gr < n) ? rs : 0.0;
+                        rtot += rs;
+                    }
+                    double fs = 0.0;
+                    for (int f = t; f < 4096; f += 256) {
+                        const int rr = f >> 6, q = f & 63;
+                        if (i * 64 + rr < n && j * 64 + q < n) fs += a(rr, q) * a(rr, q);
+                    }
+                    frob += fs;
+                }
+                s2g_tile(Xt(j), ldk, sX);   // X_ij, kept in sX for the tiles to its right
+#pragma unroll
+                for (int r2 = r + 1; r2 < RR; ++r2) {
+                    if (r2 < nr) {
+                        g2s_tile(sL, Lt(j0 + r2, j), ldl);
+                        __syncthreads();
+                        mma64<false, true>(acc[r2], sX, sL, -1.0);
+                        __syncthreads();
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    // the row block is final: take mu off its diagonal; column sums of the
+    // symmetric matrix are its row sums
+    if (t < 64) {
+        Kb[(int64_t)(i * 64 + t) * ldk + i * 64 + t] -= mu;
+        double *colp = (double *)(ws + M.offCol);
+        colp[i * 64 + t] = (i * 64 + t < n) ? rtot : 0.0;
+    }
+    const double fsum = block_sum(frob, red);
+    if (t == 0) ((double *)(ws + M.offCol))[np + i] = fsum;
 }
 
 // ---------------------------------------------------------------------------
@@ -599,7 +710,7 @@ __global__ __launch_bounds__(256) void k_convert(ChunkDev cd, char *ws, int use_
     const double c = use_scale_g ? ctl->scale_g : ctl->scale;
     const int n = M.n, np = M.np;
     const double *A = (const double *)(ws + M.offK);
-    T *X = (T *)(ws + M.offL);
+    T *X = (T *)(ws + M.offX0);
     const int64_t ldk = np + 64;
     for (int f = threadIdx.x; f < 4096; f += 256) {
         const int r = ti * 64 + (f >> 6), q = tj * 64 + (f & 63);
@@ -637,17 +748,32 @@ hipError_t launch_chol(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st) 
     else hipLaunchKernelGGL(k_chol<double>, dim3(cd.nsub), dim3(256), 0, st, cd, ws);
     return hipGetLastError();
 }
+hipError_t launch_subst_sym(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st) {
+    if (fp32) {
+        hipLaunchKernelGGL((k_subst<float, 4, 1, 3, true>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_rsolve<float, 4, 3>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
+    } else {
+        hipLaunchKernelGGL((k_subst<double, 4, 1, 2, true>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_rsolve<double, 4, 2>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
+    }
+    return hipGetLastError();
+}
 hipError_t launch_subst(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st) {
     // one column tile per task keeps enough tasks in flight (two per task
     // halved the concurrency and ran 1.7x slower); FP32 fits three
     // workgroups per CU
-    if (fp32) hipLaunchKernelGGL((k_subst<float, 4, 1, 3>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
-    else hipLaunchKernelGGL((k_subst<double, 4, 1, 2>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
+    if (fp32) hipLaunchKernelGGL((k_subst<float, 4, 1, 3, false>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
+    else hipLaunchKernelGGL((k_subst<double, 4, 1, 2, false>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
     return hipGetLastError();
 }
 hipError_t launch_bounds(const ChunkDev &cd, char *ws, const BoundsArgs &ba, int prec, hipStream_t st) {
     hipLaunchKernelGGL(k_bounds, dim3(cd.nsub), dim3(256), 0, st, cd, ws, ba);
     LAUNCH_CHECK();
+    // symmetric sign iteration: X_0 may differ from its transpose by a unit
+    // of the last place where A~'s two triangles round apart; the first
+    // update rebuilds X_1 exactly symmetric from the upper tiles
     return launch_convert(cd, ws, prec, 0, st);
 }
 

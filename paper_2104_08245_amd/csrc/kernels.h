@@ -35,6 +35,8 @@ struct NsArgs {
     double theta, rmax;    // stagnation switch: r_k > theta r_{k-1} and r_k < rmax
     int32_t persistent;    // queue-driven fixed grid instead of one workgroup per tile
     int32_t pgrid;         // workgroups of a persistent launch
+    int32_t sym;           // symmetric sign iteration: upper tiles, mirrored (FP16/BF16)
+    int32_t pad_;
 };
 
 // Coupled Newton-Schulz inverse (Eq. inv1-inv3), stop rule as for the sign
@@ -66,6 +68,8 @@ struct ExtractArgs {
     int32_t bs;
     int32_t prec;
     int32_t nfinal;
+    int32_t sym;           // symmetric sign iteration: apply L^-T to the column block
+    int32_t L_fp32;        // the factor is stored in FP32 (else FP64)
 };
 
 hipError_t launch_gather(const ChunkDev &cd, char *ws, const GatherArgs &ga, hipStream_t st);
@@ -74,6 +78,8 @@ hipError_t launch_inverse(const ChunkDev &cd, char *ws, const InvArgs &ia, hipSt
 // fp32: arithmetic on the FP32 matrix cores (FP64 storage either way)
 hipError_t launch_chol(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st);
 hipError_t launch_subst(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st);
+// symmetric sign iteration: [W | y] = L^-1 [K | E], then A~ = W L^-T - mu I in place
+hipError_t launch_subst_sym(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st);
 hipError_t launch_set_header(char *ws, double mu, hipStream_t st);
 hipError_t launch_trace_sums(const void *stats, int32_t nb, char *ws, hipStream_t st);
 hipError_t launch_bounds(const ChunkDev &cd, char *ws, const BoundsArgs &ba, int prec, hipStream_t st);

@@ -39,6 +39,14 @@ template <> struct Lp<__bf16> {
 // row per 8 columns) spread over all positions as well.
 __device__ __forceinline__ int lds_swz(int n, int c) { return n * LBK + ((c ^ ((n ^ (n >> 3)) & 7)) << 3); }
 
+// The two operand tiles of lp_tile_product (BM x LBK 16-bit values each),
+// one allocation per kernel; free again when lp_tile_product returns, so an
+// epilogue may stage through them.
+template <int BM> __device__ __forceinline__ uint16_t *lp_lds() {
+    __shared__ __attribute__((aligned(16))) uint16_t buf[2 * BM * LBK];
+    return buf;
+}
+
 // acc = A[row0 .. row0 + BM, 0 .. np) * B[0 .. np, col0 .. col0 + BM): one
 // BM x BM tile (BM = 128: each of the 4 waves 64x64 as 2x2 32x32 MFMA blocks;
 // BM = 64: one 32x32 block per wave), K in slices of 64. A is staged in LDS
@@ -48,7 +56,9 @@ __device__ __forceinline__ int lds_swz(int n, int c) { return n * LBK + ((c ^ ((
 // row wm WT + i 32 + (e / 4) 8 + (l / 32) 4 + e % 4 and column
 // wn WT + j 32 + l % 32 of the tile (w = wave = 2 wm + wn, l = lane,
 // WT = BM / 2). All 256 threads must call it.
-template <typename T, int BM>
+// BSYM: B is symmetric, so B[k][n] = B[n][k] and its tile is loaded by rows
+// exactly like A (no transposition on the way into LDS).
+template <typename T, int BM, bool BSYM = false>
 __device__ __forceinline__ void lp_tile_product(const uint16_t *Ag, const uint16_t *Bg, int ldx, int np, int row0,
                                                 int col0, v16f (&acc)[BM / 64][BM / 64]) {
     typedef typename Lp<T>::vec vec;
@@ -56,12 +66,12 @@ __device__ __forceinline__ void lp_tile_product(const uint16_t *Ag, const uint16
     constexpr int NB = WT / 32;         // 32x32 MFMA blocks per wave dimension
     constexpr int AQ = BM / 32;         // 16-byte A loads per thread
     constexpr int BT = 2 * BM;          // threads that load a 4(k) x 8(n) B block
-    __shared__ __attribute__((aligned(16))) uint16_t sA[1][BM * LBK];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[1][BM * LBK];
+    uint16_t(*sA)[BM * LBK] = (uint16_t(*)[BM * LBK])lp_lds<BM>();
+    uint16_t(*sB)[BM * LBK] = (uint16_t(*)[BM * LBK])(lp_lds<BM>() + BM * LBK);
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int wm = w >> 1, wn = w & 1;
     const int ac = (t & 7) * 8;
-    const bool bload = (BT >= 256) || t < BT;   // BM = 128: every thread
+    const bool bload = BSYM || (BT >= 256) || t < BT;   // BM = 128: every thread
     // B block of thread t: k rows 4 kq .. 4 kq + 3, columns 8 nci .. 8 nci + 7.
     // Each group of 16 lanes covers 8 column blocks and two k quads, so its
     // 8-byte LDS stores land on 16 distinct 8-byte bank slots.
@@ -83,7 +93,8 @@ __device__ __forceinline__ void lp_tile_product(const uint16_t *Ag, const uint16
     const __amdgpu_buffer_rsrc_t rsA = __builtin_amdgcn_make_buffer_rsrc((void *)Ag, (short)0, nrec, 0x00020000);
     const __amdgpu_buffer_rsrc_t rsB = __builtin_amdgcn_make_buffer_rsrc((void *)Bg, (short)0, nrec, 0x00020000);
     const uint32_t va = (uint32_t)(((row0 + (t >> 3)) * ldx + ac) * 2);
-    const uint32_t vb = (uint32_t)((kq * 4 * ldx + col0 + nc) * 2);
+    const uint32_t vb = BSYM ? (uint32_t)(((col0 + (t >> 3)) * ldx + ac) * 2)
+                             : (uint32_t)((kq * 4 * ldx + col0 + nc) * 2);
     const int sa32 = 64 * ldx, srow = 2 * ldx;   // bytes of 32 rows / one row
     const int nk = np / LBK;
     // One LDS buffer and one register set per workgroup (32 KB of LDS and
@@ -97,18 +108,28 @@ __device__ __forceinline__ void lp_tile_product(const uint16_t *Ag, const uint16
     do {                                                                         \
         const bool in_ = (ks) < nk;                                              \
         const uint32_t oa_ = in_ ? va + (uint32_t)((ks) * LBK * 2) : 0x80000000u; \
-        const uint32_t ob_ = (in_ && bload) ? vb + (uint32_t)((ks) * LBK * srow) \
-                                            : 0x80000000u;                       \
+        const uint32_t ob_ = !(in_ && bload) ? 0x80000000u                      \
+                             : BSYM ? vb + (uint32_t)((ks) * LBK * 2)            \
+                                    : vb + (uint32_t)((ks) * LBK * srow);        \
         S##a0 = NS_BUF(rsA, oa_, 0);                                             \
         S##a1 = NS_BUF(rsA, oa_, sa32);                                          \
         if constexpr (AQ > 2) {                                                  \
             S##a2 = NS_BUF(rsA, oa_, 2 * sa32);                                  \
             S##a3 = NS_BUF(rsA, oa_, 3 * sa32);                                  \
         }                                                                        \
-        S##b0 = NS_BUF(rsB, ob_, 0);                                             \
-        S##b1 = NS_BUF(rsB, ob_, srow);                                          \
-        S##b2 = NS_BUF(rsB, ob_, 2 * srow);                                      \
-        S##b3 = NS_BUF(rsB, ob_, 3 * srow);                                      \
+        if constexpr (BSYM) {                                                    \
+            S##b0 = NS_BUF(rsB, ob_, 0);                                         \
+            S##b1 = NS_BUF(rsB, ob_, sa32);                                      \
+            if constexpr (AQ > 2) {                                              \
+                S##b2 = NS_BUF(rsB, ob_, 2 * sa32);                              \
+                S##b3 = NS_BUF(rsB, ob_, 3 * sa32);                              \
+            }                                                                    \
+        } else {                                                                 \
+            S##b0 = NS_BUF(rsB, ob_, 0);                                         \
+            S##b1 = NS_BUF(rsB, ob_, srow);                                      \
+            S##b2 = NS_BUF(rsB, ob_, 2 * srow);                                  \
+            S##b3 = NS_BUF(rsB, ob_, 3 * srow);                                  \
+        }                                                                        \
     } while (0)
 // B is a 4(k) x 8(n) block in S##b0..S##b3 (one k row each); column j of it
 // becomes 4 consecutive k for LDS row n = nc + j
@@ -134,7 +155,14 @@ __device__ __forceinline__ void lp_tile_product(const uint16_t *Ag, const uint16
             *(uint4 *)&sA[buf_][lds_swz((t >> 3) + 64, t & 7)] = S##a2;          \
             *(uint4 *)&sA[buf_][lds_swz((t >> 3) + 96, t & 7)] = S##a3;          \
         }                                                                        \
-        if (bload) {                                                             \
+        if constexpr (BSYM) {                                                    \
+            *(uint4 *)&sB[buf_][lds_swz(t >> 3, t & 7)] = S##b0;                 \
+            *(uint4 *)&sB[buf_][lds_swz((t >> 3) + 32, t & 7)] = S##b1;          \
+            if constexpr (AQ > 2) {                                              \
+                *(uint4 *)&sB[buf_][lds_swz((t >> 3) + 64, t & 7)] = S##b2;      \
+                *(uint4 *)&sB[buf_][lds_swz((t >> 3) + 96, t & 7)] = S##b3;      \
+            }                                                                    \
+        } else if (bload) {                                                      \
             NS_BCOL(S, 0, x); NS_BCOL(S, 1, x); NS_BCOL(S, 2, y);                \
             NS_BCOL(S, 3, y); NS_BCOL(S, 4, z); NS_BCOL(S, 5, z);                \
             NS_BCOL(S, 6, w); NS_BCOL(S, 7, w);                                  \

@@ -33,6 +33,8 @@ struct SubMeta {
     int64_t offX1;    // ldx*ldx elements of the NS precision: X buffer 1
     int64_t offB;     // ldx*ldx elements: R = I - X^2
     int64_t offVec;   // nown * NOLSM_NVEC * np * 6 floats/doubles: finishing vectors
+    int64_t offX0;    // X buffer 0: offL, or its own ldx*ldx buffer on the
+                      // symmetric route (which keeps L until the extraction)
     int64_t offRes;   // max(max_iter, inv_max_iter) * ntile_ns doubles: residual partials
     // coupled Newton-Schulz inverse only (0 otherwise): ldx*ldx elements each
     int64_t offY0, offY1;   // Y_k ping-pong; after convergence S^-1 and K in 16 bits

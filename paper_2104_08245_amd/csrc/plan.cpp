@@ -38,7 +38,7 @@ int nolsm_elem_for(int32_t prec) {
 }
 
 size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_iter, int32_t inverse,
-                        int32_t nown) {
+                        int32_t nown, int32_t sym) {
     const size_t n = (size_t)np;
     const size_t P = n / NOLSM_TILE;
     const size_t nt = (n + ns_tile - 1) / ns_tile;
@@ -54,6 +54,7 @@ size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_i
     b += align256((size_t)NOLSM_NVEC * n * 6 * 8 * nown);  // finishing vectors per owned molecule
     b += align256((size_t)max_iter * nt * nt * 8);  // residual partials
     if (inverse == NOLSM_INV_COUPLED_NS) b += 4 * align256(ldx * ldx * (size_t)elem);  // Y, Z ping-pong
+    if (sym) b += align256(ldx * ldx * (size_t)elem);   // X0 beside L (kept to the end)
     return b;
 }
 
@@ -308,10 +309,10 @@ extern "C" void nolsm_default_opts(nolsm_solve_opts *o, int32_t prec) {
     o->sched = NOLSM_SCHED_GRAPH;
     o->debug_poison_mol = -1;
     o->ns_small_tile_mask = 0x5;   // 64 and 192 rows: 128-row tiles would waste work
-    // 16-bit sign iterations: the FP32 factor's error (kappa(S_J) 2^-24) sits
-    // far below their own floor, and the FP32 matrix cores run 3x faster
-    o->inverse = (prec == NOLSM_FP16 || prec == NOLSM_BF16) ? NOLSM_INV_CHOLESKY_FP32 : NOLSM_INV_CHOLESKY;
+    o->inverse = NOLSM_INV_CHOLESKY;
     o->inv_max_iter = 40;
+    o->sym_sign = 0;
+    o->reserved_ = 0;
 }
 
 extern "C" int nolsm_plan_info(const nolsm_plan *p, nolsm_plan_sizes *o) {
@@ -387,6 +388,11 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
         nolsm_set_last_error("the FP32 Cholesky route serves the FP16/BF16 sign iterations only");
         return NOLSM_E_ARG;
     }
+    if (opts->sym_sign && ((opts->prec != NOLSM_FP16 && opts->prec != NOLSM_BF16) ||
+                           opts->inverse == NOLSM_INV_COUPLED_NS)) {
+        nolsm_set_last_error("the symmetric sign iteration needs FP16/BF16 and a Cholesky route");
+        return NOLSM_E_ARG;
+    }
     if (opts->inverse == NOLSM_INV_COUPLED_NS) {
         if (opts->prec != NOLSM_FP16 && opts->prec != NOLSM_BF16) {
             nolsm_set_last_error("the coupled Newton-Schulz inverse runs in FP16/BF16 only");
@@ -405,6 +411,7 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
         pl->sched = opts->sched;
         pl->max_iter = opts->max_iter;
         pl->inverse = opts->inverse;
+        pl->sym = opts->sym_sign ? 1 : 0;
         pl->inv_max_iter = opts->inverse == NOLSM_INV_COUPLED_NS ? opts->inv_max_iter : 0;
         // residual partial slots serve both iterations, one after the other
         const int32_t res_slots = std::max(pl->max_iter, pl->inv_max_iter);
@@ -435,7 +442,7 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
         pl->ws_full = 0;
         auto slot_bytes = [&](int32_t g) {
             return nolsm_slot_bytes(np_of(g), tile_of(g), pl->elem, res_slots, pl->inverse,
-                                    pl->own_ptr[g + 1] - pl->own_ptr[g]) + ctl_bytes;
+                                    pl->own_ptr[g + 1] - pl->own_ptr[g], pl->sym) + ctl_bytes;
         };
         for (int32_t J = 0; J < ng; ++J) {
             const size_t sb = slot_bytes(J);
@@ -503,6 +510,8 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
                 m.offX1 = (int64_t)off; off += align256(ldx * ldx * pl->elem);
                 m.offB = (int64_t)off; off += align256(ldx * ldx * pl->elem);
                 m.offVec = (int64_t)off; off += align256((size_t)NOLSM_NVEC * n * 6 * 8 * m.nown);
+                m.offX0 = m.offL;
+                if (pl->sym) { m.offX0 = (int64_t)off; off += align256(ldx * ldx * pl->elem); }
                 m.offRes = (int64_t)off; off += align256((size_t)res_slots * m.ntile_ns * 8);
                 if (pl->inverse == NOLSM_INV_COUPLED_NS) {
                     m.offY0 = (int64_t)off; off += align256(ldx * ldx * pl->elem);
@@ -520,8 +529,10 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
                 // FP16/BF16 slots with 64-row tiles get their own list
                 std::vector<uint32_t> &tl =
                     (T == 64 && (pl->prec == NOLSM_FP16 || pl->prec == NOLSM_BF16)) ? ch.t_ns64 : ch.t_ns;
+                // symmetric route: upper tiles only, each mirrors itself
+                const bool sym = pl->sym != 0;
                 for (int32_t a = 0; a < nt; ++a)
-                    for (int32_t b = 0; b < nt; ++b) tl.push_back(NOLSM_TASK(s, a, b));
+                    for (int32_t b = sym ? a : 0; b < nt; ++b) tl.push_back(NOLSM_TASK(s, a, b));
                 // (slot, 256-row block, owned molecule): the molecules of one row
                 // block are adjacent, so they run together on one XCD and share
                 // the streamed rows through its L2

@@ -40,7 +40,7 @@ struct nolsm_plan {
     bool configured = false;
     bool bound = false;
     int32_t prec = -1, sched = -1, max_iter = 0, ns_tile = 0, elem = 0;
-    int32_t inverse = 0, inv_max_iter = 0;
+    int32_t inverse = 0, inv_max_iter = 0, sym = 0;
     size_t ws_bytes = 0, ws_min = 0, ws_full = 0;
     std::vector<HostChunk> chunks;
     std::vector<char> image;              // metadata image uploaded by bind
@@ -60,7 +60,7 @@ struct nolsm_plan {
 
 // Internal helpers implemented in plan.cpp
 size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_iter, int32_t inverse,
-                        int32_t nown);
+                        int32_t nown, int32_t sym);
 int nolsm_ns_tile_for(int32_t prec, int32_t np, uint64_t small_mask);
 int nolsm_elem_for(int32_t prec);
 void nolsm_set_last_error(const std::string &s);

@@ -150,6 +150,8 @@ def test_bad_options_rejected(L, config1):
                dict(inverse=L.INV_COUPLED_NS),                       # FP64: 16-bit route only
                dict(inverse=L.INV_CHOLESKY_FP32),                    # FP64: 16-bit route only
                dict(prec=L.PREC["fp32"], inverse=L.INV_CHOLESKY_FP32),
+               dict(sym_sign=1),                                     # FP64: 16-bit only
+               dict(prec=L.PREC["fp16"], sym_sign=1, inverse=L.INV_COUPLED_NS),
                dict(prec=L.PREC["fp16"], inverse=L.INV_COUPLED_NS, inv_max_iter=1)):
         opts = L.default_opts("fp64")
         for k, v in kw.items():
@@ -194,8 +196,8 @@ def test_combination_equals_oracle(L, config1):
     assert np.array_equal(g[2], np.arange(config1.K.nb + 1)) and np.array_equal(g[3], np.arange(config1.K.nb))
 
 
-def test_default_inverse_route_per_precision(L):
-    # the 16-bit sign iterations default to the FP32 Cholesky route
-    for prec, want in (("fp64", L.INV_CHOLESKY), ("fp32", L.INV_CHOLESKY),
-                       ("fp16", L.INV_CHOLESKY_FP32), ("bf16", L.INV_CHOLESKY_FP32)):
-        assert L.default_opts(prec).inverse == want
+def test_default_route_is_fp64_cholesky_on_a(L):
+    # every precision defaults to the FP64 factor and the sign of A_J itself
+    for prec in ("fp64", "fp32", "fp16", "bf16"):
+        o = L.default_opts(prec)
+        assert o.inverse == L.INV_CHOLESKY and o.sym_sign == 0

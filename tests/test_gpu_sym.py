@@ -1,0 +1,142 @@
+"""The symmetric sign iteration (option sym_sign) vs the CPU oracle, through
+the C ABI.
+
+With S_J = L L^T, A_J - mu I = L^-T (L^-1 K_J L^-T - mu I) L^T, so
+sign(A_J) = L^-T sign(A~) L^T with A~ = L^-1 K_J L^-T - mu I symmetric, and
+the owned columns of D are L^-T (y - sign(A~) y) / 2 with y = L^-1 E_cJ: the
+same D as the oracle's definition (Eq. purification_submatrix). The 16-bit
+iteration on A~ has the same spectrum and the same FP16/BF16 floor as the one
+on A_J, so the mixed bounds of the per-molecule path apply unchanged. Outside
+the spectrum the sign is -I or +I after a few steps and the result is exact to
+the factor's precision, which pins the setup (A~, y) and the final L^-T solve
+tightly.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import nolsm as o
+
+pytestmark = pytest.mark.gpu
+
+MIXED = {"fp16": dict(dcols=5e-3, energy=1e-3), "bf16": dict(dcols=4e-2, energy=1e-2)}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ref1(config1):
+    return o.nolsm(config1)
+
+
+def solve(system, prec, mu=None, **kw):
+    from paper_2104_08245_amd import Solver
+    import torch
+    say(f"[gpu] symmetric solve prec={prec} nmol={system.nmol} mu={mu} {kw}")
+    sv = Solver(system, prec=prec, device="cuda:0", sym_sign=1, **kw)
+    sv.run(mu=mu)
+    torch.cuda.synchronize()
+    return sv
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def check_mixed(sv, ref, nmol, prec, tag):
+    st = sv.host_stats()
+    assert np.all(st["status"] == 0)
+    dc = sv.host_dcols()
+    errs = np.array([rel(dc[J], ref.Dcols[J]) for J in range(nmol)])
+    de = np.abs(st["energy_KD"] - ref.E)
+    say(f"{tag}: Dcols rel-F max {errs.max():.3e} mean {errs.mean():.3e}; |dE_J| max {de.max():.3e}; "
+        f"iters {st['iters'].min()}..{st['iters'].max()}")
+    assert errs.max() <= MIXED[prec]["dcols"]
+    assert de.max() <= MIXED[prec]["energy"]
+    return st
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_symmetric_within_stated_error(torch, config1, ref1, prec):
+    st = check_mixed(solve(config1, prec), ref1, config1.nmol, prec, f"{prec} symmetric")
+    # same spectrum, same scale rule: the iteration counts stay those of A_J
+    assert np.all(np.abs(st["iters"] - ref1.iters) <= 3)
+
+
+def test_symmetric_on_fp32_factor(torch, config1, ref1):
+    from paper_2104_08245_amd import _lib as L
+    check_mixed(solve(config1, "fp16", inverse=L.INV_CHOLESKY_FP32), ref1, config1.nmol, "fp16",
+                "fp16 symmetric, FP32 factor")
+
+
+def test_symmetric_nonzero_mu(torch, config1):
+    ref = o.nolsm(config1, mu=0.25)
+    check_mixed(solve(config1, "fp16", mu=0.25), ref, config1.nmol, "fp16", "fp16 symmetric mu=0.25")
+
+
+def test_symmetric_outside_spectrum_is_exact(torch, config1):
+    # mu above the spectrum: sign = -I and Dcols = S_J^-1 E_cJ; the FP32
+    # finishing leaves ~1e-7, so the setup and the L^-T solve are held to 1e-5
+    Js = list(range(0, config1.nmol, 7))
+    hi = o.nolsm(config1, mu=50.0, molecules=Js)
+    sv = solve(config1, "fp16", mu=50.0)
+    dc = sv.host_dcols()
+    worst = max(rel(dc[J], hi.Dcols[J]) for J in Js)
+    say("symmetric mu=50 worst rel-F", worst)
+    assert worst <= 1e-5
+    sv.run(mu=-50.0)
+    torch.cuda.synchronize()
+    assert np.abs(sv.Dcols.cpu().numpy()).max() <= 1e-5 * max(np.abs(d).max() for d in dc)
+
+
+def test_symmetric_combined(torch, config1):
+    sv = solve(config1, "fp16", combine=True)
+    ref = o.nolsm_groups(config1, sv.plan.groups())
+    check_mixed(sv, ref, config1.nmol, "fp16", "fp16 symmetric combined")
+
+
+@pytest.mark.parametrize("prec", ["fp16"])
+def test_symmetric_schedules_chunks_and_replays_bit_identical(torch, config1, prec):
+    from paper_2104_08245_amd import Solver, _lib as L
+    base = solve(config1, prec, sched=L.SCHED_STREAM)
+    ref = base.Dcols.cpu().numpy()
+    for kw in (dict(sched=L.SCHED_PERSISTENT), dict(sched=L.SCHED_PER_BUCKET),
+               dict(ws_bytes=base.plan.info()["ws_full_bytes"] // 3 + 4096)):
+        other = solve(config1, prec, **kw)
+        assert np.array_equal(other.Dcols.cpu().numpy(), ref), kw
+    sv = Solver(config1, prec=prec, device="cuda:0", sym_sign=1, sched=L.SCHED_GRAPH)
+    s = torch.cuda.Stream()
+    for rep in range(3):
+        say(f"[gpu] symmetric graph replay {rep}")
+        sv.Dcols.zero_()
+        torch.cuda.synchronize()
+        sv.run(stream=s)
+        s.synchronize()
+        assert np.array_equal(sv.Dcols.cpu().numpy(), ref), rep
+
+
+def test_symmetric_not_spd_flagged(torch, config1, ref1):
+    sv = solve(config1, "fp16", debug_poison_mol=5)
+    st = sv.host_stats()
+    assert st["status"][5] != 0
+    assert np.all(np.delete(st["status"], 5) == 0)
+
+
+def test_symmetric_rejects_outputs_defined_on_a(torch, config1):
+    from paper_2104_08245_amd import Solver, NolsmError, _lib as L
+    sv = Solver(config1, prec="fp16", device="cuda:0", sym_sign=1)
+    sv.want_w()
+    with pytest.raises(NolsmError) as e:
+        sv.run()
+    assert e.value.code == L.E_ARG
