@@ -178,7 +178,7 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sched", default="graph", choices=["graph", "stream", "bucket", "persistent"])
+    ap.add_argument("--sched", default="graph", choices=["graph", "stream", "bucket", "persistent", "pipeline"])
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB "
                          "(reference for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -231,7 +231,7 @@ def main():
     from paper_2104_08245_amd import Solver, _lib as L
 
     sched = {"graph": L.SCHED_GRAPH, "stream": L.SCHED_STREAM, "bucket": L.SCHED_PER_BUCKET,
-             "persistent": L.SCHED_PERSISTENT}[args.sched]
+             "persistent": L.SCHED_PERSISTENT, "pipeline": L.SCHED_PIPELINE}[args.sched]
     dev = torch.device("cuda:0")
     if args.inverse == "auto":
         args.inverse = "cholesky"

@@ -90,9 +90,19 @@ typedef enum {
     NOLSM_SCHED_STREAM = 1,        /* same kernels launched directly           */
     NOLSM_SCHED_PER_BUCKET = 2,    /* baseline: one launch per size bucket per
                                       phase (buckets of 64 rows)               */
-    NOLSM_SCHED_PERSISTENT = 3     /* as GRAPH, but each Newton-Schulz launch is a
+    NOLSM_SCHED_PERSISTENT = 3,    /* as GRAPH, but each Newton-Schulz launch is a
                                       fixed grid (2 workgroups per CU) draining
                                       per-XCD device work queues of tiles      */
+    NOLSM_SCHED_PIPELINE = 4       /* as GRAPH, with the workspace split into two
+                                      chunk regions used in turn: the setup of
+                                      chunk c + 1 (gather, factor, substitution,
+                                      bounds) runs on a second stream of the
+                                      library's, beside the sign iteration,
+                                      finishing and extraction of chunk c, with
+                                      events for the order; the stream of the
+                                      call waits for all of it. Needs a stream
+                                      other than the null stream (else runs as
+                                      STREAM).                                 */
 } nolsm_sched;
 
 /* How T_J(S)^-1 is applied when forming A_J = T_J(S)^-1 T_J(K) - mu I and

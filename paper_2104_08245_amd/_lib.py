@@ -14,7 +14,7 @@ MOL_OK, MOL_NOT_SPD, MOL_NOCONV = 0, 1, 2
 FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
 BOUNDS_GERSHGORIN, BOUNDS_LEARNED = 0, 1
-SCHED_GRAPH, SCHED_STREAM, SCHED_PER_BUCKET, SCHED_PERSISTENT = 0, 1, 2, 3
+SCHED_GRAPH, SCHED_STREAM, SCHED_PER_BUCKET, SCHED_PERSISTENT, SCHED_PIPELINE = 0, 1, 2, 3, 4
 INV_CHOLESKY, INV_COUPLED_NS, INV_CHOLESKY_FP32 = 0, 1, 2
 PLAN_COMBINE = 1
 MLP_NFEAT = 12

@@ -107,10 +107,20 @@ struct PhaseEvents {
     }
 };
 
-static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEvents *prof = nullptr) {
+struct LaunchArgs {
+    GatherArgs ga;
+    BoundsArgs ba;
+    NsArgs na;
+    InvArgs ia;
+    FinishArgs fa;
+    ExtractArgs ea;
+};
+
+static LaunchArgs make_args(const nolsm_plan *pl, const BatchArgs &b) {
+    LaunchArgs A;
     const char *base = (const char *)pl->d_meta;
     const nolsm_solve_opts &o = *b.o;
-    GatherArgs ga;
+    GatherArgs &ga = A.ga;
     ga.Krp = (const int32_t *)(base + pl->o_Krp);
     ga.Kci = (const int32_t *)(base + pl->o_Kci);
     ga.Srp = (const int32_t *)(base + pl->o_Srp);
@@ -123,7 +133,7 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
     ga.Sval = b.dS;
     ga.bs = pl->bs;
     ga.poison_J = o.debug_poison_mol;
-    BoundsArgs ba;
+    BoundsArgs &ba = A.ba;
     ba.d_mlp = o.d_mlp;
     ba.d_norm = o.d_mlp_norm;
     ba.d_features = o.d_features;
@@ -131,7 +141,7 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
     ba.safety = o.mlp_safety > 0 ? o.mlp_safety : 1.05f;
     ba.learned = o.bounds == NOLSM_BOUNDS_LEARNED;
     ba.scale_mult = o.debug_scale_mult;
-    NsArgs na;
+    NsArgs &na = A.na;
     na.prec = o.prec;
     na.max_iter = o.max_iter;
     na.fixed_iters = o.fixed_iters;
@@ -143,17 +153,17 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
     na.pgrid = pl->pgrid;
     na.sym = o.sym_sign ? 1 : 0;
     na.pad_ = 0;
-    InvArgs ia;
+    InvArgs &ia = A.ia;
     ia.prec = o.prec;
     ia.max_iter = o.inv_max_iter;
     ia.theta = na.theta;
     ia.rmax = na.rmax;
     ia.own_pos = ga.own_pos;
     ia.bs = pl->bs;
-    FinishArgs fa;
+    FinishArgs &fa = A.fa;
     fa.prec = o.prec;
     fa.nfinal = (o.prec == NOLSM_FP16 || o.prec == NOLSM_BF16) ? o.n_final_fp32 : 0;
-    ExtractArgs ea;
+    ExtractArgs &ea = A.ea;
     ea.Krp = ga.Krp; ea.Kci = ga.Kci; ea.Srp = ga.Srp; ea.Sci = ga.Sci;
     ea.sub_blk = (const int32_t *)(base + pl->o_sub_blk);
     ea.sub_ptr = (const int32_t *)(base + pl->o_sub_ptr);
@@ -173,48 +183,117 @@ static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEven
     ea.nfinal = fa.nfinal;
     ea.sym = o.sym_sign ? 1 : 0;
     ea.L_fp32 = o.inverse == NOLSM_INV_CHOLESKY_FP32;
+    return A;
+}
+
+// gather, factor / inverse, substitution, bounds and X_0 of one chunk
+static int enqueue_setup(const nolsm_plan *pl, const BatchArgs &b, const LaunchArgs &A, const HostChunk &ch,
+                         hipStream_t st, PhaseEvents *prof) {
+    const nolsm_solve_opts &o = *b.o;
+    char *ws = b.ws + ch.base;
+    const ChunkDev cd = chunk_dev(pl, ch, ws);
+    hipError_t e;
+    if (prof) prof->mark(PH_GATHER);
+    if ((e = launch_gather(cd, ws, A.ga, st)) != hipSuccess) return hip_fail(e, "gather launch");
+    const bool fp32 = o.inverse == NOLSM_INV_CHOLESKY_FP32;
+    if (o.inverse == NOLSM_INV_COUPLED_NS) {
+        if (prof) prof->mark(PH_INV);
+        if ((e = launch_inverse(cd, ws, A.ia, st)) != hipSuccess) return hip_fail(e, "inverse launch");
+    } else {
+        if (prof) prof->mark(PH_CHOL);
+        if ((e = launch_chol(cd, ws, fp32, st)) != hipSuccess) return hip_fail(e, "Cholesky launch");
+        if (prof) prof->mark(PH_SUBST);
+        e = o.sym_sign ? launch_subst_sym(cd, ws, fp32, st) : launch_subst(cd, ws, fp32, st);
+        if (e != hipSuccess) return hip_fail(e, "substitution launch");
+    }
+    if (prof) prof->mark(PH_BOUNDS);
+    if ((e = launch_bounds(cd, ws, A.ba, o.prec, st)) != hipSuccess) return hip_fail(e, "bounds launch");
+    return NOLSM_OK;
+}
+
+// sign iteration, finishing, extraction and W of one chunk
+static int enqueue_solve(const nolsm_plan *pl, const BatchArgs &b, const LaunchArgs &A, const HostChunk &ch,
+                         hipStream_t st, PhaseEvents *prof) {
+    const nolsm_solve_opts &o = *b.o;
+    char *ws = b.ws + ch.base;
+    const ChunkDev cd = chunk_dev(pl, ch, ws);
+    hipError_t e;
+    if (prof) prof->mark(PH_NS);
+    for (int it = 0; it < o.max_iter; ++it) {
+        e = launch_ns_iter(cd, ws, A.na, it, st);
+        if (e != hipSuccess) return hip_fail(e, "Newton-Schulz launch");
+    }
+    if (prof) prof->mark(PH_FINISH);
+    if ((e = launch_finish(cd, ws, A.fa, st)) != hipSuccess) return hip_fail(e, "finish launch");
+    if (prof) prof->mark(PH_EXTRACT);
+    if ((e = launch_extract(cd, ws, A.ea, st)) != hipSuccess) return hip_fail(e, "extract launch");
+    if (A.ea.Wcols) {
+        if (prof) prof->mark(PH_WMAT);
+        if ((e = launch_wcols(cd, ws, A.ea, st)) != hipSuccess) return hip_fail(e, "W launch");
+    }
+    if (prof) {
+        prof->n_ns += 2 * o.max_iter;
+        prof->n_fin += A.fa.nfinal == 0 ? 1 : (A.fa.nfinal == 1 ? 3 : 9);
+    }
+    return NOLSM_OK;
+}
+
+// every chunk in turn on one stream
+static int enqueue(nolsm_plan *pl, const BatchArgs &b, hipStream_t st, PhaseEvents *prof = nullptr) {
+    const LaunchArgs A = make_args(pl, b);
     for (const HostChunk &ch : pl->chunks) {
-        const ChunkDev cd = chunk_dev(pl, ch, b.ws);
-        hipError_t e;
-        if (prof) prof->mark(PH_GATHER);
-        if ((e = launch_gather(cd, b.ws, ga, st)) != hipSuccess) return hip_fail(e, "gather launch");
-        if (o.inverse == NOLSM_INV_COUPLED_NS) {
-            if (prof) prof->mark(PH_INV);
-            if ((e = launch_inverse(cd, b.ws, ia, st)) != hipSuccess) return hip_fail(e, "inverse launch");
-        } else if (o.sym_sign) {
-            const bool fp32 = o.inverse == NOLSM_INV_CHOLESKY_FP32;
-            if (prof) prof->mark(PH_CHOL);
-            if ((e = launch_chol(cd, b.ws, fp32, st)) != hipSuccess) return hip_fail(e, "Cholesky launch");
-            if (prof) prof->mark(PH_SUBST);
-            if ((e = launch_subst_sym(cd, b.ws, fp32, st)) != hipSuccess) return hip_fail(e, "substitution launch");
-        } else {
-            if (prof) prof->mark(PH_CHOL);
-            const bool fp32 = o.inverse == NOLSM_INV_CHOLESKY_FP32;
-            if ((e = launch_chol(cd, b.ws, fp32, st)) != hipSuccess) return hip_fail(e, "Cholesky launch");
-            if (prof) prof->mark(PH_SUBST);
-            if ((e = launch_subst(cd, b.ws, fp32, st)) != hipSuccess) return hip_fail(e, "substitution launch");
-        }
-        if (prof) prof->mark(PH_BOUNDS);
-        if ((e = launch_bounds(cd, b.ws, ba, o.prec, st)) != hipSuccess) return hip_fail(e, "bounds launch");
-        if (prof) prof->mark(PH_NS);
-        for (int it = 0; it < o.max_iter; ++it) {
-            e = launch_ns_iter(cd, b.ws, na, it, st);
-            if (e != hipSuccess) return hip_fail(e, "Newton-Schulz launch");
-        }
-        if (prof) prof->mark(PH_FINISH);
-        if ((e = launch_finish(cd, b.ws, fa, st)) != hipSuccess) return hip_fail(e, "finish launch");
-        if (prof) prof->mark(PH_EXTRACT);
-        if ((e = launch_extract(cd, b.ws, ea, st)) != hipSuccess) return hip_fail(e, "extract launch");
-        if (ea.Wcols) {
-            if (prof) prof->mark(PH_WMAT);
-            if ((e = launch_wcols(cd, b.ws, ea, st)) != hipSuccess) return hip_fail(e, "W launch");
-        }
-        if (prof) {
-            prof->n_ns += 2 * o.max_iter;
-            prof->n_fin += fa.nfinal == 0 ? 1 : (fa.nfinal == 1 ? 3 : 9);
-        }
+        int rc = enqueue_setup(pl, b, A, ch, st, prof);
+        if (rc == NOLSM_OK) rc = enqueue_solve(pl, b, A, ch, st, prof);
+        if (rc != NOLSM_OK) return rc;
     }
     if (prof) prof->mark(PH_END);
+    return NOLSM_OK;
+}
+
+// Pipeline schedule: the chunks alternate between two workspace regions.
+// The setups run in order on the library's stream s2 and the solves in
+// order on the call's stream st; solve(c) waits for setup(c), and setup(c)
+// for solve(c - 2), the last user of its region. The two streams fork from
+// and join back into st, so a capture of st holds all of it.
+static int pipe_resources(nolsm_plan *pl) {
+    const size_t need = 2 * pl->chunks.size() + 2;
+    if (!pl->aux_stream) {
+        hipStream_t s2 = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "pipeline stream");
+        pl->aux_stream = s2;
+    }
+    while (pl->events.size() < need) {
+        hipEvent_t ev = nullptr;
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "pipeline event");
+        pl->events.push_back(ev);
+    }
+    return NOLSM_OK;
+}
+
+static int enqueue_pipe(nolsm_plan *pl, const BatchArgs &b, hipStream_t st) {
+    int rc = pipe_resources(pl);
+    if (rc != NOLSM_OK) return rc;
+    const LaunchArgs A = make_args(pl, b);
+    hipStream_t s2 = (hipStream_t)pl->aux_stream;
+    const size_t nc = pl->chunks.size();
+    auto ev = [&](size_t i) { return (hipEvent_t)pl->events[i]; };
+    // events: [0, nc) setup done, [nc, 2 nc) solve done, 2 nc fork, 2 nc + 1 join
+    hipError_t e;
+    if ((e = hipEventRecord(ev(2 * nc), st)) != hipSuccess) return hip_fail(e, "pipeline fork");
+    if ((e = hipStreamWaitEvent(s2, ev(2 * nc), 0)) != hipSuccess) return hip_fail(e, "pipeline fork");
+    for (size_t c = 0; c < nc; ++c) {
+        const HostChunk &ch = pl->chunks[c];
+        if (c >= 2 && (e = hipStreamWaitEvent(s2, ev(nc + c - 2), 0)) != hipSuccess) return hip_fail(e, "pipeline wait");
+        if ((rc = enqueue_setup(pl, b, A, ch, s2, nullptr)) != NOLSM_OK) return rc;
+        if ((e = hipEventRecord(ev(c), s2)) != hipSuccess) return hip_fail(e, "pipeline record");
+        if ((e = hipStreamWaitEvent(st, ev(c), 0)) != hipSuccess) return hip_fail(e, "pipeline wait");
+        if ((rc = enqueue_solve(pl, b, A, ch, st, nullptr)) != NOLSM_OK) return rc;
+        if ((e = hipEventRecord(ev(nc + c), st)) != hipSuccess) return hip_fail(e, "pipeline record");
+    }
+    if ((e = hipEventRecord(ev(2 * nc + 1), s2)) != hipSuccess) return hip_fail(e, "pipeline join");
+    if ((e = hipStreamWaitEvent(st, ev(2 * nc + 1), 0)) != hipSuccess) return hip_fail(e, "pipeline join");
     return NOLSM_OK;
 }
 
@@ -264,6 +343,13 @@ extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const doub
     {
         hipError_t e = launch_set_header((char *)d_ws, mu, st);
         if (e != hipSuccess) return hip_fail(e, "header launch");
+        // the pipeline's second region has a header of its own
+        for (const HostChunk &ch : pl->chunks)
+            if (ch.base) {
+                e = launch_set_header((char *)d_ws + ch.base, mu, st);
+                if (e != hipSuccess) return hip_fail(e, "header launch");
+                break;
+            }
     }
     if (opts->profile) {
         PhaseEvents pe;
@@ -287,7 +373,8 @@ extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const doub
         p.n_ns_launches = pe.n_ns;
         p.n_fin_launches = pe.n_fin;
         pl->prof = p;
-    } else if ((opts->sched == NOLSM_SCHED_GRAPH || opts->sched == NOLSM_SCHED_PERSISTENT) && st != nullptr) {
+    } else if ((opts->sched == NOLSM_SCHED_GRAPH || opts->sched == NOLSM_SCHED_PERSISTENT ||
+                opts->sched == NOLSM_SCHED_PIPELINE) && st != nullptr) {
         const void *key[6] = {dK_val, dS_val, d_ws, dDcols, dD_val, dstats};
         bool hit = pl->graph_exec && pl->g_stream == stream && same_opts(pl->g_opts, *opts);
         for (int i = 0; i < 6 && hit; ++i) hit = pl->g_key[i] == key[i];
@@ -295,7 +382,7 @@ extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const doub
             drop_graph(pl);
             hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e, "graph capture begin");
-            rc = enqueue(pl, b, st);
+            rc = opts->sched == NOLSM_SCHED_PIPELINE ? enqueue_pipe(pl, b, st) : enqueue(pl, b, st);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(st, &g);
             if (rc != NOLSM_OK) {
@@ -407,5 +494,7 @@ extern "C" int nolsm_profile_last(const nolsm_plan *pl, nolsm_profile *out) {
 extern "C" void nolsm_plan_destroy(nolsm_plan *pl) {
     if (!pl) return;
     drop_graph(pl);
+    for (void *ev : pl->events) (void)hipEventDestroy((hipEvent_t)ev);
+    if (pl->aux_stream) (void)hipStreamDestroy((hipStream_t)pl->aux_stream);
     delete pl;
 }

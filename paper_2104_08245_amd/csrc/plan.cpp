@@ -382,7 +382,7 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
     if (!pl || !opts) { nolsm_set_last_error("configure: null argument"); return NOLSM_E_ARG; }
     if (opts->prec < NOLSM_FP64 || opts->prec > NOLSM_BF16) { nolsm_set_last_error("bad precision"); return NOLSM_E_ARG; }
     if (opts->max_iter < 2 || opts->max_iter > NOLSM_MAX_ITER_CAP) { nolsm_set_last_error("max_iter must be 2..128"); return NOLSM_E_ARG; }
-    if (opts->sched < NOLSM_SCHED_GRAPH || opts->sched > NOLSM_SCHED_PERSISTENT) { nolsm_set_last_error("bad schedule"); return NOLSM_E_ARG; }
+    if (opts->sched < NOLSM_SCHED_GRAPH || opts->sched > NOLSM_SCHED_PIPELINE) { nolsm_set_last_error("bad schedule"); return NOLSM_E_ARG; }
     if (opts->inverse < NOLSM_INV_CHOLESKY || opts->inverse > NOLSM_INV_CHOLESKY_FP32) { nolsm_set_last_error("bad inverse"); return NOLSM_E_ARG; }
     if (opts->inverse == NOLSM_INV_CHOLESKY_FP32 && opts->prec != NOLSM_FP16 && opts->prec != NOLSM_BF16) {
         nolsm_set_last_error("the FP32 Cholesky route serves the FP16/BF16 sign iterations only");
@@ -450,7 +450,11 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
             pl->ws_full += sb;
         }
         pl->ws_full += 256 + qbytes;
-        if (ws_bytes < pl->ws_min + 256 + qbytes) {
+        // the pipeline schedule keeps two chunks resident: half the
+        // workspace each
+        const bool pipe = pl->sched == NOLSM_SCHED_PIPELINE;
+        const size_t region = pipe ? (ws_bytes / 2) & ~(size_t)255 : ws_bytes;
+        if (region < pl->ws_min + 256 + qbytes) {
             nolsm_set_last_error("workspace smaller than the largest submatrix needs");
             return NOLSM_E_WORKSPACE;
         }
@@ -467,7 +471,7 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
                 const int32_t J = order[i];
                 if (pl->sched == NOLSM_SCHED_PER_BUCKET && np_of(J) != bucket) break;
                 const size_t sb = slot_bytes(J);
-                if (used + sb + 256 + qbytes > ws_bytes) break;
+                if (used + sb + 256 + qbytes > region) break;
                 used += sb;
                 js.push_back(J);
                 ++i;
@@ -547,6 +551,7 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
             pad8(ch.t_ns);
             pad8(ch.t_ns64);
             pad8(ch.t_rows);
+            ch.base = (pipe && (pl->chunks.size() & 1)) ? region : 0;
             pl->chunks.push_back(std::move(ch));
         }
         // metadata image

@@ -18,6 +18,8 @@ struct HostChunk {
     size_t off_ctl = 0;       // workspace offset of the SubCtl array
     size_t off_ictl = 0;      // workspace offset of the InvCtl array (0: none)
     size_t off_q = 0;         // workspace offset of the queue counters
+    size_t base = 0;          // offset of the chunk's region in the workspace
+                              // (pipeline schedule: two regions in turn)
     // metadata image offsets (bytes from d_meta)
     size_t o_meta = 0, o_subst = 0, o_conv = 0, o_ns = 0, o_ns64 = 0, o_rows = 0;
 };
@@ -55,6 +57,9 @@ struct nolsm_plan {
     double g_mu = 0.0;
     nolsm_solve_opts g_opts;
     void *g_stream = nullptr;
+    // pipeline schedule: the library's second stream and its order events
+    void *aux_stream = nullptr;
+    std::vector<void *> events;
     nolsm_profile prof = {};
 };
 

@@ -347,3 +347,27 @@ def test_fp16_on_fp64_cholesky_route_within_stated_error(torch, config1, ref1):
     errs = np.array([rel(dc[J], ref1.Dcols[J]) for J in range(config1.nmol)])
     assert errs.max() <= MIXED["fp16"]["dcols"]
     assert np.abs(st["energy_KD"] - ref1.E).max() <= MIXED["fp16"]["energy"]
+
+
+@pytest.mark.parametrize("prec,sym", [("fp64", 0), ("fp16", 1)])
+def test_pipeline_schedule_bit_identical(torch, config1, prec, sym):
+    # two workspace regions, setups on the library's second stream: every
+    # chunk computes exactly what the one-stream schedule computes
+    from paper_2104_08245_amd import Solver, _lib as L
+    kw = dict(sym_sign=1) if sym else {}
+    base = solve(config1, prec, sched=L.SCHED_STREAM, **kw)
+    ref = base.Dcols.cpu().numpy()
+    full = base.plan.info()["ws_full_bytes"]
+    for ws in (None, 2 * (full // 5) + 8192):
+        sv = Solver(config1, prec=prec, device="cuda:0", sched=L.SCHED_PIPELINE, ws_bytes=ws, **kw)
+        nch = sv.plan.info()["nchunks"]
+        assert nch >= 2
+        s = torch.cuda.Stream()
+        for rep in range(3):
+            say(f"[gpu] pipeline replay {rep} prec={prec} sym={sym} chunks={nch}")
+            sv.Dcols.zero_()
+            torch.cuda.synchronize()
+            sv.run(stream=s)
+            s.synchronize()
+            assert np.array_equal(sv.Dcols.cpu().numpy(), ref), (ws, rep)
+        assert np.all(sv.host_stats()["status"] == 0)
