@@ -106,9 +106,11 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky S_J = L L^T, left-looking by 64-column panels, one workgroup per
-// submatrix. Also stores the inverses of the diagonal tiles (used as GEMMs
-// by the substitution). A non-positive pivot marks the molecule NOT_SPD.
+// Cholesky S_J = L L^T, left-looking by 64-column panels: per panel, one
+// launch factors and inverts the diagonal tiles (one workgroup per
+// submatrix) and one launch forms the tiles below them in parallel. The
+// inverses of the diagonal tiles are kept (the substitution applies them as
+// GEMMs). A non-positive pivot marks the molecule NOT_SPD.
 // ---------------------------------------------------------------------------
 // Cholesky of the 64x64 diagonal tile in LDS (lower part read), right-looking
 // by columns with the entries in registers: thread t holds column q = t % 64,
@@ -194,8 +196,11 @@ template <typename T> __device__ void trinv64_reg(const T (*Lt)[LDP], T (*Di)[LD
     __syncthreads();
 }
 
+// Panel j, diagonal tile: L_jj L_jj^T = S_jj - sum_{k<j} L_jk L_jk^T, and
+// its inverse. One workgroup per submatrix with P > j. A non-positive pivot
+// marks the submatrix NOT_SPD; its later launches then skip it.
 template <typename T>
-__global__ __launch_bounds__(256, 2) void k_chol(ChunkDev cd, char *ws) {
+__global__ __launch_bounds__(256, 2) void k_chol_diag(ChunkDev cd, char *ws, int j) {
     // two tiles (66.6 KB in FP64) plus small buffers: two workgroups fit one CU
     __shared__ T sA[64][LDP];
     __shared__ T sB[64][LDP];
@@ -205,56 +210,82 @@ __global__ __launch_bounds__(256, 2) void k_chol(ChunkDev cd, char *ws) {
     const int s = blockIdx.x;
     if (s >= cd.nsub) return;
     const SubMeta M = cd.meta[s];
+    SubCtl *ctl = cd.ctl + s;
+    if (j >= M.P || ctl->status != NOLSM_MOL_OK) return;
     T *L = (T *)(ws + M.offL);         // S, factored in place (FP32 route: FP32)
     T *Dinv = (T *)(ws + M.offDinv);
     const int64_t ld = M.np;
-    const int P = M.P;
+    auto Lt = [&](int r, int c) { return L + (int64_t)(r * 64) * ld + c * 64; };
     if (threadIdx.x == 0) fail = 0;
+    AccT<T> acc;
+    g2acc(acc, Lt(j, j), ld);
+    for (int k = 0; k < j; ++k) {
+        g2s_tile(sA, Lt(j, k), ld);
+        __syncthreads();
+        mma64<false, true>(acc, sA, sA, -1.0);
+        __syncthreads();
+    }
+    acc2s(sA, acc);
     __syncthreads();
-    for (int j = 0; j < P; ++j) {
-        for (int i = j; i < P; ++i) {
-            AccT<T> acc;
-            g2s_tile(sA, L + (int64_t)(i * 64) * ld + j * 64, ld);
-            __syncthreads();
-            s2acc(acc, sA);
-            __syncthreads();
-            for (int k = 0; k < j; ++k) {
-                g2s_tile(sA, L + (int64_t)(i * 64) * ld + k * 64, ld);
-                g2s_tile(sB, L + (int64_t)(j * 64) * ld + k * 64, ld);
+    potrf64_reg(sA, cb, &fail);
+    if (fail) {
+        if (threadIdx.x == 0) { ctl->status = NOLSM_MOL_NOT_SPD; ctl->done = 1; }
+        return;
+    }
+    trinv64_reg(sA, sB, rd, cb);
+    s2g_tile(Lt(j, j), ld, sA);
+    s2g_tile(Dinv + (int64_t)j * 4096, 64, sB);
+}
+
+// Panel j below the diagonal: L_ij = (S_ij - sum_{k<j} L_ik L_jk^T) L_jj^-T
+// for CHOL_PR row tiles i per workgroup, which share each L_jk load; the
+// row tiles of a panel run in parallel. Grid: (submatrix, block of rows).
+#define CHOL_PR 4
+template <typename T, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_chol_panel(ChunkDev cd, char *ws, int j) {
+    __shared__ T sA[64][LDP];
+    __shared__ T sB[64][LDP];
+    const int s = blockIdx.x;
+    if (s >= cd.nsub) return;
+    const SubMeta M = cd.meta[s];
+    const int P = M.P, i0 = j + 1 + (int)blockIdx.y * CHOL_PR;
+    if (i0 >= P || cd.ctl[s].status != NOLSM_MOL_OK) return;
+    T *L = (T *)(ws + M.offL);
+    const T *Dinv = (const T *)(ws + M.offDinv);
+    const int64_t ld = M.np;
+    auto Lt = [&](int r, int c) { return L + (int64_t)(r * 64) * ld + c * 64; };
+    const int nr = min(CHOL_PR, P - i0);
+    AccT<T> acc[CHOL_PR];
+#pragma unroll
+    for (int r = 0; r < CHOL_PR; ++r)
+        if (r < nr) g2acc(acc[r], Lt(i0 + r, j), ld);
+    for (int k = 0; k < j; ++k) {
+        g2s_tile(sB, Lt(j, k), ld);
+#pragma unroll
+        for (int r = 0; r < CHOL_PR; ++r) {
+            if (r < nr) {
+                g2s_tile(sA, Lt(i0 + r, k), ld);
                 __syncthreads();
-                mma64<false, true>(acc, sA, sB, -1.0);
-                __syncthreads();
-            }
-            if (i == j) {
-                acc2s(sA, acc);
-                __syncthreads();
-                potrf64_reg(sA, cb, &fail);
-                if (fail) break;
-                trinv64_reg(sA, sB, rd, cb);
-                s2g_tile(L + (int64_t)(j * 64) * ld + j * 64, ld, sA);
-                s2g_tile(Dinv + (int64_t)j * 4096, 64, sB);
-                __syncthreads();
-            } else {
-                // L_ij = acc * L_jj^-T, with L_jj^-1 read back from the
-                // workspace (written by this workgroup above)
-                acc2s(sA, acc);
-                g2s_tile(sB, Dinv + (int64_t)j * 4096, 64);
-                __syncthreads();
-                AccT<T> o;
-                acc_zero(o);
-                mma64<false, true>(o, sA, sB);
-                __syncthreads();
-                acc2s(sB, o);
-                __syncthreads();
-                s2g_tile(L + (int64_t)(i * 64) * ld + j * 64, ld, sB);
+                mma64<false, true>(acc[r], sA, sB, -1.0);
                 __syncthreads();
             }
         }
-        if (fail) break;
     }
-    if (threadIdx.x == 0) {
-        SubCtl *c = cd.ctl + s;
-        if (fail) { c->status = NOLSM_MOL_NOT_SPD; c->done = 1; }
+    g2s_tile(sB, Dinv + (int64_t)j * 4096, 64);
+#pragma unroll
+    for (int r = 0; r < CHOL_PR; ++r) {
+        if (r < nr) {
+            acc2s(sA, acc[r]);
+            __syncthreads();
+            AccT<T> o;
+            acc_zero(o);
+            mma64<false, true>(o, sA, sB);   // acc L_jj^-T
+            __syncthreads();
+            acc2s(sA, o);
+            __syncthreads();
+            s2g_tile(Lt(i0 + r, j), ld, sA);
+            __syncthreads();
+        }
     }
 }
 
@@ -743,10 +774,22 @@ hipError_t launch_gather(const ChunkDev &cd, char *ws, const GatherArgs &ga, hip
     hipLaunchKernelGGL(k_gather, dim3(cd.max_m, cd.nsub), dim3(256), lds, st, cd, ws, ga);
     return hipGetLastError();
 }
+// Cholesky of every submatrix of the chunk, left-looking by 64-column panels:
+// per panel a diagonal launch and a launch of the tiles below it.
 hipError_t launch_chol(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st) {
-    if (fp32) hipLaunchKernelGGL(k_chol<float>, dim3(cd.nsub), dim3(256), 0, st, cd, ws);
-    else hipLaunchKernelGGL(k_chol<double>, dim3(cd.nsub), dim3(256), 0, st, cd, ws);
-    return hipGetLastError();
+    const int pmax = cd.max_np / 64;
+    for (int j = 0; j < pmax; ++j) {
+        if (fp32) hipLaunchKernelGGL(k_chol_diag<float>, dim3(cd.nsub), dim3(256), 0, st, cd, ws, j);
+        else hipLaunchKernelGGL(k_chol_diag<double>, dim3(cd.nsub), dim3(256), 0, st, cd, ws, j);
+        LAUNCH_CHECK();
+        const int rows = pmax - 1 - j;
+        if (rows <= 0) continue;
+        const dim3 grid(cd.nsub, (rows + CHOL_PR - 1) / CHOL_PR);
+        if (fp32) hipLaunchKernelGGL((k_chol_panel<float, 3>), grid, dim3(256), 0, st, cd, ws, j);
+        else hipLaunchKernelGGL((k_chol_panel<double, 2>), grid, dim3(256), 0, st, cd, ws, j);
+        LAUNCH_CHECK();
+    }
+    return hipSuccess;
 }
 hipError_t launch_subst_sym(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st) {
     if (fp32) {
