@@ -201,3 +201,27 @@ def test_default_route_is_fp64_cholesky_on_a(L):
     for prec in ("fp64", "fp32", "fp16", "bf16"):
         o = L.default_opts(prec)
         assert o.inverse == L.INV_CHOLESKY and o.sym_sign == 0
+
+
+def test_pipeline_schedule_splits_the_workspace(L, config1):
+    # two resident chunks: each gets half of the workspace
+    from paper_2104_08245_amd import Plan, NolsmError
+    s = config1
+    p = Plan(s.K.nb, s.K.bs, s.K.row_ptr, s.K.col_idx)
+    g = L.default_opts("fp16")
+    p.configure(g, 1 << 40)
+    full = p.info()["ws_full_bytes"]
+    for ws in (full, full // 2, full // 4):
+        g = L.default_opts("fp16")
+        p.configure(g, ws)
+        n_graph = p.info()["nchunks"]
+        o = L.default_opts("fp16", sched=L.SCHED_PIPELINE)
+        p.configure(o, ws)
+        assert p.info()["nchunks"] >= max(2, n_graph)
+    # a workspace that holds the largest submatrix once, but not in each half,
+    # serves the one-region schedules and is refused by the pipeline
+    small = p.info()["ws_min_bytes"] + (1 << 20)
+    p.configure(L.default_opts("fp16"), small)
+    with pytest.raises(NolsmError) as e:
+        p.configure(L.default_opts("fp16", sched=L.SCHED_PIPELINE), small)
+    assert e.value.code == L.E_WORKSPACE
