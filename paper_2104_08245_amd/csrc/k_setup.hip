@@ -120,7 +120,8 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
 // has passed the barrier that follows its last read. The factor L (zeros
 // above the diagonal) is written back to D. A non-positive pivot sets *fail.
 template <typename T> __device__ void potrf64_reg(T (*D)[LDP], T (*cb)[64], int *fail) {
-    const int t = threadIdx.x, q = t & 63, w = t >> 6;
+    // w in a scalar register: the row tests below are branches, not masks
+    const int t = threadIdx.x, q = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
     T v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = D[w + 4 * i][q];
@@ -138,10 +139,11 @@ template <typename T> __device__ void potrf64_reg(T (*D)[LDP], T (*cb)[64], int 
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int r = w + 4 * i;
+            if (r < c) continue;   // finished rows; r is uniform in a wave: no divergence
             const T lr = col[r] * rp;
             if (q == c) {
                 if (r > c) v[i] = lr;
-                else if (r == c) v[i] = piv;
+                else v[i] = piv;
             } else if (q > c && r >= q) {
                 v[i] -= lr * lq;
             }
@@ -166,7 +168,7 @@ template <typename T> __device__ void potrf64_reg(T (*D)[LDP], T (*cb)[64], int 
 // it, then every row r > q takes off L[r][q] times it. Entries above the
 // diagonal stay exact zeros. rd: 64 values of LDS, xb: 2 x 64.
 template <typename T> __device__ void trinv64_reg(const T (*Lt)[LDP], T (*Di)[LDP], T *rd, T (*xb)[64]) {
-    const int t = threadIdx.x, c = t & 63, w = t >> 6;
+    const int t = threadIdx.x, c = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
     if (t < 64) rd[t] = (T)1 / Lt[t][t];
     T b[16];
 #pragma unroll
@@ -187,7 +189,7 @@ template <typename T> __device__ void trinv64_reg(const T (*Lt)[LDP], T (*Di)[LD
         const T xq = xb[q & 1][c];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const int r = w + 4 * i;
+            const int r = w + 4 * i;   // uniform in a wave: rows above q are skipped without divergence
             if (r > q) b[i] -= Lt[r][q] * xq;
         }
     }
