@@ -137,6 +137,37 @@ template <typename T, typename G> __device__ __forceinline__ void s2g_tile(G *g,
         }
     }
 }
+// The same 64x64 tile copy split in two halves, so that the global loads of
+// the next tile can be in flight while the current one is multiplied from
+// LDS: g2r_tile issues the loads into registers (same thread mapping as
+// g2s_tile), r2s_tile writes them to LDS.
+template <typename G> struct RegTile { G v[16]; };
+template <typename G> __device__ __forceinline__ void g2r_tile(RegTile<G> &x, const G *g, int64_t ld) {
+    const int t = threadIdx.x;
+    const int c4 = (t & 15) * 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = i * 16 + (t >> 4);
+        if constexpr (sizeof(G) == 8) {
+            const double2 *p = (const double2 *)(g + (int64_t)r * ld + c4);
+            const double2 a = p[0], b = p[1];
+            x.v[4 * i] = a.x; x.v[4 * i + 1] = a.y; x.v[4 * i + 2] = b.x; x.v[4 * i + 3] = b.y;
+        } else {
+            const float4 a = *(const float4 *)(g + (int64_t)r * ld + c4);
+            x.v[4 * i] = a.x; x.v[4 * i + 1] = a.y; x.v[4 * i + 2] = a.z; x.v[4 * i + 3] = a.w;
+        }
+    }
+}
+template <typename T, typename G> __device__ __forceinline__ void r2s_tile(T (*s)[LDP], const RegTile<G> &x) {
+    const int t = threadIdx.x;
+    const int c4 = (t & 15) * 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = i * 16 + (t >> 4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[r][c4 + q] = (T)x.v[4 * i + q];
+    }
+}
 template <typename T> __device__ __forceinline__ void acc2s(T (*s)[LDP], const AccT<T> &a) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)

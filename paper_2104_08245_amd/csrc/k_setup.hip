@@ -336,21 +336,35 @@ __global__ __launch_bounds__(256, OCC) void k_subst(ChunkDev cd, char *ws) {
 #pragma unroll
             for (int c = 0; c < SC; ++c)
                 if (r < nr && c < nc) g2acc(acc[r][c], Bt(c, i0 + r), ldk);
-        for (int k = 0; k < i0; ++k) {
+        // the updates from the finished rows k < i0, one (k, r) step at a
+        // time: the tiles of the next step are loaded into registers while
+        // this step multiplies from LDS
+        if (i0 > 0) {
+            RegTile<T> pl;
+            g2r_tile(pl, Lt(i0, 0), ldl);
+            r2s_tile(sA, pl);
+            for (int k = 0; k < i0; ++k) {
 #pragma unroll
-            for (int c = 0; c < SC; ++c)
-                if (c < nc) g2s_tile(sB[c], Bt(c, k), ldk);
+                for (int c = 0; c < SC; ++c)
+                    if (c < nc) g2s_tile(sB[c], Bt(c, k), ldk);
+                __syncthreads();
 #pragma unroll
-            for (int r = 0; r < SR; ++r) {
-                if (r < nr) {
-                    g2s_tile(sA, Lt(i0 + r, k), ldl);
-                    __syncthreads();
+                for (int r = 0; r < SR; ++r) {
+                    if (r < nr) {
+                        const bool last_r = (r + 1 == nr);
+                        const int kn = last_r ? k + 1 : k, rn = last_r ? 0 : r + 1;
+                        const bool more = kn < i0;
+                        if (more) g2r_tile(pl, Lt(i0 + rn, kn), ldl);
 #pragma unroll
-                    for (int c = 0; c < SC; ++c)
-                        if (c < nc) mma64<false, false>(acc[r][c], sA, sB[c], -1.0);
-                    __syncthreads();
+                        for (int c = 0; c < SC; ++c)
+                            if (c < nc) mma64<false, false>(acc[r][c], sA, sB[c], -1.0);
+                        __syncthreads();
+                        if (more) r2s_tile(sA, pl);
+                        if (!last_r) __syncthreads();
+                    }
                 }
             }
+            __syncthreads();
         }
         // the diagonal block of the pass, in order
 #pragma unroll
@@ -548,17 +562,31 @@ __global__ __launch_bounds__(256, OCC) void k_rsolve(ChunkDev cd, char *ws) {
 #pragma unroll
         for (int r = 0; r < RR; ++r)
             if (r < nr) g2acc(acc[r], Xt(j0 + r), ldk);
-        for (int k = 0; k < j0; ++k) {
-            g2s_tile(sX, Xt(k), ldk);
+        // - X_ik L_jk^T for the finished tiles k < j0, one (k, r) step at a
+        // time: the tiles of the next step are loaded into registers while
+        // this step multiplies from LDS
+        if (j0 > 0) {
+            RegTile<T> pl;
+            g2r_tile(pl, Lt(j0, 0), ldl);
+            r2s_tile(sL, pl);
+            for (int k = 0; k < j0; ++k) {
+                g2s_tile(sX, Xt(k), ldk);
+                __syncthreads();
 #pragma unroll
-            for (int r = 0; r < RR; ++r) {
-                if (r < nr) {
-                    g2s_tile(sL, Lt(j0 + r, k), ldl);
-                    __syncthreads();
-                    mma64<false, true>(acc[r], sX, sL, -1.0);   // - X_ik L_jk^T
-                    __syncthreads();
+                for (int r = 0; r < RR; ++r) {
+                    if (r < nr) {
+                        const bool last_r = (r + 1 == nr);
+                        const int kn = last_r ? k + 1 : k, rn = last_r ? 0 : r + 1;
+                        const bool more = kn < j0;
+                        if (more) g2r_tile(pl, Lt(j0 + rn, kn), ldl);
+                        mma64<false, true>(acc[r], sX, sL, -1.0);
+                        __syncthreads();
+                        if (more) r2s_tile(sL, pl);
+                        if (!last_r) __syncthreads();
+                    }
                 }
             }
+            __syncthreads();
         }
 #pragma unroll
         for (int r = 0; r < RR; ++r) {
