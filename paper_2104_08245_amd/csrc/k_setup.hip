@@ -166,8 +166,10 @@ template <typename T> __device__ void potrf64_reg(T (*D)[LDP], T (*cb)[64], int 
 // holds column c = t % 64, rows r = w + 4i of the right-hand side B; at step q
 // the owners of row q scale it by 1/L[q][q] (final row q of Di) and publish
 // it, then every row r > q takes off L[r][q] times it. Entries above the
-// diagonal stay exact zeros. rd: 64 values of LDS, xb: 2 x 64.
-template <typename T> __device__ void trinv64_reg(const T (*Lt)[LDP], T (*Di)[LDP], T *rd, T (*xb)[64]) {
+// diagonal stay exact zeros. The result goes straight from registers to the
+// global 64x64 row-major Dg (row r of a wave's lanes is 512 contiguous
+// bytes). rd: 64 values of LDS, xb: 2 x 64.
+template <typename T> __device__ void trinv64_reg(const T (*Lt)[LDP], T *Dg, T *rd, T (*xb)[64]) {
     const int t = threadIdx.x, c = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
     if (t < 64) rd[t] = (T)1 / Lt[t][t];
     T b[16];
@@ -194,18 +196,17 @@ template <typename T> __device__ void trinv64_reg(const T (*Lt)[LDP], T (*Di)[LD
         }
     }
 #pragma unroll
-    for (int i = 0; i < 16; ++i) Di[w + 4 * i][c] = b[i];
-    __syncthreads();
+    for (int i = 0; i < 16; ++i) Dg[(w + 4 * i) * 64 + c] = b[i];
 }
 
 // Panel j, diagonal tile: L_jj L_jj^T = S_jj - sum_{k<j} L_jk L_jk^T, and
 // its inverse. One workgroup per submatrix with P > j. A non-positive pivot
 // marks the submatrix NOT_SPD; its later launches then skip it.
 template <typename T>
-__global__ __launch_bounds__(256, 2) void k_chol_diag(ChunkDev cd, char *ws, int j) {
-    // two tiles (66.6 KB in FP64) plus small buffers: two workgroups fit one CU
+__global__ __launch_bounds__(256, 3) void k_chol_diag(ChunkDev cd, char *ws, int j) {
+    // one tile (33 KB in FP64) plus small buffers: three workgroups share a
+    // CU, so that the 64-step column chains of one hide those of another
     __shared__ T sA[64][LDP];
-    __shared__ T sB[64][LDP];
     __shared__ T cb[2][64];
     __shared__ T rd[64];
     __shared__ int fail;
@@ -234,9 +235,8 @@ __global__ __launch_bounds__(256, 2) void k_chol_diag(ChunkDev cd, char *ws, int
         if (threadIdx.x == 0) { ctl->status = NOLSM_MOL_NOT_SPD; ctl->done = 1; }
         return;
     }
-    trinv64_reg(sA, sB, rd, cb);
+    trinv64_reg(sA, Dinv + (int64_t)j * 4096, rd, cb);
     s2g_tile(Lt(j, j), ld, sA);
-    s2g_tile(Dinv + (int64_t)j * 4096, 64, sB);
 }
 
 // Panel j below the diagonal: L_ij = (S_ij - sum_{k<j} L_ik L_jk^T) L_jj^-T
