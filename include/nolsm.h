@@ -135,8 +135,12 @@ typedef struct {
     int32_t prec;            /* nolsm_prec                                       */
     int32_t n_final_fp32;    /* FP16/BF16: FP32 finishing iterations, 0..2
                                 (default 2), applied column-restricted to Y_J   */
-    double tol;              /* FP64/FP32: stop at ||X^2 - I||_F < tol
-                                (defaults 1e-10 / 1e-5)                          */
+    double tol;              /* stop at ||X^2 - I||_F < tol (defaults FP64
+                                1e-10, FP32 1e-5). FP16/BF16: the hand-over to
+                                the FP32 finishing iterations; the default -1
+                                derives it from the format and n_final_fp32
+                                (FP16 0.104, BF16 0.174 with two finishing
+                                iterations), 0 leaves only the stagnation test */
     int32_t max_iter;        /* iteration slots per solve (default 60)           */
     int32_t fixed_iters;     /* > 0: exactly this many low-precision updates, no
                                 residual test (the paper's fixed step count)    */

@@ -146,7 +146,7 @@ static LaunchArgs make_args(const nolsm_plan *pl, const BatchArgs &b) {
     na.max_iter = o.max_iter;
     na.fixed_iters = o.fixed_iters;
     na.allow_restart = 1;
-    na.tol = o.tol;
+    na.tol = nolsm_switch_tol(o.prec, o.n_final_fp32, o.tol);
     na.theta = o.switch_theta > 0 ? o.switch_theta : 0.7;
     na.rmax = o.switch_rmax > 0 ? o.switch_rmax : 0.5;
     na.persistent = o.sched == NOLSM_SCHED_PERSISTENT;

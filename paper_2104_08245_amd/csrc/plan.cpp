@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <queue>
 #include <iterator>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -35,6 +36,25 @@ int nolsm_elem_for(int32_t prec) {
         case NOLSM_FP32: return 4;
         default: return 2;
     }
+}
+
+// Residual below which the 16-bit sign iteration hands over to the FP32
+// finishing iterations (a tol < 0 asks for it; tol >= 0 is used as given).
+// One Newton-Schulz step maps e = 1 - x^2 of every eigenvalue x to
+// 3/4 e^2 + 1/4 e^3, and ||X^2 - I||_F bounds every |e|, so f FP32 steps
+// from a residual r leave at most 3/4 r^2 (f = 1) or 27/64 r^4 (f = 2).
+// The switch point puts that below a tenth of the unit roundoff u of the
+// 16-bit format (2^-11 FP16, 2^-8 BF16), under the rounding the 16-bit
+// iterate itself carries: FP16 0.104, BF16 0.174 with f = 2. Without
+// finishing steps only the stagnation test stops the iteration.
+double nolsm_switch_tol(int32_t prec, int32_t n_final_fp32, double tol) {
+    if (tol >= 0.0) return tol;
+    if (prec == NOLSM_FP64) return 1e-10;
+    if (prec == NOLSM_FP32) return 1e-5;
+    const double u = (prec == NOLSM_FP16) ? std::ldexp(1.0, -11) : std::ldexp(1.0, -8);
+    if (n_final_fp32 >= 2) return std::pow(u / 10.0 * 64.0 / 27.0, 0.25);
+    if (n_final_fp32 == 1) return std::sqrt(u / 10.0 * 4.0 / 3.0);
+    return 0.0;
 }
 
 size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_iter, int32_t inverse,
@@ -299,7 +319,9 @@ extern "C" void nolsm_default_opts(nolsm_solve_opts *o, int32_t prec) {
     std::memset(o, 0, sizeof(*o));
     o->prec = prec;
     o->n_final_fp32 = (prec == NOLSM_FP16 || prec == NOLSM_BF16) ? 2 : 0;
-    o->tol = (prec == NOLSM_FP64) ? 1e-10 : (prec == NOLSM_FP32 ? 1e-5 : 0.0);
+    // FP16/BF16: negative = the switch point derived from the precision and
+    // the finishing iterations at configure time (nolsm_switch_tol)
+    o->tol = (prec == NOLSM_FP64) ? 1e-10 : (prec == NOLSM_FP32 ? 1e-5 : -1.0);
     o->max_iter = (prec == NOLSM_FP64) ? 48 : 40;
     o->fixed_iters = 0;
     o->switch_theta = 0.7;

@@ -94,6 +94,32 @@ def test_mixed_within_stated_error_config1(torch, config1, ref1, prec):
     assert np.all(st["iters_fp32"] == 2)
 
 
+# hand-over to the FP32 finishing: two exact Newton-Schulz steps take a
+# residual r to at most 27/64 r^4, which the default switch point keeps under
+# a tenth of the 16-bit unit roundoff
+SWITCH = {"fp16": (2.0 ** -11 / 10 * 64 / 27) ** 0.25, "bf16": (2.0 ** -8 / 10 * 64 / 27) ** 0.25}
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_switch_point_saves_iterations_not_accuracy(torch, config1, ref1, prec):
+    stag = solve(config1, prec, tol=0.0)          # stagnation test only
+    sv = solve(config1, prec)                     # default switch point
+    a, b = stag.host_stats(), sv.host_stats()
+    assert np.all(a["status"] == 0) and np.all(b["status"] == 0)
+    # every submatrix hands over below the switch point or at stagnation,
+    # never later than the stagnation-only run
+    assert np.all(b["iters"] <= a["iters"])
+    assert np.all((b["resid"] < SWITCH[prec]) | (b["iters"] == a["iters"]))
+    de_a = np.abs(a["energy_KD"] - ref1.E)
+    de_b = np.abs(b["energy_KD"] - ref1.E)
+    say(f"{prec}: iterations {a['iters'].mean():.2f} -> {b['iters'].mean():.2f}; "
+        f"|dE_J| max {de_a.max():.3e} -> {de_b.max():.3e}")
+    assert de_b.max() <= MIXED[prec]["energy"]
+    # what the finishing leaves of the earlier hand-over is far below the
+    # 16-bit rounding that dominates both runs
+    assert de_b.max() <= 1.25 * de_a.max()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp16"])
 def test_schedules_and_replays_bit_identical(torch, config1, prec):
     from paper_2104_08245_amd import _lib as L

@@ -69,9 +69,15 @@ def check_mixed(sv, ref, nmol, prec, tag):
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_symmetric_within_stated_error(torch, config1, ref1, prec):
+    from paper_2104_08245_amd import Solver
     st = check_mixed(solve(config1, prec), ref1, config1.nmol, prec, f"{prec} symmetric")
-    # same spectrum, same scale rule: the iteration counts stay those of A_J
-    assert np.all(np.abs(st["iters"] - ref1.iters) <= 3)
+    # same spectrum, same scale rule, same stopping rule: the iteration
+    # counts stay those of the iteration on A_J, up to where each run's
+    # 16-bit rounding lets the residual cross the switch point (BF16: within 2)
+    on_a = Solver(config1, prec=prec, device="cuda:0")
+    on_a.run()
+    torch.cuda.synchronize()
+    assert np.all(np.abs(st["iters"] - on_a.host_stats()["iters"]) <= 2)
 
 
 def test_symmetric_on_fp32_factor(torch, config1, ref1):
