@@ -44,15 +44,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ns_lp_fp16_cube32768_traffic.md
 NS_SOURCE = os.path.join(ROOT, "paper_2104_08245_amd", "csrc", "k_ns.hip")
 
 
-def measured_traffic(config, prec, sym):
+def measured_traffic(config, prec, sym, mean_iters):
     """HBM bytes per NS launch from the committed FETCH_SIZE/WRITE_SIZE
     summary (copy-calibrated), or None when the summary does not cover this
-    workload and kernel variant, or the kernel source has changed since the
-    counters were taken."""
+    workload and kernel variant, the kernel source has changed since the
+    counters were taken, or the iterations per submatrix differ (the
+    average runs over every launch of a step, converged ones included)."""
     import hashlib
     if config != 3 or prec != "fp16" or not os.path.exists(TRAFFIC_FILE):
         return None
-    sha, nbytes, variant = None, None, None
+    sha, nbytes, variant, iters = None, None, None, None
     for line in open(TRAFFIC_FILE):
         if line.startswith("kernel_source_sha256 "):
             sha = line.split(":", 1)[1].strip()
@@ -60,8 +61,11 @@ def measured_traffic(config, prec, sym):
             variant = line.split(":", 1)[1].strip()
         elif line.startswith("k_ns_lp traffic_bytes_per_launch:"):
             nbytes = int(line.split(":", 1)[1])
+        elif line.startswith("k_ns_lp mean_iterations:"):
+            iters = float(line.split(":", 1)[1])
     cur = hashlib.sha256(open(NS_SOURCE, "rb").read()).hexdigest()
-    ok = sha == cur and nbytes and variant == ("sym" if sym else "plain")
+    ok = (sha == cur and nbytes and variant == ("sym" if sym else "plain") and iters is not None
+          and abs(iters - mean_iters) <= 0.05)
     return nbytes if ok else None
 
 
@@ -299,7 +303,7 @@ def main():
     ns_tf = exec_gemm_flops / (prof["ms_ns"] / 1e3) / 1e12 if prof["ms_ns"] > 0 else 0.0
     peak = PEAK_TFLOPS[args.prec]
     roofline = {"bound": "mfma", "achieved": round(ns_tf, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(ns_tf / peak, 4), "traffic": measured_traffic(args.config, args.prec, sym),
+                "frac": round(ns_tf / peak, 4), "traffic": measured_traffic(args.config, args.prec, sym, float(it.mean())),
                 "kernel": ("k_ns_lp" + ("<sym>" if sym else "")) if args.prec in ("fp16", "bf16") else "k_ns64",
                 "launches": prof["n_ns_launches"],
                 "avg_launch_ms": round(prof["ms_ns"] / max(1, prof["n_ns_launches"]), 4)}
