@@ -189,6 +189,17 @@ typedef struct {
 /* Fills *o with the defaults above for precision `prec`. */
 void nolsm_default_opts(nolsm_solve_opts *o, int32_t prec);
 
+/* The residual ||X^2 - I||_F at which a solve with these options stops the
+ * sign iteration (Eq. NS1; reading of the stopping rule in the design
+ * notes): `tol` itself when tol >= 0; for tol < 0 the default of `prec`
+ * (FP64 1e-10, FP32 1e-5) or, for FP16/BF16, the hand-over to the
+ * n_final_fp32 exact FP32 steps: one step maps e = 1 - x^2 of an eigenvalue
+ * to 3/4 e^2 + 1/4 e^3, so two leave 27/64 r^4 to leading order, held
+ * below a tenth of the format's unit roundoff u (2^-11 FP16, 2^-8 BF16):
+ * r = (64 u / 270)^(1/4); one step: r = (4 u / 30)^(1/2); none: 0 (the
+ * stagnation test alone). Pure function of its arguments, host only. */
+double nolsm_switch_tol(int32_t prec, int32_t n_final_fp32, double tol);
+
 /* Per-molecule statistics, written to device memory by nolsm_sign_batch. */
 typedef struct {
     int32_t iters;           /* Newton-Schulz updates taken in the main precision */

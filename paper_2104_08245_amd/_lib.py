@@ -78,7 +78,7 @@ EXPORTED = ["nolsm_default_opts", "nolsm_build_submatrices", "nolsm_plan_info", 
             "nolsm_plan_configure", "nolsm_plan_bind", "nolsm_sign_batch", "nolsm_assemble_D",
             "nolsm_plan_destroy", "nolsm_strerror", "nolsm_mlp_forward", "nolsm_mlp_loss_grad",
             "nolsm_mlp_adam", "nolsm_profile_last", "nolsm_trace_sums", "nolsm_mu_bisect",
-            "nolsm_plan_groups"]
+            "nolsm_plan_groups", "nolsm_switch_tol"]
 
 _lib = None
 
@@ -95,6 +95,8 @@ def lib():
     p_i32 = C.POINTER(C.c_int32)
     L.nolsm_default_opts.argtypes = [C.POINTER(SolveOpts), i32]
     L.nolsm_default_opts.restype = None
+    L.nolsm_switch_tol.argtypes = [i32, i32, dbl]
+    L.nolsm_switch_tol.restype = dbl
     L.nolsm_build_submatrices.argtypes = [C.POINTER(Pattern), C.POINTER(Pattern), i32, C.POINTER(vp)]
     L.nolsm_plan_info.argtypes = [vp, C.POINTER(PlanSizes)]
     L.nolsm_plan_export.argtypes = [vp, p_i32, p_i32, p_i32, p_i32, p_i32, p_i32]
@@ -116,9 +118,8 @@ def lib():
     L.nolsm_mlp_adam.argtypes = [vp, vp, vp, vp, i32, C.c_double, C.c_double, C.c_double, C.c_double, vp]
     for name in EXPORTED:
         f = getattr(L, name)
-        if f.restype is C.c_int or name not in ("nolsm_default_opts", "nolsm_plan_destroy", "nolsm_strerror"):
-            if name not in ("nolsm_default_opts", "nolsm_plan_destroy", "nolsm_strerror"):
-                f.restype = C.c_int
+        if name not in ("nolsm_default_opts", "nolsm_plan_destroy", "nolsm_strerror", "nolsm_switch_tol"):
+            f.restype = C.c_int
     _lib = L
     return L
 

@@ -42,12 +42,12 @@ int nolsm_elem_for(int32_t prec) {
 // finishing iterations (a tol < 0 asks for it; tol >= 0 is used as given).
 // One Newton-Schulz step maps e = 1 - x^2 of every eigenvalue x to
 // 3/4 e^2 + 1/4 e^3, and ||X^2 - I||_F bounds every |e|, so f FP32 steps
-// from a residual r leave at most 3/4 r^2 (f = 1) or 27/64 r^4 (f = 2).
-// The switch point puts that below a tenth of the unit roundoff u of the
-// 16-bit format (2^-11 FP16, 2^-8 BF16), under the rounding the 16-bit
+// from a residual r leave 3/4 r^2 (f = 1) or 27/64 r^4 (f = 2) to leading
+// order. The switch point puts that below a tenth of the unit roundoff u of
+// the 16-bit format (2^-11 FP16, 2^-8 BF16), under the rounding the 16-bit
 // iterate itself carries: FP16 0.104, BF16 0.174 with f = 2. Without
 // finishing steps only the stagnation test stops the iteration.
-double nolsm_switch_tol(int32_t prec, int32_t n_final_fp32, double tol) {
+extern "C" double nolsm_switch_tol(int32_t prec, int32_t n_final_fp32, double tol) {
     if (tol >= 0.0) return tol;
     if (prec == NOLSM_FP64) return 1e-10;
     if (prec == NOLSM_FP32) return 1e-5;

@@ -68,5 +68,4 @@ size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_i
                         int32_t nown, int32_t sym);
 int nolsm_ns_tile_for(int32_t prec, int32_t np, uint64_t small_mask);
 int nolsm_elem_for(int32_t prec);
-double nolsm_switch_tol(int32_t prec, int32_t n_final_fp32, double tol);
 void nolsm_set_last_error(const std::string &s);

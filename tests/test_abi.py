@@ -225,3 +225,34 @@ def test_pipeline_schedule_splits_the_workspace(L, config1):
     with pytest.raises(NolsmError) as e:
         p.configure(L.default_opts("fp16", sched=L.SCHED_PIPELINE), small)
     assert e.value.code == L.E_WORKSPACE
+
+
+def test_switch_point_of_the_16bit_iteration(L):
+    """The hand-over residual that nolsm_switch_tol returns, against what two
+    (one) exact Newton-Schulz steps of the oracle (Eq. NS1) leave of it on a
+    spectrum whose whole residual sits in one eigenvalue (the worst case:
+    ||X^2 - I||_F bounds every |1 - x^2|): a tenth of the format's unit
+    roundoff at leading order, the higher orders adding under 15%."""
+    lib = L.lib()
+    rng = np.random.default_rng(7)
+    n = 96
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    signs = np.where(np.arange(n) % 3 == 0, -1.0, 1.0)
+    for prec, u in (("fp16", 2.0 ** -11), ("bf16", 2.0 ** -8)):
+        for steps in (1, 2):
+            r = lib.nolsm_switch_tol(L.PREC[prec], steps, -1.0)
+            e = np.zeros(n)
+            e[0] = r
+            A = (Q * (signs * np.sqrt(1.0 - e))) @ Q.T
+            assert abs(np.linalg.norm(A @ A - np.eye(n)) - r) < 1e-12
+            X, _, _, _ = o.newton_schulz_sign(A, 1.0, tol=0.0, max_iter=steps)
+            left = np.linalg.norm(X @ X - np.eye(n))
+            assert u / 10 <= left <= 1.15 * u / 10, (prec, steps, r, left)
+        assert lib.nolsm_switch_tol(L.PREC[prec], 0, -1.0) == 0.0
+        assert lib.nolsm_switch_tol(L.PREC[prec], 2, 0.3) == 0.3
+    assert lib.nolsm_switch_tol(L.PREC["fp64"], 0, -1.0) == 1e-10
+    assert lib.nolsm_switch_tol(L.PREC["fp32"], 0, -1.0) == 1e-5
+    # the defaults ask for the derived point in 16 bits only
+    for prec in ("fp16", "bf16"):
+        assert L.default_opts(prec).tol < 0
+    assert L.default_opts("fp64").tol == 1e-10
