@@ -22,6 +22,6 @@ def gpu_available():
 
 
 @pytest.fixture(scope="session")
-def config1():
+def box64():
     import synth
     return synth.make_config(1)

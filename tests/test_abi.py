@@ -64,9 +64,9 @@ int main(void) {
     assert np.dtype(L.MOLSTATS_DTYPE).itemsize == C.sizeof(L.MolStats)
 
 
-def test_plan_equals_oracle_merge(L, config1):
+def test_plan_equals_oracle_merge(L, box64):
     from paper_2104_08245_amd import Plan
-    s = config1
+    s = box64
     p = Plan(s.K.nb, s.K.bs, s.K.row_ptr, s.K.col_idx, s.S.row_ptr, s.S.col_idx)
     ex = p.export()
     ref = o.plan_arrays(s.K.nb, s.K.row_ptr, s.K.col_idx, s.S.row_ptr, s.S.col_idx)
@@ -121,9 +121,9 @@ def test_malformed_patterns_rejected(L, case):
     assert e.value.code == L.E_PATTERN
 
 
-def test_configure_chunks_and_workspace_errors(L, config1):
+def test_configure_chunks_and_workspace_errors(L, box64):
     from paper_2104_08245_amd import Plan, NolsmError
-    s = config1
+    s = box64
     p = Plan(s.K.nb, s.K.bs, s.K.row_ptr, s.K.col_idx)
     opts = L.default_opts("fp16")
     mb = p.configure(opts, 1 << 40)
@@ -142,9 +142,9 @@ def test_configure_chunks_and_workspace_errors(L, config1):
     assert p.info()["nchunks"] == buckets
 
 
-def test_bad_options_rejected(L, config1):
+def test_bad_options_rejected(L, box64):
     from paper_2104_08245_amd import Plan, NolsmError
-    s = config1
+    s = box64
     p = Plan(s.K.nb, s.K.bs, s.K.row_ptr, s.K.col_idx)
     for kw in (dict(prec=7), dict(max_iter=1), dict(max_iter=500), dict(sched=9), dict(inverse=5),
                dict(inverse=L.INV_COUPLED_NS),                       # FP64: 16-bit route only
@@ -169,7 +169,7 @@ def _chain_pattern(nb):
     return np.array(ptr, np.int32), np.array(idx, np.int32)
 
 
-def test_combination_equals_oracle(L, config1):
+def test_combination_equals_oracle(L, box64):
     # integer work: the library's groups must equal the oracle's exactly
     import synth
     from oracle import combine as cb
@@ -178,7 +178,7 @@ def test_combination_equals_oracle(L, config1):
                                                   np.arange(8, dtype=np.int32))]
     slab = synth.water_slab(config_id=104, r_c=0.9, n_dense=96, n_dilute=96,
                             box=np.array([2.0, 2.0, 6.0]), z_split=1.4)
-    for name, s in (("config1", config1), ("slab", slab)):
+    for name, s in (("box64", box64), ("slab", slab)):
         cases.append((name, s.K.nb, s.K.row_ptr, s.K.col_idx))
     for name, nb, rp, ci in cases:
         p = Plan(nb, 6, rp, ci, flags=L.PLAN_COMBINE)
@@ -191,9 +191,9 @@ def test_combination_equals_oracle(L, config1):
         assert inf["ngroups"] == len(want[0]) - 1
         assert inf["sum_gn3"] == cb.cubic_cost(want[0]) * 216.0
     # without the flag every molecule is its own submatrix
-    p = Plan(config1.K.nb, 6, config1.K.row_ptr, config1.K.col_idx)
+    p = Plan(box64.K.nb, 6, box64.K.row_ptr, box64.K.col_idx)
     g = p.groups()
-    assert np.array_equal(g[2], np.arange(config1.K.nb + 1)) and np.array_equal(g[3], np.arange(config1.K.nb))
+    assert np.array_equal(g[2], np.arange(box64.K.nb + 1)) and np.array_equal(g[3], np.arange(box64.K.nb))
 
 
 def test_default_route_is_fp64_cholesky_on_a(L):
@@ -203,10 +203,10 @@ def test_default_route_is_fp64_cholesky_on_a(L):
         assert o.inverse == L.INV_CHOLESKY and o.sym_sign == 0
 
 
-def test_pipeline_schedule_splits_the_workspace(L, config1):
+def test_pipeline_schedule_splits_the_workspace(L, box64):
     # two resident chunks: each gets half of the workspace
     from paper_2104_08245_amd import Plan, NolsmError
-    s = config1
+    s = box64
     p = Plan(s.K.nb, s.K.bs, s.K.row_ptr, s.K.col_idx)
     g = L.default_opts("fp16")
     p.configure(g, 1 << 40)

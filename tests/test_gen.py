@@ -14,8 +14,8 @@ def test_deterministic_per_seed():
     assert not np.array_equal(a.centres, c.centres)
 
 
-def test_geometry_and_density(config1):
-    s = config1
+def test_geometry_and_density(box64):
+    s = box64
     n = s.nmol
     assert abs(n / np.prod(s.box) - 33.4) < 1e-9
     d = synth.min_image(s.centres[:, None] - s.centres[None], s.box)
@@ -23,9 +23,9 @@ def test_geometry_and_density(config1):
     assert r.min() >= MIN_SEP
 
 
-def test_matrices_symmetric_spd(config1):
+def test_matrices_symmetric_spd(box64):
     from oracle.nolsm import dense
-    s = config1
+    s = box64
     K, S = dense(s.K), dense(s.S)
     assert np.array_equal(K, K.T) and np.array_equal(S, S.T)
     np.linalg.cholesky(S)

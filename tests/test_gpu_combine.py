@@ -59,16 +59,16 @@ def oracle_on(system, sv):
     return o.nolsm_groups(system, g), g
 
 
-def test_fp64_combined_matches_oracle_config1(torch, config1):
-    sv = solve(config1, "fp64")
-    ref, g = oracle_on(config1, sv)
-    say(f"config1: {len(g[0]) - 1} groups for {config1.nmol} molecules, "
+def test_fp64_combined_matches_oracle_box64(torch, box64):
+    sv = solve(box64, "fp64")
+    ref, g = oracle_on(box64, sv)
+    say(f"box64: {len(g[0]) - 1} groups for {box64.nmol} molecules, "
         f"largest owns {np.diff(g[2]).max()}")
-    assert len(g[0]) - 1 < config1.nmol
+    assert len(g[0]) - 1 < box64.nmol
     st = sv.host_stats()
     assert np.all(st["status"] == 0)
     dc = sv.host_dcols()
-    worst = max(rel(dc[J], ref.Dcols[J]) for J in range(config1.nmol))
+    worst = max(rel(dc[J], ref.Dcols[J]) for J in range(box64.nmol))
     say("fp64 combined worst per-molecule rel-F", worst)
     assert worst <= 1e-10
     assert rel(sv.host_D(), ref.D_val) <= 1e-10
@@ -89,13 +89,13 @@ def test_fp64_full_cell_groups_fill_the_tile(torch, full_cell):
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
-def test_mixed_combined_within_stated_error(torch, config1, prec):
-    sv = solve(config1, prec)
-    ref, _ = oracle_on(config1, sv)
+def test_mixed_combined_within_stated_error(torch, box64, prec):
+    sv = solve(box64, prec)
+    ref, _ = oracle_on(box64, sv)
     st = sv.host_stats()
     assert np.all(st["status"] == 0)
     dc = sv.host_dcols()
-    errs = np.array([rel(dc[J], ref.Dcols[J]) for J in range(config1.nmol)])
+    errs = np.array([rel(dc[J], ref.Dcols[J]) for J in range(box64.nmol)])
     de = np.abs(st["energy_KD"] - ref.E)
     say(f"{prec} combined: Dcols rel-F max {errs.max():.3e} mean {errs.mean():.3e}; "
         f"|dE_J| max {de.max():.3e}")
@@ -117,30 +117,30 @@ def test_full_cell_combined_equals_uncombined_with_w(torch, full_cell):
         assert rel(runs[1][1][J], runs[0][1][J]) <= 1e-9
 
 
-def test_combined_coupled_inverse_route(torch, config1):
+def test_combined_coupled_inverse_route(torch, box64):
     # bounds of the 16-bit inverse route (derived with the per-molecule test)
     from paper_2104_08245_amd import _lib as L
-    sv = solve(config1, "fp16", inverse=L.INV_COUPLED_NS)
-    ref, _ = oracle_on(config1, sv)
+    sv = solve(box64, "fp16", inverse=L.INV_COUPLED_NS)
+    ref, _ = oracle_on(box64, sv)
     st = sv.host_stats()
     assert np.all(st["status"] == 0)
     dc = sv.host_dcols()
-    errs = np.array([rel(dc[J], ref.Dcols[J]) for J in range(config1.nmol)])
+    errs = np.array([rel(dc[J], ref.Dcols[J]) for J in range(box64.nmol)])
     say(f"fp16 combined coupled-NS: Dcols rel-F max {errs.max():.3e}")
     assert errs.max() <= 3e-2
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp16"])
-def test_combined_chunked_and_replayed_bit_identical(torch, config1, prec):
+def test_combined_chunked_and_replayed_bit_identical(torch, box64, prec):
     from paper_2104_08245_amd import Solver, _lib as L
-    one = solve(config1, prec)
+    one = solve(box64, prec)
     ref = one.Dcols.cpu().numpy()
     full = one.plan.info()["ws_full_bytes"]
-    many = solve(config1, prec, ws_bytes=full // 3 + 4096)
+    many = solve(box64, prec, ws_bytes=full // 3 + 4096)
     assert many.plan.info()["nchunks"] >= 3
     assert np.array_equal(many.Dcols.cpu().numpy(), ref)
     assert np.array_equal(many.D.cpu().numpy(), one.D.cpu().numpy())
-    sv = Solver(config1, prec=prec, device="cuda:0", combine=True, sched=L.SCHED_GRAPH)
+    sv = Solver(box64, prec=prec, device="cuda:0", combine=True, sched=L.SCHED_GRAPH)
     s = torch.cuda.Stream()
     for rep in range(3):
         say(f"[gpu] combined graph replay {rep} prec={prec}")
@@ -151,24 +151,24 @@ def test_combined_chunked_and_replayed_bit_identical(torch, config1, prec):
         assert np.array_equal(sv.Dcols.cpu().numpy(), ref), rep
 
 
-def test_not_spd_marks_every_owned_molecule(torch, config1):
-    sv = solve(config1, "fp64", debug_poison_mol=5)
+def test_not_spd_marks_every_owned_molecule(torch, box64):
+    sv = solve(box64, "fp64", debug_poison_mol=5)
     g = sv.plan.groups()
     grp = int(np.searchsorted(g[2], np.flatnonzero(g[3] == 5)[0], side="right") - 1)
     owned = set(g[3][g[2][grp]:g[2][grp + 1]].tolist())
     st = sv.host_stats()
     say(f"poisoned molecule 5 sits in a group owning {sorted(owned)}")
-    for J in range(config1.nmol):
+    for J in range(box64.nmol):
         assert (st["status"][J] != 0) == (J in owned)
 
 
-def test_fp64_combined_nonzero_mu(torch, config1):
-    sv = solve(config1, "fp64")
+def test_fp64_combined_nonzero_mu(torch, box64):
+    sv = solve(box64, "fp64")
     g = sv.plan.groups()
-    ref = o.nolsm_groups(config1, g, mu=0.25)
+    ref = o.nolsm_groups(box64, g, mu=0.25)
     sv.run(mu=0.25)
     torch.cuda.synchronize()
     dc = sv.host_dcols()
-    worst = max(rel(dc[J], ref.Dcols[J]) for J in range(config1.nmol))
+    worst = max(rel(dc[J], ref.Dcols[J]) for J in range(box64.nmol))
     say("fp64 combined mu=0.25 worst rel-F", worst)
     assert worst <= 1e-10

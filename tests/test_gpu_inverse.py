@@ -37,8 +37,8 @@ def torch():
 
 
 @pytest.fixture(scope="module")
-def ref1(config1):
-    return o.nolsm(config1)
+def ref1(box64):
+    return o.nolsm(box64)
 
 
 def solve(system, prec, **kw):
@@ -56,51 +56,51 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
-def test_coupled_inverse_route_matches_oracle(torch, config1, ref1, prec):
-    sv = solve(config1, prec)
+def test_coupled_inverse_route_matches_oracle(torch, box64, ref1, prec):
+    sv = solve(box64, prec)
     st = sv.host_stats()
     assert np.all(st["status"] == 0)
     assert np.all((st["iters_inv"] >= 5) & (st["iters_inv"] <= 30))
     dc = sv.host_dcols()
-    errs = np.array([rel(dc[J], ref1.Dcols[J]) for J in range(config1.nmol)])
+    errs = np.array([rel(dc[J], ref1.Dcols[J]) for J in range(box64.nmol)])
     dE = np.abs(st["energy_KD"] - ref1.E)
     say(f"{prec} coupled-NS route: Dcols rel-F max {errs.max():.3e} mean {errs.mean():.3e}; "
         f"|dE| max {dE.max():.3e} mean {dE.mean():.3e}; inverse iterations "
         f"{st['iters_inv'].min()}..{st['iters_inv'].max()}")
     assert errs.max() <= BOUNDS[prec]
-    for J in range(config1.nmol):
-        KJ, _, _, p = o.submatrix(config1, J)
+    for J in range(box64.nmol):
+        KJ, _, _, p = o.submatrix(box64, J)
         krows = KJ[6 * p:6 * p + 6, :]
         assert dE[J] <= BOUNDS[prec] * np.linalg.norm(krows) * np.linalg.norm(ref1.Dcols[J])
 
 
-def test_cholesky_route_reports_no_inverse_iterations(torch, config1):
+def test_cholesky_route_reports_no_inverse_iterations(torch, box64):
     from paper_2104_08245_amd import Solver
     import torch as T
-    sv = Solver(config1, prec="fp16", device="cuda:0")
+    sv = Solver(box64, prec="fp16", device="cuda:0")
     sv.run()
     T.cuda.synchronize()
     assert np.all(sv.host_stats()["iters_inv"] == 0)
 
 
-def test_coupled_inverse_flags_indefinite_overlap(torch, config1):
+def test_coupled_inverse_flags_indefinite_overlap(torch, box64):
     # S_J with a negative pivot: the scaled iteration has an eigenvalue of
     # c S_J below 0 and diverges, which marks the molecule NOT_SPD
-    sv = solve(config1, "fp16", debug_poison_mol=3)
+    sv = solve(box64, "fp16", debug_poison_mol=3)
     st = sv.host_stats()
     assert st["status"][3] != 0
-    ok = np.arange(config1.nmol) != 3
+    ok = np.arange(box64.nmol) != 3
     assert np.all(st["status"][ok] == 0)
 
 
-def test_coupled_inverse_route_nonzero_mu(torch, config1):
+def test_coupled_inverse_route_nonzero_mu(torch, box64):
     from paper_2104_08245_amd import Solver, _lib as L
-    ref = o.nolsm(config1, mu=0.25)
-    sv = Solver(config1, prec="fp16", device="cuda:0", inverse=L.INV_COUPLED_NS)
+    ref = o.nolsm(box64, mu=0.25)
+    sv = Solver(box64, prec="fp16", device="cuda:0", inverse=L.INV_COUPLED_NS)
     sv.run(mu=0.25)
     torch.cuda.synchronize()
     assert np.all(sv.host_stats()["status"] == 0)
     dc = sv.host_dcols()
-    errs = np.array([rel(dc[J], ref.Dcols[J]) for J in range(config1.nmol)])
+    errs = np.array([rel(dc[J], ref.Dcols[J]) for J in range(box64.nmol)])
     say(f"fp16 coupled-NS mu=0.25: Dcols rel-F max {errs.max():.3e}")
     assert errs.max() <= BOUNDS["fp16"]

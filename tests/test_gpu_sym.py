@@ -36,8 +36,8 @@ def torch():
 
 
 @pytest.fixture(scope="module")
-def ref1(config1):
-    return o.nolsm(config1)
+def ref1(box64):
+    return o.nolsm(box64)
 
 
 def solve(system, prec, mu=None, **kw):
@@ -68,35 +68,35 @@ def check_mixed(sv, ref, nmol, prec, tag):
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
-def test_symmetric_within_stated_error(torch, config1, ref1, prec):
+def test_symmetric_within_stated_error(torch, box64, ref1, prec):
     from paper_2104_08245_amd import Solver
-    st = check_mixed(solve(config1, prec), ref1, config1.nmol, prec, f"{prec} symmetric")
+    st = check_mixed(solve(box64, prec), ref1, box64.nmol, prec, f"{prec} symmetric")
     # same spectrum, same scale rule, same stopping rule: the iteration
     # counts stay those of the iteration on A_J, up to where each run's
     # 16-bit rounding lets the residual cross the switch point (BF16: within 2)
-    on_a = Solver(config1, prec=prec, device="cuda:0")
+    on_a = Solver(box64, prec=prec, device="cuda:0")
     on_a.run()
     torch.cuda.synchronize()
     assert np.all(np.abs(st["iters"] - on_a.host_stats()["iters"]) <= 2)
 
 
-def test_symmetric_on_fp32_factor(torch, config1, ref1):
+def test_symmetric_on_fp32_factor(torch, box64, ref1):
     from paper_2104_08245_amd import _lib as L
-    check_mixed(solve(config1, "fp16", inverse=L.INV_CHOLESKY_FP32), ref1, config1.nmol, "fp16",
+    check_mixed(solve(box64, "fp16", inverse=L.INV_CHOLESKY_FP32), ref1, box64.nmol, "fp16",
                 "fp16 symmetric, FP32 factor")
 
 
-def test_symmetric_nonzero_mu(torch, config1):
-    ref = o.nolsm(config1, mu=0.25)
-    check_mixed(solve(config1, "fp16", mu=0.25), ref, config1.nmol, "fp16", "fp16 symmetric mu=0.25")
+def test_symmetric_nonzero_mu(torch, box64):
+    ref = o.nolsm(box64, mu=0.25)
+    check_mixed(solve(box64, "fp16", mu=0.25), ref, box64.nmol, "fp16", "fp16 symmetric mu=0.25")
 
 
-def test_symmetric_outside_spectrum_is_exact(torch, config1):
+def test_symmetric_outside_spectrum_is_exact(torch, box64):
     # mu above the spectrum: sign = -I and Dcols = S_J^-1 E_cJ; the FP32
     # finishing leaves ~1e-7, so the setup and the L^-T solve are held to 1e-5
-    Js = list(range(0, config1.nmol, 7))
-    hi = o.nolsm(config1, mu=50.0, molecules=Js)
-    sv = solve(config1, "fp16", mu=50.0)
+    Js = list(range(0, box64.nmol, 7))
+    hi = o.nolsm(box64, mu=50.0, molecules=Js)
+    sv = solve(box64, "fp16", mu=50.0)
     dc = sv.host_dcols()
     worst = max(rel(dc[J], hi.Dcols[J]) for J in Js)
     say("symmetric mu=50 worst rel-F", worst)
@@ -106,22 +106,22 @@ def test_symmetric_outside_spectrum_is_exact(torch, config1):
     assert np.abs(sv.Dcols.cpu().numpy()).max() <= 1e-5 * max(np.abs(d).max() for d in dc)
 
 
-def test_symmetric_combined(torch, config1):
-    sv = solve(config1, "fp16", combine=True)
-    ref = o.nolsm_groups(config1, sv.plan.groups())
-    check_mixed(sv, ref, config1.nmol, "fp16", "fp16 symmetric combined")
+def test_symmetric_combined(torch, box64):
+    sv = solve(box64, "fp16", combine=True)
+    ref = o.nolsm_groups(box64, sv.plan.groups())
+    check_mixed(sv, ref, box64.nmol, "fp16", "fp16 symmetric combined")
 
 
 @pytest.mark.parametrize("prec", ["fp16"])
-def test_symmetric_schedules_chunks_and_replays_bit_identical(torch, config1, prec):
+def test_symmetric_schedules_chunks_and_replays_bit_identical(torch, box64, prec):
     from paper_2104_08245_amd import Solver, _lib as L
-    base = solve(config1, prec, sched=L.SCHED_STREAM)
+    base = solve(box64, prec, sched=L.SCHED_STREAM)
     ref = base.Dcols.cpu().numpy()
     for kw in (dict(sched=L.SCHED_PERSISTENT), dict(sched=L.SCHED_PER_BUCKET),
                dict(ws_bytes=base.plan.info()["ws_full_bytes"] // 3 + 4096)):
-        other = solve(config1, prec, **kw)
+        other = solve(box64, prec, **kw)
         assert np.array_equal(other.Dcols.cpu().numpy(), ref), kw
-    sv = Solver(config1, prec=prec, device="cuda:0", sym_sign=1, sched=L.SCHED_GRAPH)
+    sv = Solver(box64, prec=prec, device="cuda:0", sym_sign=1, sched=L.SCHED_GRAPH)
     s = torch.cuda.Stream()
     for rep in range(3):
         say(f"[gpu] symmetric graph replay {rep}")
@@ -132,16 +132,16 @@ def test_symmetric_schedules_chunks_and_replays_bit_identical(torch, config1, pr
         assert np.array_equal(sv.Dcols.cpu().numpy(), ref), rep
 
 
-def test_symmetric_not_spd_flagged(torch, config1, ref1):
-    sv = solve(config1, "fp16", debug_poison_mol=5)
+def test_symmetric_not_spd_flagged(torch, box64, ref1):
+    sv = solve(box64, "fp16", debug_poison_mol=5)
     st = sv.host_stats()
     assert st["status"][5] != 0
     assert np.all(np.delete(st["status"], 5) == 0)
 
 
-def test_symmetric_rejects_outputs_defined_on_a(torch, config1):
+def test_symmetric_rejects_outputs_defined_on_a(torch, box64):
     from paper_2104_08245_amd import Solver, NolsmError, _lib as L
-    sv = Solver(config1, prec="fp16", device="cuda:0", sym_sign=1)
+    sv = Solver(box64, prec="fp16", device="cuda:0", sym_sign=1)
     sv.want_w()
     with pytest.raises(NolsmError) as e:
         sv.run()

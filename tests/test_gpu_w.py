@@ -33,8 +33,8 @@ def torch():
 
 
 @pytest.fixture(scope="module")
-def refw(config1):
-    return o.nolsm(config1, want_w=True, keep_x=True)
+def refw(box64):
+    return o.nolsm(box64, want_w=True, keep_x=True)
 
 
 def solve_w(system, prec, **kw):
@@ -53,42 +53,42 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def test_w_fp64_matches_oracle_config1(torch, config1, refw):
-    sv = solve_w(config1, "fp64")
+def test_w_fp64_matches_oracle_box64(torch, box64, refw):
+    sv = solve_w(box64, "fp64")
     assert np.all(sv.host_stats()["status"] == 0)
     wc = sv.host_dcols("W")
-    worst = max(rel(wc[J], refw.Wcols[J]) for J in range(config1.nmol))
+    worst = max(rel(wc[J], refw.Wcols[J]) for J in range(box64.nmol))
     say("W fp64 worst per-molecule rel-F", worst)
     assert worst <= 1e-9
     W = sv.W.cpu().numpy().reshape(-1, 6, 6)
     assert rel(W, refw.W_val) <= 1e-9
 
 
-def test_w_kernel_is_the_exact_product(torch, config1, refw):
+def test_w_kernel_is_the_exact_product(torch, box64, refw):
     # isolates the W kernel: its output equals (A_J + mu I) Dcols_J formed on
     # the CPU from the oracle's A_J and the GPU's own Dcols_J; the FP64
     # Cholesky route makes the GPU's A_J the oracle's to rounding
     from paper_2104_08245_amd import _lib as L
-    sv = solve_w(config1, "fp16", inverse=L.INV_CHOLESKY)
+    sv = solve_w(box64, "fp16", inverse=L.INV_CHOLESKY)
     dc, wc = sv.host_dcols(), sv.host_dcols("W")
-    for J in range(0, config1.nmol, 5):
+    for J in range(0, box64.nmol, 5):
         _, A = refw.xs[J]
-        ref = (A + config1.mu * np.eye(A.shape[0])) @ dc[J]
+        ref = (A + box64.mu * np.eye(A.shape[0])) @ dc[J]
         assert rel(wc[J], ref) <= 1e-10
 
 
-def test_w_fp16_within_stated_error(torch, config1, refw):
-    sv = solve_w(config1, "fp16")
+def test_w_fp16_within_stated_error(torch, box64, refw):
+    sv = solve_w(box64, "fp16")
     wc = sv.host_dcols("W")
-    errs = [rel(wc[J], refw.Wcols[J]) for J in range(config1.nmol)]
+    errs = [rel(wc[J], refw.Wcols[J]) for J in range(box64.nmol)]
     say("W fp16 per-molecule rel-F max", max(errs), "mean", float(np.mean(errs)))
     assert max(errs) <= 1e-2
 
 
-def test_w_not_spd_molecule_is_zero(torch, config1):
+def test_w_not_spd_molecule_is_zero(torch, box64):
     from paper_2104_08245_amd import Solver
     import torch as T
-    sv = Solver(config1, prec="fp64", device="cuda:0", debug_poison_mol=3)
+    sv = Solver(box64, prec="fp64", device="cuda:0", debug_poison_mol=3)
     sv.want_w()
     sv.run()
     T.cuda.synchronize()
@@ -99,15 +99,15 @@ def test_w_not_spd_molecule_is_zero(torch, config1):
     assert np.all(np.isfinite(np.concatenate([w.ravel() for w in wc])))
 
 
-def test_w_fp64_nonzero_mu(torch, config1):
+def test_w_fp64_nonzero_mu(torch, box64):
     # W = (A_J + mu I) Dcols_J: the shift enters twice (in A_J and added back)
-    ref = o.nolsm(config1, mu=0.25, want_w=True)
+    ref = o.nolsm(box64, mu=0.25, want_w=True)
     from paper_2104_08245_amd import Solver
-    sv = Solver(config1, prec="fp64", device="cuda:0")
+    sv = Solver(box64, prec="fp64", device="cuda:0")
     sv.want_w()
     sv.run(mu=0.25)
     torch.cuda.synchronize()
     wc = sv.host_dcols("W")
-    worst = max(rel(wc[J], ref.Wcols[J]) for J in range(config1.nmol))
+    worst = max(rel(wc[J], ref.Wcols[J]) for J in range(box64.nmol))
     say("W fp64 mu=0.25 worst rel-F", worst)
     assert worst <= 1e-9

@@ -72,8 +72,8 @@ def test_p2_block_diagonal():
         assert abs(r.N[J] - 4) < 1e-10
 
 
-def test_p3_per_submatrix_invariants(config1):
-    s = config1
+def test_p3_per_submatrix_invariants(box64):
+    s = box64
     r = o.nolsm(s, molecules=range(0, 64, 7), keep_x=True)
     for J in range(0, 64, 7):
         KJ, SJ, idx, p = o.submatrix(s, J)
@@ -106,8 +106,8 @@ def test_p4_identity_overlap_is_eigenprojector():
     assert np.linalg.norm(D - P) <= 1e-10 * np.linalg.norm(P)
 
 
-def test_p4_mu_outside_spectrum(config1):
-    s = config1
+def test_p4_mu_outside_spectrum(box64):
+    s = box64
     Js = [0, 17, 40]
     hi = o.nolsm(s, mu=50.0, molecules=Js)
     lo = o.nolsm(s, mu=-50.0, molecules=Js)
@@ -132,8 +132,8 @@ def test_p4_scalar(k, sv, mu):
     assert abs(r.D_val[0, 0, 0] - expect) < 1e-14
 
 
-def test_p5_gershgorin_encloses_spectrum(config1):
-    s = config1
+def test_p5_gershgorin_encloses_spectrum(box64):
+    s = box64
     for J in (3, 33, 63):
         KJ, SJ, idx, p = o.submatrix(s, J)
         A = np.linalg.solve(SJ, KJ)
@@ -145,8 +145,8 @@ def test_p5_gershgorin_encloses_spectrum(config1):
         assert np.abs(lam).max() * (1.0 / np.abs(A).sum(axis=1).max()) <= 1.0
 
 
-def test_p6_indexing_brute_force(config1):
-    s = config1
+def test_p6_indexing_brute_force(box64):
+    s = box64
     lists, self_pos = o.merge(s.K.nb, s.K.row_ptr, s.K.col_idx, s.S.row_ptr, s.S.col_idx)
     d = synth.min_image(s.centres[:, None] - s.centres[None], s.box)
     r = np.sqrt((d ** 2).sum(-1))
@@ -176,8 +176,8 @@ def test_merge_is_union_of_different_patterns():
     assert sp.tolist() == [0, 1, 1, 2]
 
 
-def test_sign_is_scale_invariant(config1):
-    s = config1
+def test_sign_is_scale_invariant(box64):
+    s = box64
     KJ, SJ, idx, p = o.submatrix(s, 11)
     a = o.solve_submatrix(KJ, SJ, p, 6, 0.0)
     A = a.A
@@ -200,8 +200,8 @@ def test_validate_rejects_bad_patterns():
         o.validate_pattern(2, np.array([0, 2, 4]), np.array([0, 2, 0, 1]))  # out of range
 
 
-def test_not_spd_and_noconv_flags(config1):
-    s = config1
+def test_not_spd_and_noconv_flags(box64):
+    s = box64
     KJ, SJ, idx, p = o.submatrix(s, 5)
     bad = SJ.copy()
     bad[0, 0] = -1.0
@@ -248,8 +248,8 @@ def test_pins_reject_planted_mistakes(kind, monkeypatch):
     assert np.linalg.norm(D - Dex) / np.linalg.norm(Dex) > 1e-6
 
 
-def test_vectorized_gather_equals_plain_gather(config1):
-    s = config1
+def test_vectorized_gather_equals_plain_gather(box64):
+    s = box64
     lists, _ = o.neighbour_lists(s)
     for J in (0, 9, 63):
         a = o.gather(lists[J], 6, s.K.row_ptr, s.K.col_idx, s.K.val)

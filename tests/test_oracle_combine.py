@@ -51,8 +51,8 @@ def test_c2_block_diagonal_never_merges():
     assert groups_as_sets(g) == [[J] for J in range(8)]
 
 
-def test_c3_termination_and_cost(config1):
-    s = config1
+def test_c3_termination_and_cost(box64):
+    s = box64
     plan = o.plan_arrays(s.K.nb, s.K.row_ptr, s.K.col_idx, s.S.row_ptr, s.S.col_idx)
     g = cb.combine_groups(s.K.nb, plan["sub_ptr"], plan["sub_blk"])
     grp_ptr, grp_blk, own_ptr, own_J = g
@@ -90,8 +90,8 @@ def test_c4_full_cell_combined_is_exact():
     assert abs(r.N.sum() - Co.shape[1]) < 1e-9
 
 
-def test_c5_trivial_grouping_is_the_per_molecule_oracle(config1):
-    s = config1
+def test_c5_trivial_grouping_is_the_per_molecule_oracle(box64):
+    s = box64
     plan = o.plan_arrays(s.K.nb, s.K.row_ptr, s.K.col_idx, s.S.row_ptr, s.S.col_idx)
     nb = s.K.nb
     trivial = (plan["sub_ptr"], plan["sub_blk"], np.arange(nb + 1), np.arange(nb))

@@ -19,9 +19,9 @@ def scale(S):
     return 1.0 / np.abs(S).sum(axis=1).max()
 
 
-def test_i1_equals_lapack_inverse(config1):
+def test_i1_equals_lapack_inverse(box64):
     for J in (0, 21, 63):
-        _, SJ, _, _ = o.submatrix(config1, J)
+        _, SJ, _, _ = o.submatrix(box64, J)
         Sinv, k, r, ok = o.coupled_ns_inverse(SJ, scale(SJ))
         assert ok and r < 1e-12 and 5 <= k <= 30
         ref = np.linalg.inv(SJ)
@@ -39,8 +39,8 @@ def test_i2_closed_forms():
     assert ok and k == 0 and np.array_equal(Sinv, np.eye(5))
 
 
-def test_i3_polynomial_structure(config1):
-    _, SJ, _, _ = o.submatrix(config1, 7)
+def test_i3_polynomial_structure(box64):
+    _, SJ, _, _ = o.submatrix(box64, 7)
     Sinv, _, _, ok = o.coupled_ns_inverse(SJ, scale(SJ))
     assert ok
     assert np.linalg.norm(Sinv - Sinv.T) <= 1e-13 * np.linalg.norm(Sinv)
@@ -48,10 +48,10 @@ def test_i3_polynomial_structure(config1):
     assert np.linalg.norm(Sinv @ SJ - np.eye(n)) <= 1e-11
 
 
-def test_i4_density_matrix_equals_cholesky_route(config1):
+def test_i4_density_matrix_equals_cholesky_route(box64):
     for J in (3, 33, 50):
-        a = o.solve_molecule(config1, J)
-        b = o.solve_molecule(config1, J, inverse="coupled_ns")
+        a = o.solve_molecule(box64, J)
+        b = o.solve_molecule(box64, J, inverse="coupled_ns")
         assert a.status == b.status == o.OK
         assert np.linalg.norm(b.Dcols - a.Dcols) <= 1e-10 * np.linalg.norm(a.Dcols)
         assert abs(a.E_J - b.E_J) <= 1e-10 * max(1.0, abs(a.E_J))
@@ -85,8 +85,8 @@ def _mutant(kind):
 
 
 @pytest.mark.parametrize("kind", ["no_half", "plus_sign", "stale_Y", "no_square"])
-def test_inverse_pins_reject_planted_mistakes(kind, config1):
-    _, SJ, _, _ = o.submatrix(config1, 0)
+def test_inverse_pins_reject_planted_mistakes(kind, box64):
+    _, SJ, _, _ = o.submatrix(box64, 0)
     with np.errstate(all="ignore"):
         Sinv, _, _, _ = _mutant(kind)(SJ, scale(SJ), max_iter=40)
         ref = np.linalg.inv(SJ)

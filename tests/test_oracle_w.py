@@ -60,8 +60,8 @@ def test_w2_block_diagonal():
         assert np.allclose(r.Wcols[J], WJ, rtol=0, atol=1e-12 * np.abs(WJ).max())
 
 
-def test_w3_projector_identity(config1):
-    s = config1
+def test_w3_projector_identity(box64):
+    s = box64
     for J in (0, 17, 40, 63):
         r = o.solve_molecule(s, J, want_w=True)
         assert r.status == o.OK
