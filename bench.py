@@ -69,6 +69,39 @@ def measured_traffic(config, prec, sym, mean_iters):
     return nbytes if ok else None
 
 
+# ------------------------------------------------------- density-matrix checks
+DENSITY_PROBES = 16
+
+
+def density_against_fp64(system, sv, args, dev):
+    """Idempotency ||D S D - D||_F / ||D||_F (probe estimate), asymmetry and
+    Tr(D S) per molecule of the assembled D of this solve and of the FP64
+    solve of the same batch on the GPU (whose D equals the FP64 oracle's to
+    1e-10 in the parity tests; the oracle itself would take hours here),
+    with the relative Frobenius difference of the two D."""
+    import torch
+    import scipy.sparse.linalg as spla
+    from paper_2104_08245_amd import Solver, diagnostics as dg
+    t0 = time.time()
+    ex = sv.plan.export()
+    nb, bs = system.K.nb, system.K.bs
+    S = dg.block_csr(nb, bs, system.S.row_ptr, system.S.col_idx, system.S.val)
+    Dm = dg.block_csr(nb, bs, ex["D_row_ptr"], ex["D_col_idx"], sv.host_D())
+    res = {"probes": DENSITY_PROBES,
+           "mixed": dg.density_checks(Dm, S, system.nmol, probes=DENSITY_PROBES, seed=11)}
+    ref = Solver(system, prec="fp64", device=dev, ws_budget=int(args.ws_gb * (1 << 30) // 2),
+                 combine=args.combine)
+    ref.run()
+    torch.cuda.synchronize()
+    D64 = dg.block_csr(nb, bs, ex["D_row_ptr"], ex["D_col_idx"], ref.host_D())
+    res["fp64_gpu"] = dg.density_checks(D64, S, system.nmol, probes=DENSITY_PROBES, seed=11)
+    res["rel_diff_D_vs_fp64"] = float(spla.norm(Dm - D64) / spla.norm(D64))
+    del ref
+    torch.cuda.empty_cache()
+    log(f"density checks: {time.time() - t0:.1f}s")
+    return res
+
+
 # ------------------------------------------------------------------ CPU leg
 _SYS = None
 
@@ -196,6 +229,9 @@ def main():
                     help="run the 16-bit sign iteration on the symmetric similar matrix "
                          "L^-1 K L^-T - mu I (upper GEMM tiles only, mirrored; default on, "
                          "--no-sym iterates on A = S^-1 K - mu I)")
+    ap.add_argument("--density", action=argparse.BooleanOptionalAction, default=True,
+                    help="16-bit runs: idempotency, asymmetry and trace of the assembled D, and of the "
+                         "FP64 GPU solve of the same batch (after the timed steps)")
     ap.add_argument("--combine", action="store_true",
                     help="combine submatrices (cubic criterion) before solving")
     ap.add_argument("--bounds-eval", action="store_true",
@@ -366,6 +402,8 @@ def main():
         out["w_matrix"] = {"ms": round(prof["ms_wmat"], 3),
                            "GB_per_s": round(wbytes / (prof["ms_wmat"] / 1e3) / 1e9, 1) if prof["ms_wmat"] > 0 else None,
                            "bytes": wbytes}
+    if args.density and args.prec in ("fp16", "bf16"):
+        out["density_checks"] = density_against_fp64(system, sv, args, dev)
     if cpu is not None:
         E = st["energy_KD"]
         dE = np.array([abs(E[J] - e) for J, e in cpu["E"].items()])

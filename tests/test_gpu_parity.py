@@ -120,6 +120,37 @@ def test_switch_point_saves_iterations_not_accuracy(torch, box64, ref1, prec):
     assert de_b.max() <= 1.25 * de_a.max()
 
 
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_assembled_density_checks_against_oracle(torch, box64, ref1, prec):
+    # With D_m = D + d and rho = ||d||_F / ||D||_F: D_m S D_m - D_m moves by
+    # d S D + D S d - d + d S d, so the idempotency error of the mixed D stays
+    # within ((||S D||_2 + ||D S||_2 + 1) rho + ||S||_2 ||D||_F rho^2
+    # + f rho) / (1 - rho) of the oracle's own truncation floor f; the
+    # asymmetry within (2 + g) rho / (1 - rho); Tr(D S) per molecule within
+    # ||d||_F ||S||_F / N (Cauchy-Schwarz)
+    from paper_2104_08245_amd import diagnostics as dg
+    import scipy.sparse.linalg as spla
+    sv = solve(box64, prec, sym_sign=1)
+    ex = sv.plan.export()
+    nb, bs = box64.K.nb, box64.K.bs
+    S = dg.block_csr(nb, bs, box64.S.row_ptr, box64.S.col_idx, box64.S.val)
+    Dm = dg.block_csr(nb, bs, ex["D_row_ptr"], ex["D_col_idx"], sv.host_D())
+    Do = dg.block_csr(nb, bs, ex["D_row_ptr"], ex["D_col_idx"], ref1.D_val)
+    cm, co = dg.density_checks(Dm, S, box64.nmol), dg.density_checks(Do, S, box64.nmol)
+    nD = spla.norm(Do)
+    rho = spla.norm(Dm - Do) / nD
+    Sd, Dd = S.toarray(), Do.toarray()
+    sd, ds, s2 = np.linalg.norm(Sd @ Dd, 2), np.linalg.norm(Dd @ Sd, 2), np.linalg.norm(Sd, 2)
+    say(f"{prec}: idempotency {cm['idempotency']:.3e} (oracle {co['idempotency']:.3e}), "
+        f"asymmetry {cm['asymmetry']:.3e} (oracle {co['asymmetry']:.3e}), D rel diff {rho:.3e}")
+    f, g = co["idempotency"], co["asymmetry"]
+    assert rho <= MIXED[prec]["dcols"]
+    assert abs(cm["idempotency"] - f) <= ((sd + ds + 1) * rho + s2 * nD * rho ** 2 + f * rho) / (1 - rho)
+    assert abs(cm["asymmetry"] - g) <= (2 + g) * rho / (1 - rho)
+    dtr = abs(cm["trace_DS_per_molecule"] - co["trace_DS_per_molecule"])
+    assert dtr <= rho * nD * np.linalg.norm(Sd) / box64.nmol
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp16"])
 def test_schedules_and_replays_bit_identical(torch, box64, prec):
     from paper_2104_08245_amd import _lib as L
