@@ -141,6 +141,8 @@ static LaunchArgs make_args(const nolsm_plan *pl, const BatchArgs &b) {
     ba.safety = o.mlp_safety > 0 ? o.mlp_safety : 1.05f;
     ba.learned = o.bounds == NOLSM_BOUNDS_LEARNED;
     ba.scale_mult = o.debug_scale_mult;
+    ba.sym = o.sym_sign ? 1 : 0;
+    ba.pad_ = 0;
     NsArgs &na = A.na;
     na.prec = o.prec;
     na.max_iter = o.max_iter;

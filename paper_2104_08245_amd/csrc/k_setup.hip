@@ -760,11 +760,18 @@ template <> __device__ __forceinline__ float cvt<float>(double x) { return (floa
 template <> __device__ __forceinline__ _Float16 cvt<_Float16>(double x) { return (_Float16)(float)x; }
 template <> __device__ __forceinline__ __bf16 cvt<__bf16>(double x) { return (__bf16)(float)x; }
 
-template <typename T>
+// SYM (the symmetric iteration on A~ = L^-1 K L^-T - mu I, 16-bit): only
+// tiles ti <= tj read A~; an off-diagonal tile also writes its transpose
+// (staged in LDS), and a diagonal tile takes its lower half from its upper
+// half, so X_0 is exactly symmetric and the FP64 tiles below the diagonal
+// are never read.
+template <typename T, bool SYM>
 __global__ __launch_bounds__(256) void k_convert(ChunkDev cd, char *ws, int use_scale_g) {
+    __shared__ T tt[SYM ? 64 : 1][SYM ? 65 : 1];
     const uint32_t task = xcd_task(cd.t_conv);
     if (task == NOLSM_TASK_NONE) return;
     const int s = task_slot(task), ti = task_a(task), tj = task_b(task);
+    if (SYM && ti > tj) return;
     const SubMeta M = cd.meta[s];
     const SubCtl *ctl = cd.ctl + s;
     if (ctl->status != NOLSM_MOL_OK) return;
@@ -775,8 +782,17 @@ __global__ __launch_bounds__(256) void k_convert(ChunkDev cd, char *ws, int use_
     const int64_t ldk = np + 64;
     for (int f = threadIdx.x; f < 4096; f += 256) {
         const int r = ti * 64 + (f >> 6), q = tj * 64 + (f & 63);
-        const double v = (r < n && q < n) ? c * A[(int64_t)r * ldk + q] : (r == q ? 1.0 : 0.0);
-        X[(int64_t)r * M.ldx + q] = cvt<T>(v);
+        const int ra = (SYM && r > q) ? q : r, qa = (SYM && r > q) ? r : q;
+        const double v = (r < n && q < n) ? c * A[(int64_t)ra * ldk + qa] : (r == q ? 1.0 : 0.0);
+        const T x = cvt<T>(v);
+        X[(int64_t)r * M.ldx + q] = x;
+        if constexpr (SYM) tt[f & 63][f >> 6] = x;
+    }
+    if constexpr (SYM) {
+        if (ti == tj) return;   // uniform per workgroup
+        __syncthreads();
+        for (int f = threadIdx.x; f < 4096; f += 256)
+            X[(int64_t)(tj * 64 + (f >> 6)) * M.ldx + ti * 64 + (f & 63)] = tt[f >> 6][f & 63];
     }
 }
 
@@ -844,18 +860,22 @@ hipError_t launch_subst(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st)
 hipError_t launch_bounds(const ChunkDev &cd, char *ws, const BoundsArgs &ba, int prec, hipStream_t st) {
     hipLaunchKernelGGL(k_bounds, dim3(cd.nsub), dim3(256), 0, st, cd, ws, ba);
     LAUNCH_CHECK();
-    // symmetric sign iteration: X_0 may differ from its transpose by a unit
-    // of the last place where A~'s two triangles round apart; the first
-    // update rebuilds X_1 exactly symmetric from the upper tiles
-    return launch_convert(cd, ws, prec, 0, st);
+    return launch_convert(cd, ws, prec, 0, ba.sym, st);
 }
 
-hipError_t launch_convert(const ChunkDev &cd, char *ws, int prec, int use_scale_g, hipStream_t st) {
+hipError_t launch_convert(const ChunkDev &cd, char *ws, int prec, int use_scale_g, int sym, hipStream_t st) {
+    const bool sy = sym != 0;
     switch (prec) {
-        case 0: hipLaunchKernelGGL(k_convert<double>, dim3(cd.n_conv), dim3(256), 0, st, cd, ws, use_scale_g); break;
-        case 1: hipLaunchKernelGGL(k_convert<float>, dim3(cd.n_conv), dim3(256), 0, st, cd, ws, use_scale_g); break;
-        case 2: hipLaunchKernelGGL(k_convert<_Float16>, dim3(cd.n_conv), dim3(256), 0, st, cd, ws, use_scale_g); break;
-        default: hipLaunchKernelGGL(k_convert<__bf16>, dim3(cd.n_conv), dim3(256), 0, st, cd, ws, use_scale_g); break;
+        case 0: hipLaunchKernelGGL((k_convert<double, false>), dim3(cd.n_conv), dim3(256), 0, st, cd, ws, use_scale_g); break;
+        case 1: hipLaunchKernelGGL((k_convert<float, false>), dim3(cd.n_conv), dim3(256), 0, st, cd, ws, use_scale_g); break;
+        case 2:
+            if (sy) hipLaunchKernelGGL((k_convert<_Float16, true>), dim3(cd.n_conv), dim3(256), 0, st, cd, ws, use_scale_g);
+            else hipLaunchKernelGGL((k_convert<_Float16, false>), dim3(cd.n_conv), dim3(256), 0, st, cd, ws, use_scale_g);
+            break;
+        default:
+            if (sy) hipLaunchKernelGGL((k_convert<__bf16, true>), dim3(cd.n_conv), dim3(256), 0, st, cd, ws, use_scale_g);
+            else hipLaunchKernelGGL((k_convert<__bf16, false>), dim3(cd.n_conv), dim3(256), 0, st, cd, ws, use_scale_g);
+            break;
     }
     return hipGetLastError();
 }

@@ -23,6 +23,8 @@ struct BoundsArgs {
     float safety;
     int32_t learned;
     double scale_mult;
+    int32_t sym;              // symmetric sign iteration: X_0 from the upper triangle
+    int32_t pad_;
 };
 
 // control of the sign iteration, identical for every workgroup of a launch
@@ -83,7 +85,7 @@ hipError_t launch_subst_sym(const ChunkDev &cd, char *ws, bool fp32, hipStream_t
 hipError_t launch_set_header(char *ws, double mu, hipStream_t st);
 hipError_t launch_trace_sums(const void *stats, int32_t nb, char *ws, hipStream_t st);
 hipError_t launch_bounds(const ChunkDev &cd, char *ws, const BoundsArgs &ba, int prec, hipStream_t st);
-hipError_t launch_convert(const ChunkDev &cd, char *ws, int prec, int use_scale_g, hipStream_t st);
+hipError_t launch_convert(const ChunkDev &cd, char *ws, int prec, int use_scale_g, int sym, hipStream_t st);
 hipError_t launch_ns_iter(const ChunkDev &cd, char *ws, const NsArgs &na, int it, hipStream_t st);
 hipError_t launch_finish(const ChunkDev &cd, char *ws, const FinishArgs &fa, hipStream_t st);
 hipError_t launch_extract(const ChunkDev &cd, char *ws, const ExtractArgs &ea, hipStream_t st);
