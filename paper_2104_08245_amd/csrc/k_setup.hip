@@ -526,24 +526,26 @@ __global__ __launch_bounds__(256, OCC) void k_subst(ChunkDev cd, char *ws) {
 // ---------------------------------------------------------------------------
 // Symmetric sign iteration, second half of the setup: with W = L^-1 K_J in the K
 // buffer (from the forward-only substitution), A~ = W L^-T = L^-1 K_J L^-T,
-// row block i per task, in place: X_ij = (W_ij - sum_{k<j} X_ik L_jk^T)
-// Dinv_j^T over the column tiles j in order. A row task owns its rows, so
-// the in-place update needs no other task. A~ - mu I has the spectrum of
-// A_J; being symmetric, its column sums are its row sums. Emits the bounds
-// inputs in the layout of k_subst (row sums per column tile, column sums,
-// Frobenius partials, here per row block) and takes mu off the diagonal once
-// the row block is complete. Task list: (slot, i) of k_subst; i = P returns.
-// RR column tiles per pass with their accumulators in registers.
+// row block i per launch (one workgroup per submatrix), in place:
+// X_ij = (W_ij - sum_{k<j} X_ik L_jk^T) Dinv_j^T over the column tiles
+// j >= i in order. The tiles left of the diagonal are not solved again:
+// A~ is symmetric, so X_ik = X_ki^T for k < i, final since the launch of row
+// block k; they are copied into place and feed the recursion, which saves a
+// third of the right solve's products. A~ - mu I has the spectrum of A_J;
+// being symmetric, its column sums are its row sums. Emits the bounds inputs
+// in the layout of k_subst (row sums per column tile, column sums, Frobenius
+// partials, here per row block) and takes mu off the diagonal once the row
+// block is complete. RR column tiles per pass with their accumulators in
+// registers.
 // ---------------------------------------------------------------------------
 template <typename T, int RR, int OCC>
-__global__ __launch_bounds__(256, OCC) void k_rsolve(ChunkDev cd, char *ws) {
+__global__ __launch_bounds__(256, OCC) void k_rsolve(ChunkDev cd, char *ws, int i) {
     const double mu = ((const WsHeader *)ws)->mu;
     __shared__ T sX[64][LDP];
     __shared__ T sL[64][LDP];
     __shared__ double red[256];
-    const uint32_t task = xcd_task(cd.t_subst);
-    if (task == NOLSM_TASK_NONE) return;
-    const int s = task_slot(task), i = task_a(task);
+    const int s = blockIdx.x;
+    if (s >= cd.nsub) return;
     const SubMeta M = cd.meta[s];
     if (cd.ctl[s].status != NOLSM_MOL_OK) return;
     const int P = M.P, np = M.np, n = M.n;
@@ -556,7 +558,33 @@ __global__ __launch_bounds__(256, OCC) void k_rsolve(ChunkDev cd, char *ws) {
     auto Xt = [&](int j) { return Kb + (int64_t)(i * 64) * ldk + j * 64; };   // tile (i, j)
     const int t = threadIdx.x;
     double rtot = 0.0, frob = 0.0;
-    for (int j0 = 0; j0 < P; j0 += RR) {
+    // tiles k < i: X_ik = X_ki^T (off the diagonal, never shifted by mu)
+    for (int k = 0; k < i; ++k) {
+        g2s_tile(sX, Kb + (int64_t)(k * 64) * ldk + i * 64, ldk);   // tile (k, i)
+        __syncthreads();
+        double *dst = Xt(k);
+        for (int f = t; f < 4096; f += 256) {
+            const int rr = f >> 6, q = f & 63;
+            dst[(int64_t)rr * ldk + q] = (double)sX[q][rr];
+        }
+        if (t < 64) {
+            const int gr = i * 64 + t;
+            double rs = 0.0;
+            for (int q = 0; q < 64; ++q)
+                if (k * 64 + q < n) rs += fabs((double)sX[q][t]);
+            double *rowp = (double *)(ws + M.offRow);
+            rowp[(int64_t)k * np + gr] = (gr < n) ? rs : 0.0;
+            rtot += rs;
+        }
+        double fs = 0.0;
+        for (int f = t; f < 4096; f += 256) {
+            const int rr = f >> 6, q = f & 63;
+            if (i * 64 + rr < n && k * 64 + q < n) fs += (double)sX[q][rr] * (double)sX[q][rr];
+        }
+        frob += fs;
+        __syncthreads();
+    }
+    for (int j0 = i; j0 < P; j0 += RR) {
         const int nr = min(RR, P - j0);
         AccT<T> acc[RR];
 #pragma unroll
@@ -840,14 +868,18 @@ hipError_t launch_chol(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st) 
 hipError_t launch_subst_sym(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st) {
     if (fp32) {
         hipLaunchKernelGGL((k_subst<float, 4, 1, 3, true>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
-        LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_rsolve<float, 4, 3>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
     } else {
         hipLaunchKernelGGL((k_subst<double, 4, 1, 2, true>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
-        LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_rsolve<double, 4, 2>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
     }
-    return hipGetLastError();
+    LAUNCH_CHECK();
+    // row blocks in order: block i reads the finished blocks k < i
+    const int pmax = cd.max_np / 64;
+    for (int i = 0; i < pmax; ++i) {
+        if (fp32) hipLaunchKernelGGL((k_rsolve<float, 4, 3>), dim3(cd.nsub), dim3(256), 0, st, cd, ws, i);
+        else hipLaunchKernelGGL((k_rsolve<double, 4, 2>), dim3(cd.nsub), dim3(256), 0, st, cd, ws, i);
+        LAUNCH_CHECK();
+    }
+    return hipSuccess;
 }
 hipError_t launch_subst(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st) {
     // one column tile per task keeps enough tasks in flight (two per task
