@@ -327,9 +327,14 @@ __global__ __launch_bounds__(256, OCC) void k_subst(ChunkDev cd, char *ws) {
         const int col0 = (cc + c < P) ? (cc + c) * 64 : np;
         return Kb + (int64_t)(r * 64) * ldk + col0;
     };
-    // forward: W_i = Dinv_i (B_i - sum_{k<i} L_ik W_k)
-    for (int i0 = 0; i0 < P; i0 += SR) {
-        const int nr = min(SR, P - i0);
+    // forward: W_i = Dinv_i (B_i - sum_{k<i} L_ik W_k). Row i needs only the
+    // rows above it, and the symmetric route's right solve reads W only on
+    // and above the diagonal (W_ij, j >= i: the rest of A~ comes from its
+    // upper tiles), so there the column tiles stop at their diagonal row; the
+    // E tile (y = L^-1 E) takes every row.
+    const int Pr = (FWD_ONLY && cc + nc <= P) ? cc + nc : P;
+    for (int i0 = 0; i0 < Pr; i0 += SR) {
+        const int nr = min(SR, Pr - i0);
         AccT<T> acc[SR][SC];
 #pragma unroll
         for (int r = 0; r < SR; ++r)
