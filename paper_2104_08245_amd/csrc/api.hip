@@ -133,6 +133,11 @@ static LaunchArgs make_args(const nolsm_plan *pl, const BatchArgs &b) {
     ga.Sval = b.dS;
     ga.bs = pl->bs;
     ga.poison_J = o.debug_poison_mol;
+    // the Cholesky reads T_J(S) only on and below its diagonal tiles; the
+    // symmetric route's substitutions read T_J(K) only on and above them
+    ga.s_lower = o.inverse != NOLSM_INV_COUPLED_NS;
+    ga.k_upper = o.sym_sign ? 1 : 0;
+    ga.pad_ = 0;
     BoundsArgs &ba = A.ba;
     ba.d_mlp = o.d_mlp;
     ba.d_norm = o.d_mlp_norm;

@@ -13,6 +13,9 @@ struct GatherArgs {
     int32_t s_fp32;           // write T_J(S) as FP32 (FP32 Cholesky route), else FP64
     int32_t bs;
     int32_t poison_J;
+    int32_t s_lower;          // write T_J(S) only on and below its diagonal 64-tiles
+    int32_t k_upper;          // write T_J(K) only on and above its diagonal 64-tiles
+    int32_t pad_;
 };
 
 struct BoundsArgs {
