@@ -337,7 +337,11 @@ __global__ __launch_bounds__(256, OCC) void k_subst(ChunkDev cd, char *ws) {
     // upper tiles), so there the column tiles stop at their diagonal row; the
     // E tile (y = L^-1 E) takes every row.
     const int Pr = (FWD_ONLY && cc + nc <= P) ? cc + nc : P;
-    for (int i0 = 0; i0 < Pr; i0 += SR) {
+    // The E tile alone: its rows above the first owned block are zero in
+    // E and stay zero in L^-1 E (L is lower triangular), so the solve
+    // starts at that block's row tile and sums only from there.
+    const int i1 = (cc == P) ? (M.pmin * (n / M.m)) / 64 : 0;
+    for (int i0 = i1; i0 < Pr; i0 += SR) {
         const int nr = min(SR, Pr - i0);
         AccT<T> acc[SR][SC];
 #pragma unroll
@@ -348,11 +352,11 @@ __global__ __launch_bounds__(256, OCC) void k_subst(ChunkDev cd, char *ws) {
         // the updates from the finished rows k < i0, one (k, r) step at a
         // time: the tiles of the next step are loaded into registers while
         // this step multiplies from LDS
-        if (i0 > 0) {
+        if (i0 > i1) {
             RegTile<T> pl;
-            g2r_tile(pl, Lt(i0, 0), ldl);
+            g2r_tile(pl, Lt(i0, i1), ldl);
             r2s_tile(sA, pl);
-            for (int k = 0; k < i0; ++k) {
+            for (int k = i1; k < i0; ++k) {
 #pragma unroll
                 for (int c = 0; c < SC; ++c)
                     if (c < nc) g2s_tile(sB[c], Bt(c, k), ldk);

@@ -24,7 +24,8 @@ struct SubMeta {
                       // to the NS tile, so tile loads never leave the buffer
     int32_t nown;     // molecules owned by this submatrix (1 unless combined)
     int32_t own_off;  // their offset in the owned-molecule list
-    int32_t pad2_;
+    int32_t pmin;     // smallest block position of an owned molecule (first
+                      // nonzero row block of the E columns)
     int64_t offL;     // np*np doubles (FP32 Cholesky route: floats): S -> L; later X buffer 0
     int64_t offK;     // np*(np+64) doubles: K -> W -> [A | Y]
     int64_t offDinv;  // P*64*64 doubles (or floats): inverses of the diagonal tiles of L

@@ -522,6 +522,9 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
                 m.sub_off = pl->grp_ptr[g];
                 m.own_off = pl->own_ptr[g];
                 m.nown = pl->own_ptr[g + 1] - pl->own_ptr[g];
+                m.pmin = m.p;
+                for (int32_t o = pl->own_ptr[g]; o < pl->own_ptr[g + 1]; ++o)
+                    m.pmin = std::min(m.pmin, pl->own_pos[o]);
                 const int32_t T = tile_of(g);
                 const int32_t nt = (m.np + T - 1) / T;
                 m.ntile_ns = nt * nt;
