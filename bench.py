@@ -89,7 +89,11 @@ def density_against_fp64(system, sv, args, dev):
     Dm = dg.block_csr(nb, bs, ex["D_row_ptr"], ex["D_col_idx"], sv.host_D())
     res = {"probes": DENSITY_PROBES,
            "mixed": dg.density_checks(Dm, S, system.nmol, probes=DENSITY_PROBES, seed=11)}
-    ref = Solver(system, prec="fp64", device=dev, ws_budget=int(args.ws_gb * (1 << 30) // 2),
+    # the timed solver's workspace is not needed any more: the FP64 solve
+    # gets the same budget
+    sv.ws = None
+    torch.cuda.empty_cache()
+    ref = Solver(system, prec="fp64", device=dev, ws_budget=int(args.ws_gb * (1 << 30)),
                  combine=args.combine)
     ref.run()
     torch.cuda.synchronize()
