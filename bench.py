@@ -244,7 +244,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(every submatrix is independent; see the design notes for how it would shard)",
+              "(every submatrix is independent, so molecules would be split across GPUs)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -190,8 +190,8 @@ typedef struct {
 void nolsm_default_opts(nolsm_solve_opts *o, int32_t prec);
 
 /* The residual ||X^2 - I||_F at which a solve with these options stops the
- * sign iteration (Eq. NS1; reading of the stopping rule in the design
- * notes): `tol` itself when tol >= 0; for tol < 0 the default of `prec`
+ * sign iteration (Eq. NS1; the paper runs a fixed step count instead):
+ * `tol` itself when tol >= 0; for tol < 0 the default of `prec`
  * (FP64 1e-10, FP32 1e-5) or, for FP16/BF16, the hand-over to the
  * n_final_fp32 exact FP32 steps: one step maps e = 1 - x^2 of an eigenvalue
  * to 3/4 e^2 + 1/4 e^3, so two leave 27/64 r^4 to leading order, held

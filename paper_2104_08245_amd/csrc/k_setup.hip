@@ -5,7 +5,7 @@
 // iteration acts on A_J = T_J(S)^-1 T_J(K) - mu I, and the owned columns of
 // T_J(D) need Y_J = T_J(S)^-1 E_cJ. Here T_J(S)^-1 is applied through an FP64
 // Cholesky factor (the paper's inverse is iterative; the FP64 factorisation
-// is this library's choice, see the design notes).
+// is this library's choice, for accuracy at these sizes).
 #include "dev_common.h"
 #include "kernels.h"
 
