@@ -122,7 +122,10 @@ typedef enum {
                                       ||R_k||_F); then S^-1 = c Z^2 and A_J =
                                       S^-1 K_J - mu I by two more GEMMs, with
                                       c = 1 / max row sum of |S_J|. A diverging
-                                      iteration marks the molecule NOT_SPD.   */
+                                      iteration, or one that does not stop
+                                      within inv_max_iter, marks the molecule
+                                      NOT_SPD (no inverse: its columns stay
+                                      zero and its sign iteration is skipped). */
     NOLSM_INV_CHOLESKY_FP32 = 2    /* FP16/BF16 only: the same
                                       Cholesky factor and substitution with FP32
                                       arithmetic on the matrix cores, FP64
@@ -141,7 +144,8 @@ typedef struct {
                                 derives it from the format and n_final_fp32
                                 (FP16 0.104, BF16 0.174 with two finishing
                                 iterations), 0 leaves only the stagnation test */
-    int32_t max_iter;        /* iteration slots per solve (default 60)           */
+    int32_t max_iter;        /* iteration slots per solve, 2..128 (defaults:
+                                FP64 48, FP32/FP16/BF16 40)                     */
     int32_t fixed_iters;     /* > 0: exactly this many low-precision updates, no
                                 residual test (the paper's fixed step count)    */
     double switch_theta;     /* FP32/FP16/BF16: stop when r_k > theta r_{k-1}
@@ -336,7 +340,10 @@ int nolsm_trace_sums(const nolsm_plan *plan, const nolsm_mol_stats *dstats, void
  * return dDcols / dD_val / dstats hold the last solve; *mu_out, *count_out,
  * *steps_out (may be NULL) report it. Errors as nolsm_sign_batch, plus
  * E_ARG (mu_hi <= mu_lo, tol_count <= 0, max_steps < 1) and E_NOCONV when
- * the count is not reached (the last solve is still returned). */
+ * the count is not reached, or when it is reached but some molecule of the
+ * final solve is not NOLSM_MOL_OK (a mu inside a band converges slowly; its
+ * NOCONV molecules still enter the count). With E_NOCONV the outputs, the
+ * last solve and *mu_out / *count_out / *steps_out are still returned. */
 int nolsm_mu_bisect(nolsm_plan *plan, const double *dK_val, const double *dS_val, double mu_lo,
                     double mu_hi, double n_target, double tol_count, int32_t max_steps,
                     const nolsm_solve_opts *opts, void *d_ws, size_t ws_bytes, double *dDcols,

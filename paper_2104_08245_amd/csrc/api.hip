@@ -460,7 +460,7 @@ extern "C" int nolsm_mu_bisect(nolsm_plan *pl, const double *dK_val, const doubl
         nolsm_set_last_error("mu_bisect: bad argument");
         return NOLSM_E_ARG;
     }
-    double lo = mu_lo, hi = mu_hi, mu = 0.5 * (lo + hi), cnt = 0.0;
+    double lo = mu_lo, hi = mu_hi, mu = 0.5 * (lo + hi), cnt = 0.0, n_bad = 0.0;
     int32_t step = 0;
     for (step = 1; step <= max_steps; ++step) {
         mu = 0.5 * (lo + hi);
@@ -470,6 +470,7 @@ extern "C" int nolsm_mu_bisect(nolsm_plan *pl, const double *dK_val, const doubl
         rc = nolsm_trace_sums(pl, dstats, d_ws, sums, stream);
         if (rc != NOLSM_OK) return rc;
         cnt = sums[0];
+        n_bad = sums[2];
         if (std::fabs(cnt - n_target) <= tol_count) break;
         if (cnt < n_target) lo = mu; else hi = mu;
     }
@@ -478,6 +479,14 @@ extern "C" int nolsm_mu_bisect(nolsm_plan *pl, const double *dK_val, const doubl
     if (steps_out) *steps_out = step > max_steps ? max_steps : step;
     if (std::fabs(cnt - n_target) > tol_count) {
         nolsm_set_last_error("mu_bisect: electron count not reached within max_steps");
+        return NOLSM_E_NOCONV;
+    }
+    // the count of the final solve includes molecules whose sign iteration
+    // did not meet its stop rule (a mu inside a band converges slowly): the
+    // result is returned, but not as a converged one
+    if (n_bad > 0.0) {
+        nolsm_set_last_error("mu_bisect: " + std::to_string((long long)n_bad) +
+                             " molecules not converged (or not SPD) at the final mu");
         return NOLSM_E_NOCONV;
     }
     return NOLSM_OK;

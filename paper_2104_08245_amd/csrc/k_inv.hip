@@ -79,8 +79,13 @@ __device__ int inv_decide(const InvArgs &ia, const SubMeta &M, InvCtl *ic, SubCt
         if (stop || diverge || last) {
             ic->done = 1;
             ic->iters = it;
-            if (diverge) ctl->status = NOLSM_MOL_NOT_SPD;
-            else if (last && !stop) ctl->status = NOLSM_MOL_NOCONV;
+            // no usable inverse (a diverging iteration, or none within the
+            // slots): the molecule is reported NOT_SPD and the sign iteration,
+            // finishing and extraction skip it, leaving its columns at zero
+            if (diverge || !stop) {
+                ctl->status = NOLSM_MOL_NOT_SPD;
+                ctl->done = 1;
+            }
         }
     }
     return (stop || diverge || last) ? IACT_STOP : IACT_UPDATE;

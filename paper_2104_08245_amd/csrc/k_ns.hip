@@ -59,7 +59,8 @@ __device__ int ns_decide(const NsArgs &na, const SubMeta &M, SubCtl *ctl, const 
         if (act == ACT_STOP) {
             ctl->iters = it;
             ctl->resid = r;
-            if (noconv) ctl->status = NOLSM_MOL_NOCONV;
+            // a status set earlier (NOT_SPD) is never overwritten
+            if (noconv && ctl->status == NOLSM_MOL_OK) ctl->status = NOLSM_MOL_NOCONV;
             ctl->done = 1;
         } else if (act == ACT_RESTART) {
             ctl->fallback = 1;

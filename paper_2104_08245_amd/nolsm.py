@@ -163,16 +163,26 @@ class Solver:
                                          C.c_void_p(self.ws.data_ptr()), out, C.c_void_p(st)))
         return out[0], out[1], int(out[2])
 
-    def mu_bisect(self, mu_lo, mu_hi, n_target, tol_count=0.5, max_steps=40, stream=None):
-        """Chemical potential with sum_J N_J = n_target (bisection on the GPU solves)."""
+    def mu_bisect(self, mu_lo, mu_hi, n_target, tol_count=0.5, max_steps=40, stream=None,
+                  allow_noconv=False):
+        """Chemical potential with sum_J N_J = n_target (bisection on the GPU
+        solves). Returns (mu, count, steps). The library reports E_NOCONV when
+        the count is not reached or some molecule of the final solve is not
+        OK; that raises unless allow_noconv, which then returns
+        (mu, count, steps, converged) with the last solve kept."""
         st = _stream_ptr(stream, self.device)
         mu, cnt, steps = C.c_double(), C.c_double(), C.c_int32()
-        L.check(L.lib().nolsm_mu_bisect(
+        rc = L.lib().nolsm_mu_bisect(
             self.plan.h, C.c_void_p(self.Kv.data_ptr()), C.c_void_p(self.Sv.data_ptr()), float(mu_lo),
             float(mu_hi), float(n_target), float(tol_count), int(max_steps), C.byref(self.opts),
             C.c_void_p(self.ws.data_ptr()), self.ws_bytes, C.c_void_p(self.Dcols.data_ptr()),
             C.c_void_p(self.D.data_ptr()), C.c_void_p(self.stats.data_ptr()), C.c_void_p(st),
-            C.byref(mu), C.byref(cnt), C.byref(steps)))
+            C.byref(mu), C.byref(cnt), C.byref(steps))
+        if allow_noconv:
+            if rc not in (L.NOLSM_OK, L.E_NOCONV):
+                L.check(rc)
+            return mu.value, cnt.value, steps.value, rc == L.NOLSM_OK
+        L.check(rc)
         return mu.value, cnt.value, steps.value
 
     def assemble(self, stream=None):

@@ -233,6 +233,29 @@ def build_system(centres, box, r_c, jitter_rng, onsite_rng, sample_rng=None, bas
                   K=Kc, S=Sc, mu=0.0, sample_rng=sample_rng)
 
 
+def truncate(csr, centres, box, r_cut):
+    """The blocks of `csr` whose molecule centres lie strictly closer than
+    r_cut (minimum image); diagonal blocks always stay. Values are copied."""
+    rows = np.repeat(np.arange(csr.nb), np.diff(csr.row_ptr))
+    cols = csr.col_idx.astype(np.int64)
+    d = min_image(centres[rows] - centres[cols], np.asarray(box, dtype=np.float64))
+    keep = (np.sqrt((d * d).sum(-1)) < r_cut) | (rows == cols)
+    row_ptr = np.zeros(csr.nb + 1, dtype=np.int64)
+    np.add.at(row_ptr, rows[keep] + 1, 1)
+    row_ptr = np.cumsum(row_ptr).astype(np.int32)
+    val = None if csr.val is None else np.ascontiguousarray(csr.val[keep])
+    return BlockCSR(csr.nb, csr.bs, row_ptr, csr.col_idx[keep].copy(), val)
+
+
+def two_cutoffs(system, r_k=None, r_s=None):
+    """The same system with K (or S) truncated at a smaller cutoff than the
+    other matrix, so that the two block patterns differ: with r_k < r_c the
+    pattern of S strictly contains that of K, with r_s < r_c the reverse."""
+    K = truncate(system.K, system.centres, system.box, r_k) if r_k is not None else system.K
+    S = truncate(system.S, system.centres, system.box, r_s) if r_s is not None else system.S
+    return dataclasses.replace(system, K=K, S=S)
+
+
 def cubic_box(nmol, density=DENSITY):
     L = (nmol / density) ** (1.0 / 3.0)
     return np.array([L, L, L])

@@ -78,6 +78,22 @@ def test_plan_equals_oracle_merge(L, box64):
     assert inf["sum_n3"] == pytest.approx(((6 * m) ** 3).sum())
 
 
+@pytest.mark.parametrize("kw", [dict(r_k=0.45), dict(r_s=0.45)])
+def test_plan_equals_oracle_merge_two_cutoffs(L, box64, kw):
+    # K and S truncated at different cutoffs: the plan's merge of the two
+    # generated patterns equals the oracle's, and N(J) is the larger pattern
+    import synth
+    from paper_2104_08245_amd import Plan
+    s = synth.two_cutoffs(box64, **kw)
+    p = Plan(s.K.nb, s.K.bs, s.K.row_ptr, s.K.col_idx, s.S.row_ptr, s.S.col_idx)
+    ex = p.export()
+    ref = o.plan_arrays(s.K.nb, s.K.row_ptr, s.K.col_idx, s.S.row_ptr, s.S.col_idx)
+    for k in ("sub_ptr", "sub_blk", "self_pos", "D_row_ptr", "D_col_idx", "scatter_pos"):
+        assert np.array_equal(ex[k], ref[k]), k
+    big = s.S if "r_k" in kw else s.K
+    assert np.array_equal(ex["sub_ptr"], big.row_ptr) and np.array_equal(ex["sub_blk"], big.col_idx)
+
+
 def _random_pair_patterns(rng, nb, pk, ps):
     def sym(p):
         A = rng.random((nb, nb)) < p

@@ -52,3 +52,25 @@ def test_slab_two_densities():
     assert (z[:600] < split).all() and (z[600:] >= split).all()
     m = np.diff(s.K.row_ptr)
     assert m[:600].mean() > 1.5 * m[600:].mean()
+
+
+def test_two_cutoffs_patterns_strictly_nested():
+    # K truncated at 0.45 nm inside S at 0.6 nm (and the reverse): every
+    # block of the smaller pattern is in the larger one with the same values,
+    # the larger one has blocks the smaller lacks, and both stay symmetric
+    import synth
+    from oracle import nolsm as o
+    base = synth.make_config(1)
+    for kw, small, big in ((dict(r_k=0.45), "K", "S"), (dict(r_s=0.45), "S", "K")):
+        s = synth.two_cutoffs(base, **kw)
+        a, b = getattr(s, small), getattr(s, big)
+        assert a.nnzb < b.nnzb
+        o.validate_pattern(a.nb, a.row_ptr, a.col_idx)
+        for I in range(a.nb):
+            ca = a.col_idx[a.row_ptr[I]:a.row_ptr[I + 1]]
+            cb = b.col_idx[b.row_ptr[I]:b.row_ptr[I + 1]]
+            assert set(ca.tolist()) <= set(cb.tolist())
+            full = getattr(base, small)
+            for k in range(a.row_ptr[I], a.row_ptr[I + 1]):
+                kf = o.find_block(full.row_ptr, full.col_idx, I, int(a.col_idx[k]))
+                assert np.array_equal(a.val[k], full.val[kf])

@@ -83,14 +83,25 @@ def test_cholesky_route_reports_no_inverse_iterations(torch, box64):
     assert np.all(sv.host_stats()["iters_inv"] == 0)
 
 
-def test_coupled_inverse_flags_indefinite_overlap(torch, box64):
+def test_coupled_inverse_flags_indefinite_overlap(torch, box64, ref1):
     # S_J with a negative pivot: the scaled iteration has an eigenvalue of
-    # c S_J below 0 and diverges, which marks the molecule NOT_SPD
+    # c S_J below 0 and diverges, which marks the molecule NOT_SPD: its sign
+    # iteration is skipped, its columns stay zero, its traces are zero, and
+    # the synchronous mode reports E_NOT_SPD (as on the Cholesky route)
+    from paper_2104_08245_amd import NolsmError, _lib as L
     sv = solve(box64, "fp16", debug_poison_mol=3)
     st = sv.host_stats()
-    assert st["status"][3] != 0
+    assert st["status"][3] == L.MOL_NOT_SPD
     ok = np.arange(box64.nmol) != 3
     assert np.all(st["status"][ok] == 0)
+    dc = sv.host_dcols()
+    assert np.all(dc[3] == 0)
+    assert st["trace_SD"][3] == 0 and st["energy_KD"][3] == 0
+    assert rel(dc[4], ref1.Dcols[4]) <= BOUNDS["fp16"]
+    sv.set_opts(sync_errors=1)
+    with pytest.raises(NolsmError) as e:
+        sv.run()
+    assert e.value.code == L.E_NOT_SPD
 
 
 def test_coupled_inverse_route_nonzero_mu(torch, box64):
