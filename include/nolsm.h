@@ -19,6 +19,8 @@
  *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
  *     device memory of the current device, owned by the caller. The library
  *     never allocates or frees device memory; the plan owns host memory only.
+ *     (The one device buffer of the library's own is the static workspace
+ *     array of nolsm_sign_batch_noalloc, loaded with the library's code.)
  *   - `stream` is a hipStream_t passed as void*. All device work is enqueued
  *     asynchronously on it; NULL means the legacy default stream.
  *   - Blocks are bs x bs doubles stored row-major, bs*bs contiguous values per
@@ -317,6 +319,29 @@ int nolsm_sign_batch(nolsm_plan *plan, const double *dK_val, const double *dS_va
                      double mu, const nolsm_solve_opts *opts, void *d_ws,
                      size_t ws_bytes, double *dDcols, double *dD_val,
                      nolsm_mol_stats *dstats, void *stream);
+
+/* Allocation-free variant of nolsm_sign_batch, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the workspace is a device array of the
+ * library, NOLSM_NOALLOC_WS_BYTES per GPU, held by every GPU the library runs
+ * on until the process ends. Same arguments and results as nolsm_sign_batch
+ * without d_ws / ws_bytes; the plan must be configured with
+ * ws_bytes <= NOLSM_NOALLOC_WS_BYTES (more chunks for a large batch) and bound
+ * on the current device. The kernels are launched directly on `stream` (never
+ * a graph of the library's), so the call may itself be captured by the
+ * caller. It calls no hipMalloc / hipFree and no allocating routine; the
+ * first call on a device looks up the array's address there.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (each call initialises what it reads): calls that overlap on one
+ * GPU (several streams or threads) race and must be serialised by the caller.
+ * Errors: as nolsm_sign_batch; E_WORKSPACE when the plan's workspace exceeds
+ * the array; E_ARG for the pipeline schedule, profile or sync_errors (each
+ * would create library streams, events or host buffers); E_STATE when the
+ * current device is not the plan's. */
+#define NOLSM_NOALLOC_WS_BYTES ((size_t)64 << 20)
+int nolsm_sign_batch_noalloc(nolsm_plan *plan, const double *dK_val, const double *dS_val,
+                             double mu, const nolsm_solve_opts *opts, double *dDcols,
+                             double *dD_val, nolsm_mol_stats *dstats, void *stream);
 
 /* Write-back (Sec. III-B.2; Fig. 2 h-i): D block (N(J)_a, J) <- rows
  * bs*a .. bs*a+bs-1 of molecule J's Dcols. dDcols and dD_val are device

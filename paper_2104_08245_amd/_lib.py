@@ -17,6 +17,7 @@ BOUNDS_GERSHGORIN, BOUNDS_LEARNED = 0, 1
 SCHED_GRAPH, SCHED_STREAM, SCHED_PER_BUCKET, SCHED_PERSISTENT, SCHED_PIPELINE = 0, 1, 2, 3, 4
 INV_CHOLESKY, INV_COUPLED_NS, INV_CHOLESKY_FP32 = 0, 1, 2
 PLAN_COMBINE = 1
+NOALLOC_WS_BYTES = 64 << 20   # NOLSM_NOALLOC_WS_BYTES
 MLP_NFEAT = 12
 MLP_NPARAM = 5122
 
@@ -78,7 +79,7 @@ EXPORTED = ["nolsm_default_opts", "nolsm_build_submatrices", "nolsm_plan_info", 
             "nolsm_plan_configure", "nolsm_plan_bind", "nolsm_sign_batch", "nolsm_assemble_D",
             "nolsm_plan_destroy", "nolsm_strerror", "nolsm_mlp_forward", "nolsm_mlp_loss_grad",
             "nolsm_mlp_adam", "nolsm_profile_last", "nolsm_trace_sums", "nolsm_mu_bisect",
-            "nolsm_plan_groups", "nolsm_switch_tol"]
+            "nolsm_plan_groups", "nolsm_switch_tol", "nolsm_sign_batch_noalloc"]
 
 _lib = None
 
@@ -104,6 +105,7 @@ def lib():
     L.nolsm_plan_configure.argtypes = [vp, C.POINTER(SolveOpts), sz, C.POINTER(sz)]
     L.nolsm_plan_bind.argtypes = [vp, vp, sz, vp]
     L.nolsm_sign_batch.argtypes = [vp, vp, vp, dbl, C.POINTER(SolveOpts), vp, sz, vp, vp, vp, vp]
+    L.nolsm_sign_batch_noalloc.argtypes = [vp, vp, vp, dbl, C.POINTER(SolveOpts), vp, vp, vp, vp]
     L.nolsm_assemble_D.argtypes = [vp, vp, vp, vp]
     L.nolsm_plan_destroy.argtypes = [vp]
     L.nolsm_plan_destroy.restype = None

@@ -11,6 +11,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -308,9 +309,10 @@ static bool same_opts(const nolsm_solve_opts &a, const nolsm_solve_opts &b) {
     return std::memcmp(&a, &b, sizeof(a)) == 0;
 }
 
-extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const double *dS_val, double mu,
-                                const nolsm_solve_opts *opts, void *d_ws, size_t ws_bytes, double *dDcols,
-                                double *dD_val, nolsm_mol_stats *dstats, void *stream) {
+// argument checks shared by the batch entry points
+static int check_batch(const nolsm_plan *pl, const double *dK_val, const double *dS_val,
+                       const nolsm_solve_opts *opts, const void *d_ws, size_t ws_bytes, const double *dDcols,
+                       const nolsm_mol_stats *dstats) {
     if (!pl || !dK_val || !dS_val || !opts || !d_ws || !dDcols || !dstats) {
         nolsm_set_last_error("sign_batch: null argument");
         return NOLSM_E_ARG;
@@ -342,22 +344,32 @@ extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const doub
     }
     if (ws_bytes < pl->ws_bytes) { nolsm_set_last_error("sign_batch: workspace smaller than configured"); return NOLSM_E_WORKSPACE; }
     if (((uintptr_t)d_ws) & 255) { nolsm_set_last_error("sign_batch: workspace must be 256-byte aligned"); return NOLSM_E_ARG; }
+    return NOLSM_OK;
+}
+
+// mu lives in the workspace header (outside any captured graph), so a
+// captured batch serves every mu; the pipeline's second region has a header
+// of its own
+static int write_headers(const nolsm_plan *pl, char *ws, double mu, hipStream_t st) {
+    hipError_t e = launch_set_header(ws, mu, st);
+    if (e != hipSuccess) return hip_fail(e, "header launch");
+    for (const HostChunk &ch : pl->chunks)
+        if (ch.base) {
+            e = launch_set_header(ws + ch.base, mu, st);
+            if (e != hipSuccess) return hip_fail(e, "header launch");
+            break;
+        }
+    return NOLSM_OK;
+}
+
+extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const double *dS_val, double mu,
+                                const nolsm_solve_opts *opts, void *d_ws, size_t ws_bytes, double *dDcols,
+                                double *dD_val, nolsm_mol_stats *dstats, void *stream) {
+    int rc = check_batch(pl, dK_val, dS_val, opts, d_ws, ws_bytes, dDcols, dstats);
+    if (rc != NOLSM_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     BatchArgs b{dK_val, dS_val, mu, opts, (char *)d_ws, dDcols, dD_val, (void *)dstats};
-    int rc;
-    // mu lives in the workspace header (outside any captured graph), so a
-    // captured batch serves every mu
-    {
-        hipError_t e = launch_set_header((char *)d_ws, mu, st);
-        if (e != hipSuccess) return hip_fail(e, "header launch");
-        // the pipeline's second region has a header of its own
-        for (const HostChunk &ch : pl->chunks)
-            if (ch.base) {
-                e = launch_set_header((char *)d_ws + ch.base, mu, st);
-                if (e != hipSuccess) return hip_fail(e, "header launch");
-                break;
-            }
-    }
+    if ((rc = write_headers(pl, (char *)d_ws, mu, st)) != NOLSM_OK) return rc;
     if (opts->profile) {
         PhaseEvents pe;
         pe.st = st;
@@ -428,6 +440,80 @@ extern "C" int nolsm_sign_batch(nolsm_plan *pl, const double *dK_val, const doub
         }
     }
     return NOLSM_OK;
+}
+
+// ------------------------------------------------- allocation-free variant
+// The workspace of nolsm_sign_batch_noalloc: a device array of the library.
+// Every GPU the library runs on holds its own copy, at its own address, from
+// the load of the library's code until the process ends. In host code the
+// name is a stand-in, not a device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) char scratch[NOLSM_NOALLOC_WS_BYTES];
+
+#define NOLSM_NOALLOC_MAX_DEVICES 64
+static std::mutex scratch_mu;
+static char *scratch_ptr[NOLSM_NOALLOC_MAX_DEVICES];
+
+// device address of `scratch` on device `dev`, looked up once per device with
+// that device current
+static int scratch_address(int dev, char **out) {
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "scratch symbol address");
+        if (!p || ((uintptr_t)p & 255)) {
+            nolsm_set_last_error("sign_batch_noalloc: scratch address not 256-byte aligned");
+            return NOLSM_E_HIP;
+        }
+        scratch_ptr[dev] = (char *)p;
+    }
+    *out = scratch_ptr[dev];
+    return NOLSM_OK;
+}
+
+extern "C" int nolsm_sign_batch_noalloc(nolsm_plan *pl, const double *dK_val, const double *dS_val, double mu,
+                                        const nolsm_solve_opts *opts, double *dDcols, double *dD_val,
+                                        nolsm_mol_stats *dstats, void *stream) {
+    if (!pl || !opts) {
+        nolsm_set_last_error("sign_batch_noalloc: null argument");
+        return NOLSM_E_ARG;
+    }
+    if (pl->configured && pl->ws_bytes > (size_t)NOLSM_NOALLOC_WS_BYTES) {
+        nolsm_set_last_error("sign_batch_noalloc: the plan is configured for a workspace of " +
+                             std::to_string((unsigned long long)pl->ws_bytes) + " bytes, above the " +
+                             std::to_string((unsigned long long)NOLSM_NOALLOC_WS_BYTES) +
+                             " bytes of the library's scratch array");
+        return NOLSM_E_WORKSPACE;
+    }
+    if (opts->sched == NOLSM_SCHED_PIPELINE || opts->profile || opts->sync_errors) {
+        nolsm_set_last_error("sign_batch_noalloc: launches directly on the call's stream only "
+                             "(no pipeline schedule, profile or sync_errors)");
+        return NOLSM_E_ARG;
+    }
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "current device");
+    if (dev < 0 || dev >= NOLSM_NOALLOC_MAX_DEVICES) {
+        nolsm_set_last_error("sign_batch_noalloc: device index out of range");
+        return NOLSM_E_ARG;
+    }
+    if (pl->bound && dev != pl->device) {
+        nolsm_set_last_error("sign_batch_noalloc: current device differs from the one the plan is bound on");
+        return NOLSM_E_STATE;
+    }
+    char *ws = nullptr;
+    int rc = scratch_address(dev, &ws);
+    if (rc != NOLSM_OK) return rc;
+    rc = check_batch(pl, dK_val, dS_val, opts, ws, (size_t)NOLSM_NOALLOC_WS_BYTES, dDcols, dstats);
+    if (rc != NOLSM_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    BatchArgs b{dK_val, dS_val, mu, opts, ws, dDcols, dD_val, (void *)dstats};
+    if ((rc = write_headers(pl, ws, mu, st)) != NOLSM_OK) return rc;
+    // every kernel initialises the workspace state it reads (control blocks,
+    // queue counters, residual partials) within the call, so contents left by
+    // an earlier call are never read
+    return enqueue(pl, b, st);
 }
 
 extern "C" int nolsm_trace_sums(const nolsm_plan *pl, const nolsm_mol_stats *dstats, void *d_ws,

@@ -155,6 +155,18 @@ class Solver:
             C.c_void_p(self.Dcols.data_ptr()), C.c_void_p(self.D.data_ptr() if scatter else None),
             C.c_void_p(self.stats.data_ptr()), C.c_void_p(st)))
 
+    def run_noalloc(self, mu=None, stream=None, scatter=True):
+        """nolsm_sign_batch_noalloc: the same solve with the library's static
+        workspace array instead of self.ws (the plan must be configured for
+        at most NOALLOC_WS_BYTES)."""
+        mu = self.mu if mu is None else mu
+        st = _stream_ptr(stream, self.device)
+        L.check(L.lib().nolsm_sign_batch_noalloc(
+            self.plan.h, C.c_void_p(self.Kv.data_ptr()), C.c_void_p(self.Sv.data_ptr()), float(mu),
+            C.byref(self.opts), C.c_void_p(self.Dcols.data_ptr()),
+            C.c_void_p(self.D.data_ptr() if scatter else None), C.c_void_p(self.stats.data_ptr()),
+            C.c_void_p(st)))
+
     def trace_sums(self, stream=None):
         """(sum_J N_J, sum_J E_J, #molecules not OK) of the last solve, FP64 on the GPU."""
         out = (C.c_double * 3)()

@@ -272,3 +272,25 @@ def test_switch_point_of_the_16bit_iteration(L):
     for prec in ("fp16", "bf16"):
         assert L.default_opts(prec).tol < 0
     assert L.default_opts("fp64").tol == 1e-10
+
+
+def test_noalloc_refuses_plans_beyond_its_array(L, box64):
+    # host-side checks of the allocation-free entry point, before any HIP call
+    import ctypes as C
+    from paper_2104_08245_amd import Plan
+    s = box64
+    p = Plan(s.K.nb, s.K.bs, s.K.row_ptr, s.K.col_idx)
+    opts = L.default_opts("fp16")
+    p.configure(opts, 1 << 30)
+    assert p.info()["nchunks"] == 1
+    rc = L.lib().nolsm_sign_batch_noalloc(p.h, None, None, 0.0, C.byref(opts), None, None, None, None)
+    assert rc == L.E_WORKSPACE
+    assert b"scratch array" in L.lib().nolsm_strerror(rc)
+    p.configure(opts, L.NOALLOC_WS_BYTES)
+    assert p.info()["nchunks"] >= 2
+    opts.sched = L.SCHED_PIPELINE
+    rc = L.lib().nolsm_sign_batch_noalloc(p.h, None, None, 0.0, C.byref(opts), None, None, None, None)
+    assert rc == L.E_ARG
+    src = open(HEADER).read()
+    m = re.search(r"#define NOLSM_NOALLOC_WS_BYTES \(\(size_t\)(\d+) << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == L.NOALLOC_WS_BYTES
