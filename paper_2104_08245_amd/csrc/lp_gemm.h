@@ -195,9 +195,13 @@ __device__ __forceinline__ void lp_tile_product(const uint16_t *Ag, const uint16
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         NS_GLOAD(p, kt + 1);   // past the last slice: zeros, no memory access
+        // the loads stay ahead of the products: without this fence (and with
+        // a conditional store) the compiler sinks them behind the MFMAs,
+        // next to their use, and every slice waits out the full load latency
+        __builtin_amdgcn_sched_barrier(0);
         NS_COMPUTE(0);
         __syncthreads();
-        if (kt + 1 < nk) NS_SSTORE(p, 0);
+        NS_SSTORE(p, 0);       // the last one stores zeros nothing reads
         __syncthreads();
     }
 #undef NS_BUF
