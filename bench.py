@@ -276,10 +276,12 @@ def main():
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB "
                          "(reference for the FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--inverse", default="auto", choices=["auto", "cholesky", "cholesky_fp32", "coupled_ns"],
-                    help="route to T_J(S)^-1: FP64 Cholesky, Cholesky with FP32 arithmetic "
-                         "(16-bit only; their default), or the coupled Newton-Schulz "
-                         "iteration in the NS precision (16-bit only)")
+    ap.add_argument("--inverse", default="auto",
+                    choices=["auto", "cholesky", "cholesky_apply_fp32", "cholesky_fp32", "coupled_ns"],
+                    help="route to T_J(S)^-1: FP64 Cholesky (the default of FP64/FP32), FP64 Cholesky "
+                         "applied through its FP32 copy with FP32 arithmetic (16-bit only; their "
+                         "default), Cholesky and substitution both in FP32 (16-bit only), or the "
+                         "coupled Newton-Schulz iteration in the NS precision (16-bit only)")
     ap.add_argument("--want-w", action="store_true",
                     help="also compute the energy-weighted density matrix columns each step")
     ap.add_argument("--sym", action=argparse.BooleanOptionalAction, default=True,
@@ -340,9 +342,9 @@ def main():
              "persistent": L.SCHED_PERSISTENT, "pipeline": L.SCHED_PIPELINE}[args.sched]
     dev = torch.device("cuda:0")
     if args.inverse == "auto":
-        args.inverse = "cholesky"
-    inv = {"cholesky": L.INV_CHOLESKY, "cholesky_fp32": L.INV_CHOLESKY_FP32,
-           "coupled_ns": L.INV_COUPLED_NS}[args.inverse]
+        args.inverse = "cholesky_apply_fp32" if args.prec in ("fp16", "bf16") else "cholesky"
+    inv = {"cholesky": L.INV_CHOLESKY, "cholesky_apply_fp32": L.INV_CHOLESKY_APPLY_FP32,
+           "cholesky_fp32": L.INV_CHOLESKY_FP32, "coupled_ns": L.INV_COUPLED_NS}[args.inverse]
     sym = 1 if (args.sym and args.prec in ("fp16", "bf16") and args.inverse != "coupled_ns"
                 and not args.want_w) else 0
     sv = Solver(system, prec=args.prec, device=dev, ws_budget=int(args.ws_gb * (1 << 30)), sched=sched,
@@ -414,6 +416,10 @@ def main():
         terms["inverse"] = inv_flops / (peak * 1e12)
     elif args.inverse == "cholesky_fp32":
         terms["setup_fp32"] = setup_flops / 157.3e12
+    elif args.inverse == "cholesky_apply_fp32":
+        chol_flops = float((n ** 3 / 3.0).sum())
+        terms["setup_fp64_factor"] = chol_flops / 78.6e12
+        terms["setup_fp32_apply"] = (setup_flops - chol_flops) / 157.3e12
     else:
         terms["setup_fp64"] = setup_flops / 78.6e12
     t_bound = sum(terms.values())

@@ -128,12 +128,23 @@ typedef enum {
                                       within inv_max_iter, marks the molecule
                                       NOT_SPD (no inverse: its columns stay
                                       zero and its sign iteration is skipped). */
-    NOLSM_INV_CHOLESKY_FP32 = 2    /* FP16/BF16 only: the same
+    NOLSM_INV_CHOLESKY_FP32 = 2,   /* FP16/BF16 only: the same
                                       Cholesky factor and substitution with FP32
                                       arithmetic on the matrix cores, FP64
                                       storage; its relative error, about
                                       kappa(S_J) 2^-24, stays far below the
                                       16-bit floor of the sign iteration.      */
+    NOLSM_INV_CHOLESKY_APPLY_FP32 = 3  /* FP16/BF16 only: the FP64 Cholesky
+                                      factor (FP64 pivots and NOT_SPD test), also
+                                      stored in FP32 with its diagonal-tile
+                                      inverses; the substitutions that form A_J
+                                      (or L^-1 T_J(K) L^-T) and the E columns
+                                      apply that FP32 copy with FP32 arithmetic
+                                      on the matrix cores (twice the FP64 matrix
+                                      rate), FP64 storage; the owned columns are
+                                      taken back through the FP64 factor. Error
+                                      of the application about kappa(S_J) 2^-24,
+                                      far below the 16-bit floor.              */
 } nolsm_inverse;
 
 typedef struct {

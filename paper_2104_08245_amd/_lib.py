@@ -15,7 +15,7 @@ FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
 BOUNDS_GERSHGORIN, BOUNDS_LEARNED = 0, 1
 SCHED_GRAPH, SCHED_STREAM, SCHED_PER_BUCKET, SCHED_PERSISTENT, SCHED_PIPELINE = 0, 1, 2, 3, 4
-INV_CHOLESKY, INV_COUPLED_NS, INV_CHOLESKY_FP32 = 0, 1, 2
+INV_CHOLESKY, INV_COUPLED_NS, INV_CHOLESKY_FP32, INV_CHOLESKY_APPLY_FP32 = 0, 1, 2, 3
 PLAN_COMBINE = 1
 NOALLOC_WS_BYTES = 64 << 20   # NOLSM_NOALLOC_WS_BYTES
 MLP_NFEAT = 12

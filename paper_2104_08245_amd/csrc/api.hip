@@ -203,7 +203,10 @@ static int enqueue_setup(const nolsm_plan *pl, const BatchArgs &b, const LaunchA
     hipError_t e;
     if (prof) prof->mark(PH_GATHER);
     if ((e = launch_gather(cd, ws, A.ga, st)) != hipSuccess) return hip_fail(e, "gather launch");
+    // the FP32 route factors and applies in FP32; the mixed one factors in
+    // FP64 and applies the FP32 copy of the factor
     const bool fp32 = o.inverse == NOLSM_INV_CHOLESKY_FP32;
+    const bool apply32 = fp32 || o.inverse == NOLSM_INV_CHOLESKY_APPLY_FP32;
     if (o.inverse == NOLSM_INV_COUPLED_NS) {
         if (prof) prof->mark(PH_INV);
         if ((e = launch_inverse(cd, ws, A.ia, st)) != hipSuccess) return hip_fail(e, "inverse launch");
@@ -211,7 +214,7 @@ static int enqueue_setup(const nolsm_plan *pl, const BatchArgs &b, const LaunchA
         if (prof) prof->mark(PH_CHOL);
         if ((e = launch_chol(cd, ws, fp32, st)) != hipSuccess) return hip_fail(e, "Cholesky launch");
         if (prof) prof->mark(PH_SUBST);
-        e = o.sym_sign ? launch_subst_sym(cd, ws, fp32, st) : launch_subst(cd, ws, fp32, st);
+        e = o.sym_sign ? launch_subst_sym(cd, ws, apply32, st) : launch_subst(cd, ws, apply32, st);
         if (e != hipSuccess) return hip_fail(e, "substitution launch");
     }
     if (prof) prof->mark(PH_BOUNDS);

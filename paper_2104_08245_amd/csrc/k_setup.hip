@@ -173,7 +173,7 @@ template <typename T> __device__ void potrf64_reg(T (*D)[LDP], T (*cb)[64], int 
 // diagonal stay exact zeros. The result goes straight from registers to the
 // global 64x64 row-major Dg (row r of a wave's lanes is 512 contiguous
 // bytes). rd: 64 values of LDS, xb: 2 x 64.
-template <typename T> __device__ void trinv64_reg(const T (*Lt)[LDP], T *Dg, T *rd, T (*xb)[64]) {
+template <typename T> __device__ void trinv64_reg(const T (*Lt)[LDP], T *Dg, T *rd, T (*xb)[64], float *Df = nullptr) {
     const int t = threadIdx.x, c = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
     if (t < 64) rd[t] = (T)1 / Lt[t][t];
     T b[16];
@@ -201,6 +201,9 @@ template <typename T> __device__ void trinv64_reg(const T (*Lt)[LDP], T *Dg, T *
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) Dg[(w + 4 * i) * 64 + c] = b[i];
+    if (Df)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Df[(w + 4 * i) * 64 + c] = (float)b[i];
 }
 
 // Panel j, diagonal tile: L_jj L_jj^T = S_jj - sum_{k<j} L_jk L_jk^T, and
@@ -239,8 +242,12 @@ __global__ __launch_bounds__(256, 3) void k_chol_diag(ChunkDev cd, char *ws, int
         if (threadIdx.x == 0) { ctl->status = NOLSM_MOL_NOT_SPD; ctl->done = 1; }
         return;
     }
-    trinv64_reg(sA, Dinv + (int64_t)j * 4096, rd, cb);
+    // FP64 factor applied in FP32: the tile and its inverse also in FP32
+    float *L32 = M.offL32 ? (float *)(ws + M.offL32) : nullptr;
+    float *D32 = M.offDinv32 ? (float *)(ws + M.offDinv32) + (int64_t)j * 4096 : nullptr;
+    trinv64_reg(sA, Dinv + (int64_t)j * 4096, rd, cb, D32);
     s2g_tile(Lt(j, j), ld, sA);
+    if (L32) s2g_tile(L32 + (int64_t)(j * 64) * ld + j * 64, ld, sA);
 }
 
 // Panel j below the diagonal: L_ij = (S_ij - sum_{k<j} L_ik L_jk^T) L_jj^-T
@@ -290,6 +297,7 @@ __global__ __launch_bounds__(256, OCC) void k_chol_panel(ChunkDev cd, char *ws, 
             acc2s(sA, o);
             __syncthreads();
             s2g_tile(Lt(i0 + r, j), ld, sA);
+            if (M.offL32) s2g_tile((float *)(ws + M.offL32) + (int64_t)((i0 + r) * 64) * ld + j * 64, ld, sA);
             __syncthreads();
         }
     }
@@ -323,8 +331,10 @@ __global__ __launch_bounds__(256, OCC) void k_subst(ChunkDev cd, char *ws) {
     const int P = M.P, np = M.np, n = M.n;
     const int nc = min(SC, P + 1 - cc);   // column tiles of this task
     const int64_t ldl = np, ldk = np + 64;
-    const T *L = (const T *)(ws + M.offL);
-    const T *Dinv = (const T *)(ws + M.offDinv);
+    // FP32 arithmetic reads the FP32 copy of an FP64 factor when there is one
+    const bool l32 = sizeof(T) == 4 && M.offL32;
+    const T *L = (const T *)(ws + (l32 ? M.offL32 : M.offL));
+    const T *Dinv = (const T *)(ws + (l32 ? M.offDinv32 : M.offDinv));
     double *Kb = (double *)(ws + M.offK);
     auto Lt = [&](int r, int c) { return L + (int64_t)(r * 64) * ldl + c * 64; };
     auto Bt = [&](int c, int r) {   // row tile r of this task's column c
@@ -564,8 +574,10 @@ __global__ __launch_bounds__(256, OCC) void k_rsolve(ChunkDev cd, char *ws, int 
     const int P = M.P, np = M.np, n = M.n;
     if (i >= P) return;
     const int64_t ldl = np, ldk = np + 64;
-    const T *L = (const T *)(ws + M.offL);
-    const T *Dinv = (const T *)(ws + M.offDinv);
+    // FP32 arithmetic reads the FP32 copy of an FP64 factor when there is one
+    const bool l32 = sizeof(T) == 4 && M.offL32;
+    const T *L = (const T *)(ws + (l32 ? M.offL32 : M.offL));
+    const T *Dinv = (const T *)(ws + (l32 ? M.offDinv32 : M.offDinv));
     double *Kb = (double *)(ws + M.offK);
     auto Lt = [&](int r, int c) { return L + (int64_t)(r * 64) * ldl + c * 64; };
     auto Xt = [&](int j) { return Kb + (int64_t)(i * 64) * ldk + j * 64; };   // tile (i, j)

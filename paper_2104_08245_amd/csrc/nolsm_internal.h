@@ -40,6 +40,11 @@ struct SubMeta {
     // coupled Newton-Schulz inverse only (0 otherwise): ldx*ldx elements each
     int64_t offY0, offY1;   // Y_k ping-pong; after convergence S^-1 and K in 16 bits
     int64_t offZ0, offZ1;   // Z_k ping-pong
+    // FP64 factor applied in FP32 only (0 otherwise): FP32 copies of L
+    // (np*np, tiles on and below the diagonal) and of the diagonal-tile
+    // inverses (P*64*64), written by the FP64 Cholesky, read by the
+    // substitutions
+    int64_t offL32, offDinv32;
 };
 
 // Per-slot control state, written by kernels only.

@@ -75,6 +75,8 @@ size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_i
     b += align256((size_t)max_iter * nt * nt * 8);  // residual partials
     if (inverse == NOLSM_INV_COUPLED_NS) b += 4 * align256(ldx * ldx * (size_t)elem);  // Y, Z ping-pong
     if (sym) b += align256(ldx * ldx * (size_t)elem);   // X0 beside L (kept to the end)
+    if (inverse == NOLSM_INV_CHOLESKY_APPLY_FP32)         // FP32 copies of L and Dinv
+        b += align256(n * n * 4) + align256(P * 64 * 64 * 4);
     return b;
 }
 
@@ -405,9 +407,10 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
     if (opts->prec < NOLSM_FP64 || opts->prec > NOLSM_BF16) { nolsm_set_last_error("bad precision"); return NOLSM_E_ARG; }
     if (opts->max_iter < 2 || opts->max_iter > NOLSM_MAX_ITER_CAP) { nolsm_set_last_error("max_iter must be 2..128"); return NOLSM_E_ARG; }
     if (opts->sched < NOLSM_SCHED_GRAPH || opts->sched > NOLSM_SCHED_PIPELINE) { nolsm_set_last_error("bad schedule"); return NOLSM_E_ARG; }
-    if (opts->inverse < NOLSM_INV_CHOLESKY || opts->inverse > NOLSM_INV_CHOLESKY_FP32) { nolsm_set_last_error("bad inverse"); return NOLSM_E_ARG; }
-    if (opts->inverse == NOLSM_INV_CHOLESKY_FP32 && opts->prec != NOLSM_FP16 && opts->prec != NOLSM_BF16) {
-        nolsm_set_last_error("the FP32 Cholesky route serves the FP16/BF16 sign iterations only");
+    if (opts->inverse < NOLSM_INV_CHOLESKY || opts->inverse > NOLSM_INV_CHOLESKY_APPLY_FP32) { nolsm_set_last_error("bad inverse"); return NOLSM_E_ARG; }
+    if ((opts->inverse == NOLSM_INV_CHOLESKY_FP32 || opts->inverse == NOLSM_INV_CHOLESKY_APPLY_FP32) &&
+        opts->prec != NOLSM_FP16 && opts->prec != NOLSM_BF16) {
+        nolsm_set_last_error("the FP32 Cholesky routes serve the FP16/BF16 sign iterations only");
         return NOLSM_E_ARG;
     }
     if (opts->sym_sign && ((opts->prec != NOLSM_FP16 && opts->prec != NOLSM_BF16) ||
@@ -547,6 +550,10 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
                     m.offY1 = (int64_t)off; off += align256(ldx * ldx * pl->elem);
                     m.offZ0 = (int64_t)off; off += align256(ldx * ldx * pl->elem);
                     m.offZ1 = (int64_t)off; off += align256(ldx * ldx * pl->elem);
+                }
+                if (pl->inverse == NOLSM_INV_CHOLESKY_APPLY_FP32) {
+                    m.offL32 = (int64_t)off; off += align256(n * n * 4);
+                    m.offDinv32 = (int64_t)off; off += align256((size_t)m.P * 4096 * 4);
                 }
                 ch.meta.push_back(m);
                 ch.max_m = std::max(ch.max_m, m.m);

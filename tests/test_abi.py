@@ -165,6 +165,8 @@ def test_bad_options_rejected(L, box64):
     for kw in (dict(prec=7), dict(max_iter=1), dict(max_iter=500), dict(sched=9), dict(inverse=5),
                dict(inverse=L.INV_COUPLED_NS),                       # FP64: 16-bit route only
                dict(inverse=L.INV_CHOLESKY_FP32),                    # FP64: 16-bit route only
+               dict(inverse=L.INV_CHOLESKY_APPLY_FP32),              # FP64: 16-bit route only
+               dict(inverse=4),
                dict(prec=L.PREC["fp32"], inverse=L.INV_CHOLESKY_FP32),
                dict(sym_sign=1),                                     # FP64: 16-bit only
                dict(prec=L.PREC["fp16"], sym_sign=1, inverse=L.INV_COUPLED_NS),

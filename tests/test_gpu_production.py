@@ -2,8 +2,9 @@
 differ, against the CPU oracle through the C ABI.
 
 The bench runs the 16-bit sign iteration on the symmetric similar matrix
-(sym_sign), FP64 Cholesky, the graph schedule on a side stream and several
-chunks of submatrices with n_J 516-708. The 4,096-molecule cube at r_c 0.9 nm
+(sym_sign), the FP64 Cholesky factor applied through its FP32 copy, the
+graph schedule on a side stream and several chunks of submatrices with n_J
+516-708. The 4,096-molecule cube at r_c 0.9 nm
 has the same submatrix sizes (n_J 534-696: 5-6 NS tile rows of 128 with the
 mirrored off-diagonal tiles, 9-11 row blocks of the right solve), so it is
 solved here exactly as the bench solves its batch, and a seeded sample of
@@ -94,7 +95,7 @@ def full_workspace(system, **kw):
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_bench_path_at_production_size(torch, cube, sample, ref, prec):
     from paper_2104_08245_amd import Solver, _lib as L
-    kw = dict(prec=prec, sym_sign=1, inverse=L.INV_CHOLESKY, sched=L.SCHED_GRAPH)
+    kw = dict(prec=prec, sym_sign=1, inverse=L.INV_CHOLESKY_APPLY_FP32, sched=L.SCHED_GRAPH)
     ws = full_workspace(cube, **kw) // 3 + (1 << 20)
     sv = Solver(cube, device="cuda:0", ws_bytes=ws, **kw)
     inf = sv.plan.info()

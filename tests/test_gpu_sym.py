@@ -86,6 +86,31 @@ def test_symmetric_on_fp32_factor(torch, box64, ref1):
                 "fp16 symmetric, FP32 factor")
 
 
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_symmetric_on_fp64_factor_applied_in_fp32(torch, box64, ref1, prec):
+    from paper_2104_08245_amd import _lib as L
+    check_mixed(solve(box64, prec, inverse=L.INV_CHOLESKY_APPLY_FP32), ref1, box64.nmol, prec,
+                f"{prec} symmetric, FP64 factor applied in FP32")
+
+
+def test_fp64_factor_applied_in_fp32_outside_spectrum(torch, box64):
+    # sign = -I above the spectrum: Dcols = S_J^-1 E_cJ, formed through the
+    # FP32 copy of the factor (y = L^-1 E) and the FP64 factor (L^-T); the
+    # FP32 application costs about kappa(L) 2^-24 relative
+    from paper_2104_08245_amd import _lib as L
+    Js = list(range(0, box64.nmol, 7))
+    hi = o.nolsm(box64, mu=50.0, molecules=Js)
+    for sym in (1, 0):
+        from paper_2104_08245_amd import Solver
+        sv = Solver(box64, prec="fp16", device="cuda:0", sym_sign=sym, inverse=L.INV_CHOLESKY_APPLY_FP32)
+        sv.run(mu=50.0)
+        torch.cuda.synchronize()
+        dc = sv.host_dcols()
+        worst = max(rel(dc[J], hi.Dcols[J]) for J in Js)
+        say(f"FP64 factor applied in FP32, sym={sym}, mu=50: worst rel-F {worst:.3e}")
+        assert worst <= 1e-5
+
+
 def test_symmetric_nonzero_mu(torch, box64):
     ref = o.nolsm(box64, mu=0.25)
     check_mixed(solve(box64, "fp16", mu=0.25), ref, box64.nmol, "fp16", "fp16 symmetric mu=0.25")
