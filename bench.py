@@ -209,7 +209,12 @@ def bounds_eval(args):
     from paper_2104_08245_amd import learned
 
     dev = torch.device("cuda:0")
-    ts = np.load(os.path.join(ROOT, "tests", "golden", "mlp_train.npz"))
+    # the default path iterates on L^-1 K L^-T - mu I (FP64 factor applied in
+    # FP32): its network is trained on that matrix's features; --no-sym
+    # evaluates the iteration on A_J with the network of A_J's features
+    sym = args.sym
+    path = dict(sym_sign=1, inverse=L.INV_CHOLESKY_APPLY_FP32) if sym else {}
+    ts = np.load(os.path.join(ROOT, "tests", "golden", "mlp_train_sym.npz" if sym else "mlp_train.npz"))
     t0 = time.perf_counter()
     tr = learned.train(ts["features"], ts["labels"], epochs=200, device=dev)
     torch.cuda.synchronize()
@@ -229,7 +234,7 @@ def bounds_eval(args):
             if mode == "learned":
                 kw = dict(bounds=L.BOUNDS_LEARNED, d_mlp=tr["params"].data_ptr(),
                           d_mlp_norm=tr["norm"].data_ptr())
-            sv = Solver(sysf, prec="fp16", device=dev, **kw)
+            sv = Solver(sysf, prec="fp16", device=dev, **path, **kw)
             sv.run()
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -246,7 +251,9 @@ def bounds_eval(args):
     out = {"metric": "NS iterations per submatrix, learned vs Gershgorin bounds",
            "data": "synthetic", "dtype": "f16",
            "config": {"workload": "10-frame water-like trajectory, 4096 molecules, r_c 0.9 nm",
-                      "frames": len(frames), "molecules": frames[0].nmol}}
+                      "frames": len(frames), "molecules": frames[0].nmol,
+                      "iteration_on": "L^-1 K L^-T - mu I (FP64 factor applied in FP32)" if sym
+                      else "A = S^-1 K - mu I"}}
     for mode, (its, fb, dE) in res.items():
         its = np.concatenate(its)
         dE = np.concatenate(dE)

@@ -170,7 +170,8 @@ typedef struct {
     float mlp_safety;        /* c_J = 1/(safety * rho_hat); default 1.05         */
     int32_t sched;           /* nolsm_sched                                      */
     int32_t sync_errors;     /* != 0: synchronize and return E_NOT_SPD/E_NOCONV  */
-    float *d_features;       /* optional device [nb][12] float: features of A_J  */
+    float *d_features;       /* optional device [nb][12] float: features of A_J
+                                (of L^-1 T_J(K) L^-T - mu I with sym_sign)       */
     double debug_scale_mult; /* != 0: multiply c_J (tests of the restart guard)  */
     int32_t debug_poison_mol;/* >= 0: molecule whose S_J pivot is forced <= 0    */
     int32_t profile;         /* != 0: launch directly (no graph), time each phase
@@ -197,9 +198,11 @@ typedef struct {
                                 sign(A_J) = L^-T sign(.) L^T), so each GEMM
                                 computes its upper tiles only and mirrors
                                 them; the owned columns are L^-T (y - sign(.) y)
-                                / 2 with y = L^-1 E_cJ, the same D. Not with
-                                d_wcols, d_features or learned bounds (defined
-                                on A_J). Default 0; used by configure.         */
+                                / 2 with y = L^-1 E_cJ, the same D. The
+                                features (d_features) and the learned bounds are
+                                then those of that symmetric matrix (a network
+                                trained on its features). Not with d_wcols.
+                                Default 0; used by configure.                  */
     int32_t reserved_;       /* 0                                                */
 } nolsm_solve_opts;
 

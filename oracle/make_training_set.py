@@ -6,6 +6,9 @@ evaluation system. Calls only the oracle and the input generator.
 
 TEST INFRASTRUCTURE (oracle side): run as
     python -m oracle.make_training_set [N] [out.npz] [processes]
+or, for the features of the symmetric similar matrix L^-1 K_J L^-T - mu I
+of the same submatrices (labels copied):
+    python -m oracle.make_training_set --sym [processes]
 """
 from __future__ import annotations
 
@@ -55,6 +58,51 @@ def one(J):
     return J, f, lo, hi, KJ.shape[0]
 
 
+def one_sym(J):
+    # the same submatrix, features of A~ = L^-1 K_J L^-T - mu I instead of A_J
+    s = _SYS
+    lists, self_pos = o.neighbour_lists(s)
+    idx = lists[J]
+    KJ = o.gather_vectorized(idx, 6, s.K.row_ptr, s.K.col_idx, s.K.val)
+    SJ = o.gather_vectorized(idx, 6, s.S.row_ptr, s.S.col_idx, s.S.val)
+    return J, mlp.features_symmetric(KJ, SJ, s.mu), KJ.shape[0]
+
+
+def main_sym(src=None, out=None, procs=None):
+    """Features of A~ for exactly the submatrices of the A_J set (same
+    generators, seeds and draws, same order); the labels (extreme eigenvalues
+    of the pencil, shared by A_J and A~) are copied from that set."""
+    global _SYS
+    src = src or os.path.join(ROOT, "tests", "golden", "mlp_train.npz")
+    out = out or os.path.join(ROOT, "tests", "golden", "mlp_train_sym.npz")
+    procs = procs or min(8, os.cpu_count() or 1)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    base = np.load(src)
+    total = len(base["labels"])
+    F, N = [], []
+    for si, (kind, cid, share) in enumerate(SOURCES):
+        t = time.time()
+        s = make(kind, cid)
+        o.neighbour_lists(s)
+        _SYS = s
+        rng = np.random.default_rng(cid)
+        cnt = min(int(round(total * share)), s.nmol)
+        Js = sorted(rng.choice(s.nmol, cnt, replace=False).tolist())
+        with mp.get_context("fork").Pool(procs, initializer=_single_thread) as pool:
+            res = pool.map(one_sym, Js, chunksize=8)
+        for J, f, n in res:
+            F.append(f)
+            N.append(n)
+        print(f"{kind} seed {cid}: {cnt} submatrices in {time.time() - t:.0f}s", flush=True)
+    N = np.array(N, np.int32)
+    if not np.array_equal(N, base["n"]):
+        raise RuntimeError("regenerated submatrices differ from the A_J set")
+    np.savez_compressed(out, features=np.array(F, np.float64), labels=base["labels"], n=N,
+                        source=base["source"])
+    print("wrote", out, len(F))
+
+
 def main(total=20000, out=None, procs=None):
     global _SYS
     out = out or os.path.join(ROOT, "tests", "golden", "mlp_train.npz")
@@ -85,4 +133,7 @@ def main(total=20000, out=None, procs=None):
 
 if __name__ == "__main__":
     a = sys.argv[1:]
-    main(int(a[0]) if a else 20000, a[1] if len(a) > 1 else None, int(a[2]) if len(a) > 2 else None)
+    if a and a[0] == "--sym":
+        main_sym(procs=int(a[1]) if len(a) > 1 else None)
+    else:
+        main(int(a[0]) if a else 20000, a[1] if len(a) > 1 else None, int(a[2]) if len(a) > 2 else None)

@@ -127,6 +127,22 @@ def features(A):
                      np.linalg.norm(A) / np.sqrt(n)])
 
 
+def symmetric_similar(KJ, SJ, mu):
+    """A~ = L^-1 K_J L^-T - mu I with S_J = L L^T (lower Cholesky factor):
+    similar to A_J = S_J^-1 K_J - mu I (A_J = L^-T A~ L^T), so the same
+    spectrum, and symmetric. The symmetric sign iteration runs on it; its
+    features are those of this matrix."""
+    L = sla.cholesky(SJ, lower=True)
+    W = sla.solve_triangular(L, KJ, lower=True)            # L^-1 K
+    At = sla.solve_triangular(L, W.T, lower=True).T       # (L^-1 (L^-1 K)^T)^T = L^-1 K L^-T
+    return At - mu * np.eye(KJ.shape[0])
+
+
+def features_symmetric(KJ, SJ, mu):
+    """The 12 features of A~ (symmetric_similar)."""
+    return features(symmetric_similar(KJ, SJ, mu))
+
+
 def gershgorin_box(f):
     """Intersection of the row and column Gershgorin intervals from a feature
     vector: (G_lo, G_hi)."""

@@ -332,9 +332,8 @@ static int check_batch(const nolsm_plan *pl, const double *dK_val, const double 
         nolsm_set_last_error("sign_batch: the energy-weighted output needs an even block size");
         return NOLSM_E_ARG;
     }
-    if (opts->sym_sign && (opts->d_wcols || opts->d_features || opts->bounds == NOLSM_BOUNDS_LEARNED)) {
-        nolsm_set_last_error("sign_batch: W, features and learned bounds are defined on A_J: "
-                             "they need sym_sign = 0");
+    if (opts->sym_sign && opts->d_wcols) {
+        nolsm_set_last_error("sign_batch: the energy-weighted output is formed from A_J: it needs sym_sign = 0");
         return NOLSM_E_ARG;
     }
     if (opts->bounds == NOLSM_BOUNDS_LEARNED && (!opts->d_mlp || !opts->d_mlp_norm)) {

@@ -80,3 +80,71 @@ def test_learned_bounds_save_iterations_on_trajectory(trained):
     g, l = res["gershgorin"], res["learned"]
     assert l[0].mean() < g[0].mean()
     assert l[2].max() <= max(2.0 * g[2].max(), 1e-3)
+
+
+# ------------------------------------------------ the symmetric (bench) path
+DATA_SYM = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "mlp_train_sym.npz")
+
+
+@pytest.mark.parametrize("inverse", ["cholesky", "cholesky_apply_fp32"])
+def test_features_of_symmetric_matrix_match_oracle(box64, inverse):
+    # with sym_sign the features are those of A~ = L^-1 K_J L^-T - mu I
+    import torch
+    from oracle import mlp
+    from paper_2104_08245_amd import Solver, _lib as L
+    inv = {"cholesky": L.INV_CHOLESKY, "cholesky_apply_fp32": L.INV_CHOLESKY_APPLY_FP32}[inverse]
+    mu = 0.05
+    sv = Solver(box64, prec="fp16", device="cuda:0", sym_sign=1, inverse=inv)
+    sv.want_features()
+    sv.run(mu=mu)
+    torch.cuda.synchronize()
+    f = sv.features.cpu().numpy().reshape(box64.nmol, 12)
+    # FP64 application: to the FP32 rounding of the features; FP32
+    # application: kappa(L) 2^-24 on A~ itself
+    tol = 1e-5 if inverse == "cholesky" else 1e-4
+    for J in (2, 40, 63):
+        KJ, SJ, idx, p = o.submatrix(box64, J)
+        ref = mlp.features_symmetric(KJ, SJ, mu)
+        assert np.allclose(f[J], ref, rtol=tol, atol=tol), (J, f[J], ref)
+
+
+@pytest.fixture(scope="module")
+def trained_sym():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2104_08245_amd import learned
+    d = np.load(DATA_SYM)
+    say(f"[gpu] training MLP on the symmetric-matrix features of {len(d['features'])} submatrices")
+    return learned.train(d["features"], d["labels"], epochs=60, log=say)
+
+
+def test_learned_bounds_on_symmetric_path_save_iterations(trained_sym):
+    # the benchmarked path: symmetric iteration, FP64 factor applied in FP32
+    import torch
+    from paper_2104_08245_amd import Solver, _lib as L
+    frames = synth.trajectory(nframes=2)
+    res = {}
+    for mode in ("gershgorin", "learned"):
+        its, fb, dEs = [], 0, []
+        for f, s in enumerate(frames):
+            kw = dict(sym_sign=1, inverse=L.INV_CHOLESKY_APPLY_FP32)
+            if mode == "learned":
+                kw.update(bounds=L.BOUNDS_LEARNED, d_mlp=trained_sym["params"].data_ptr(),
+                          d_mlp_norm=trained_sym["norm"].data_ptr())
+            say(f"[gpu] symmetric frame {f} {mode}")
+            sv = Solver(s, prec="fp16", **kw)
+            sv.run()
+            torch.cuda.synchronize()
+            st = sv.host_stats()
+            assert np.all(st["status"] == 0)
+            its.append(st["iters"])
+            fb += int(st["fallback"].sum())
+            for J in (5, 1000, 3000):
+                r = o.solve_molecule(s, J)
+                dEs.append(abs(st["energy_KD"][J] - r.E_J))
+        res[mode] = (np.concatenate(its), fb, np.array(dEs))
+        say(f"symmetric {mode}: mean iters {res[mode][0].mean():.3f}, fallbacks {fb}, "
+            f"max |dE| {res[mode][2].max():.2e}")
+    g, l = res["gershgorin"], res["learned"]
+    assert l[0].mean() < g[0].mean()
+    assert l[2].max() <= max(2.0 * g[2].max(), 1e-3)

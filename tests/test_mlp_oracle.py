@@ -59,3 +59,29 @@ def test_scale_never_below_gershgorin():
     assert mlp.scale_from_prediction(f, np.array([10.0, 10.0])) == 1.0 / 2.5
     c = mlp.scale_from_prediction(f, np.array([0.5, 0.5]))
     assert np.isclose(c, 1.0 / (1.05 * 1.25))
+
+
+def test_symmetric_similar_matrix_and_its_features():
+    # A~ = L^-1 K L^-T - mu I on a submatrix of the 64-molecule box: symmetric,
+    # with the spectrum of A_J (the generalized eigenvalues of (K - mu S, S)),
+    # enclosed by its Gershgorin box; its row and column radii coincide, and
+    # a planted transposition (L^-T K L^-1) breaks the spectrum check
+    import synth
+    from oracle import nolsm as o
+    s = synth.make_config(1)
+    mu = 0.1
+    for J in (0, 17, 63):
+        KJ, SJ, idx, p = o.submatrix(s, J)
+        At = mlp.symmetric_similar(KJ, SJ, mu)
+        ref = sla.eigh(KJ - mu * SJ, SJ, eigvals_only=True)
+        assert np.abs(At - At.T).max() <= 1e-12 * np.abs(At).max()
+        ev = np.linalg.eigvalsh((At + At.T) / 2)
+        assert np.abs(ev - ref).max() <= 1e-10 * np.abs(ref).max()
+        f = mlp.features_symmetric(KJ, SJ, mu)
+        assert np.allclose(f[7:9], f[9:11], rtol=1e-12, atol=1e-12)
+        glo, ghi = mlp.gershgorin_box(f)
+        assert glo <= ref.min() + 1e-12 and ref.max() <= ghi + 1e-12
+        assert abs(f[1] - np.trace(At) / At.shape[0]) <= 1e-12 * np.abs(At).max()
+        L = sla.cholesky(SJ, lower=True)
+        wrong = sla.solve_triangular(L.T, sla.solve_triangular(L.T, KJ, lower=False).T, lower=False)
+        assert np.abs(np.linalg.eigvalsh((wrong + wrong.T) / 2) - mu - ref).max() > 1e-6
