@@ -47,7 +47,8 @@ def log(*a):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ns_lp_fp16_cube32768_traffic.md")
-NS_SOURCE = os.path.join(ROOT, "paper_2104_08245_amd", "csrc", "k_ns.hip")
+# the sign-iteration kernel and its shared tile loop
+NS_SOURCES = [os.path.join(ROOT, "paper_2104_08245_amd", "csrc", f) for f in ("k_ns.hip", "lp_gemm.h")]
 
 
 def measured_traffic(config, prec, sym, mean_iters, combine):
@@ -62,7 +63,7 @@ def measured_traffic(config, prec, sym, mean_iters, combine):
         return None
     sha, nbytes, variant, iters = None, None, None, None
     for line in open(TRAFFIC_FILE):
-        if line.startswith("kernel_source_sha256 "):
+        if line.startswith("kernel_sources_sha256 "):
             sha = line.split(":", 1)[1].strip()
         elif line.startswith("k_ns_lp variant:"):
             variant = line.split(":", 1)[1].strip()
@@ -70,7 +71,10 @@ def measured_traffic(config, prec, sym, mean_iters, combine):
             nbytes = int(line.split(":", 1)[1])
         elif line.startswith("k_ns_lp mean_iterations:"):
             iters = float(line.split(":", 1)[1])
-    cur = hashlib.sha256(open(NS_SOURCE, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in NS_SOURCES:
+        h.update(open(f, "rb").read())
+    cur = h.hexdigest()
     ok = (sha == cur and nbytes and variant == ("sym" if sym else "plain") and iters is not None
           and abs(iters - mean_iters) <= 0.05)
     return nbytes if ok else None
@@ -335,7 +339,9 @@ def main():
         # GPU's job 16 of its cores, whatever the machine's total
         share = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
         workers = args.cpu_workers or min(16, share)
-        nsample = args.cpu_sample or 6 * workers
+        # about 10-20 s of oracle work on the cores of this job: 40 molecules
+        # per process (0.25-0.5 s each at these sizes)
+        nsample = args.cpu_sample or 40 * workers
         sample = sorted(rng.choice(system.nmol, size=min(nsample, system.nmol), replace=False).tolist())
         log(f"cpu baseline: oracle on {len(sample)} molecules with {workers} processes")
         cpu = cpu_baseline(system, sample, workers, single=min(4, len(sample)))
