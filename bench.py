@@ -302,6 +302,9 @@ def main():
     ap.add_argument("--density", action=argparse.BooleanOptionalAction, default=True,
                     help="16-bit runs: idempotency, asymmetry and trace of the assembled D, and of the "
                          "FP64 GPU solve of the same batch (after the timed steps)")
+    ap.add_argument("--finish-rows", action="store_true",
+                    help="FP16: the finishing products with the row-streaming vector kernel (one "
+                         "launch per product) instead of the fused matrix-core kernel")
     ap.add_argument("--combine", action="store_true",
                     help="combine submatrices (cubic criterion) before solving")
     ap.add_argument("--legs", action=argparse.BooleanOptionalAction, default=True,
@@ -361,7 +364,7 @@ def main():
     sym = 1 if (args.sym and args.prec in ("fp16", "bf16") and args.inverse != "coupled_ns"
                 and not args.want_w) else 0
     sv = Solver(system, prec=args.prec, device=dev, ws_budget=int(args.ws_gb * (1 << 30)), sched=sched,
-                inverse=inv, combine=args.combine, sym_sign=sym)
+                inverse=inv, combine=args.combine, sym_sign=sym, finish_rows=1 if args.finish_rows else 0)
     if args.want_w:
         sv.want_w()
     info = sv.plan.info()
@@ -456,6 +459,8 @@ def main():
                    "submatrix_rows": [int(n.min()), int(round(n.mean())), int(n.max())],
                    "precision": args.prec, "schedule": args.sched, "inverse": args.inverse,
                    "combined": bool(args.combine), "symmetric_sign": bool(sym), "submatrices": int(len(n)),
+                   "finishing": "row kernel" if (args.finish_rows or args.prec == "bf16") else
+                   ("fused matrix-core kernel" if args.prec == "fp16" else "none"),
                    "parallelism": "single GPU"},
         "submatrices_per_s": round(system.nmol / (ms / 1e3), 1),
         "tflops_paper_count": round(tflops_paper, 3),

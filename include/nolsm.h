@@ -203,7 +203,13 @@ typedef struct {
                                 then those of that symmetric matrix (a network
                                 trained on its features). Not with d_wcols.
                                 Default 0; used by configure.                  */
-    int32_t reserved_;       /* 0                                                */
+    int32_t finish_rows;     /* FP16: != 0 runs the column-restricted finishing
+                                products with the row-streaming vector kernel
+                                (one launch per product) instead of the default
+                                fused matrix-core kernel (both FP32-accurate:
+                                the fused one splits each n x bs block into
+                                FP16 high and low parts). BF16 always uses the
+                                vector kernel. Default 0.                      */
 } nolsm_solve_opts;
 
 /* Fills *o with the defaults above for precision `prec`. */

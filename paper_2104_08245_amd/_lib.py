@@ -43,7 +43,7 @@ class SolveOpts(C.Structure):
                 ("debug_poison_mol", C.c_int32), ("profile", C.c_int32),
                 ("ns_small_tile_mask", C.c_uint64), ("d_wcols", C.c_void_p),
                 ("inverse", C.c_int32), ("inv_max_iter", C.c_int32),
-                ("sym_sign", C.c_int32), ("reserved_", C.c_int32)]
+                ("sym_sign", C.c_int32), ("finish_rows", C.c_int32)]
 
 
 class MolStats(C.Structure):

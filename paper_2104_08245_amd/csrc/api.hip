@@ -171,6 +171,8 @@ static LaunchArgs make_args(const nolsm_plan *pl, const BatchArgs &b) {
     FinishArgs &fa = A.fa;
     fa.prec = o.prec;
     fa.nfinal = (o.prec == NOLSM_FP16 || o.prec == NOLSM_BF16) ? o.n_final_fp32 : 0;
+    fa.rows = o.finish_rows ? 1 : 0;
+    fa.pad_ = 0;
     ExtractArgs &ea = A.ea;
     ea.Krp = ga.Krp; ea.Kci = ga.Kci; ea.Srp = ga.Srp; ea.Sci = ga.Sci;
     ea.sub_blk = (const int32_t *)(base + pl->o_sub_blk);
@@ -244,7 +246,7 @@ static int enqueue_solve(const nolsm_plan *pl, const BatchArgs &b, const LaunchA
     }
     if (prof) {
         prof->n_ns += 2 * o.max_iter;
-        prof->n_fin += A.fa.nfinal == 0 ? 1 : (A.fa.nfinal == 1 ? 3 : 9);
+        prof->n_fin += finish_launches(A.fa);
     }
     return NOLSM_OK;
 }

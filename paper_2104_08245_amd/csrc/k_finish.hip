@@ -129,12 +129,133 @@ static hipError_t run_finish(const ChunkDev &cd, char *ws, int nfinal, int bs, h
     return hipSuccess;                                           // Z = 1.5 w1 - 0.75 q1 + 0.25 q3
 }
 
+// ---------------------------------------------------------------------------
+// FP16 finishing fused on the matrix cores: one workgroup per (submatrix,
+// owned molecule) runs all the products above in order. P is exact in FP16;
+// each input block v (n x bs, FP32) is split into FP16 parts h = fp16(v) and
+// l = fp16(v - h), which hold 22 of its 24 bits (the rest is below 2^-22
+// relative, absolute below 2^-24 times the FP16 subnormal scale), and
+// P [h | l | 0] is one n x 16 product on v_mfma_f32_16x16x32_f16 with FP32
+// accumulation; P v = P h + P l. The B operand [h | l | 0] sits in LDS as 16
+// rows of np + 8 values (the pad spreads the 16 rows a wave reads over all
+// banks); A is read straight from P, a 16-byte row segment per lane. The
+// workgroup (16 waves) holds at least 96 KB of LDS so that one runs per CU:
+// the 256 submatrices in flight then keep their P (0.8 MB each at n ~ 640)
+// in the 256 MB last-level cache across the nine products, where more
+// workgroups per CU would re-read it from HBM.
+// ---------------------------------------------------------------------------
+#define FIN_THREADS 1024
+#define FIN_LDS_MIN (96 * 1024)
+typedef float v4f_fin __attribute__((ext_vector_type(4)));
+
+struct FinStep { int8_t ina, inb, out, save; float alpha, beta; };
+// u1 = P y, u2 = P u1, u3 = P u2, w1 = 1.5 u1 - 0.5 u3 (saved), p1 = P w1,
+// p2, p3, w2 = 1.5 p1 - 0.5 p3 (saved), q1 = P w2, q2, q3: the sequence of
+// run_finish, same vector slots
+__constant__ FinStep fin_steps[9] = {{-1, -2, 0, -1, 1.0f, 0.0f}, {0, -2, 1, -1, 1.0f, 0.0f},
+                                     {1, -2, 2, -1, 1.0f, 0.0f},  {0, 2, 4, 3, 1.5f, -0.5f},
+                                     {4, -2, 5, -1, 1.0f, 0.0f},  {5, -2, 6, -1, 1.0f, 0.0f},
+                                     {4, 6, 8, 7, 1.5f, -0.5f},   {8, -2, 9, -1, 1.0f, 0.0f},
+                                     {9, -2, 10, -1, 1.0f, 0.0f}};
+
+__global__ __launch_bounds__(FIN_THREADS, 1) void k_finish_f16(ChunkDev cd, char *ws, int nsteps, int bs) {
+    extern __shared__ __attribute__((aligned(16))) uint16_t vb[];   // [16][np + 8]
+    const int s = blockIdx.x, o = blockIdx.y;
+    if (s >= cd.nsub) return;
+    const SubMeta M = cd.meta[s];
+    const SubCtl *ctl = cd.ctl + s;
+    if (o >= M.nown || ctl->status == NOLSM_MOL_NOT_SPD) return;
+    const int np = M.np, ldb = np + 8, ldx = M.ldx, t = threadIdx.x, w = t >> 6, l = t & 63;
+    const uint16_t *P = (const uint16_t *)(ws + ((ctl->iters & 1) ? M.offX1 : M.offX0));
+    const int64_t vs = (int64_t)np * 12;   // floats per vector slot (np x 6 doubles reserved)
+    float *V = (float *)(ws + M.offVec) + (int64_t)o * NOLSM_NVEC * vs;
+    const double *Kb = (const double *)(ws + M.offK);
+    for (int f = t; f < 4 * ldb; f += FIN_THREADS) vb[12 * ldb + f] = 0;   // columns 12..15 of B
+    for (int step = 0; step < nsteps; ++step) {
+        const FinStep S = fin_steps[step];
+        // input block, split into its FP16 high and low parts
+        for (int f = t; f < np * 6; f += FIN_THREADS) {
+            const int r = f / 6, j = f - r * 6;
+            float v = 0.0f;
+            if (j < bs) {
+                auto get = [&](int idx) -> float {
+                    if (idx == -1) return (float)Kb[(int64_t)r * (np + 64) + np + o * bs + j];
+                    return V[(int64_t)idx * vs + (int64_t)r * 6 + j];
+                };
+                v = S.alpha * get(S.ina);
+                if (S.inb >= -1) v += S.beta * get(S.inb);
+                if (S.save >= 0) V[(int64_t)S.save * vs + (int64_t)r * 6 + j] = v;
+            }
+            const _Float16 h = (_Float16)v;
+            const _Float16 lo = (_Float16)(v - (float)h);
+            vb[j * ldb + r] = __builtin_bit_cast(uint16_t, h);
+            vb[(6 + j) * ldb + r] = __builtin_bit_cast(uint16_t, lo);
+        }
+        __syncthreads();
+        // out = P [h | l | 0], 16 rows per block: lane l holds A row l % 16,
+        // k = 8 (l / 16) .. + 7 of each 32-deep step, B column l % 16 of the
+        // same k, and the results of rows 4 (l / 16) + e, column l % 16
+        const int nb = np >> 4;
+        const uint16_t *brow = vb + (l & 15) * ldb + (l >> 4) * 8;
+        // two row blocks per wave at a time (the second may be past the
+        // end: its rows are clamped to the first block and not stored), two
+        // accumulators each over k (np is a multiple of 64): eight 16-byte
+        // row segments of P in flight per lane
+        for (int rb = w; rb < nb; rb += 2 * (FIN_THREADS / 64)) {
+            const int rb2 = rb + FIN_THREADS / 64;
+            const bool two = rb2 < nb;
+            v4f_fin c00 = {0.0f, 0.0f, 0.0f, 0.0f}, c01 = c00, c10 = c00, c11 = c00;
+            const uint16_t *a0row = P + (int64_t)(rb * 16 + (l & 15)) * ldx + (l >> 4) * 8;
+            const uint16_t *a1row = P + (int64_t)((two ? rb2 : rb) * 16 + (l & 15)) * ldx + (l >> 4) * 8;
+            for (int k0 = 0; k0 < np; k0 += 64) {
+                const v8h a00 = *(const v8h *)(a0row + k0);
+                const v8h a01 = *(const v8h *)(a0row + k0 + 32);
+                const v8h a10 = *(const v8h *)(a1row + k0);
+                const v8h a11 = *(const v8h *)(a1row + k0 + 32);
+                const v8h b0 = *(const v8h *)(brow + k0);
+                const v8h b1 = *(const v8h *)(brow + k0 + 32);
+                c00 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a00, b0, c00, 0, 0, 0);
+                c01 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a01, b1, c01, 0, 0, 0);
+                c10 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a10, b0, c10, 0, 0, 0);
+                c11 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a11, b1, c11, 0, 0, 0);
+            }
+            c00 += c01;
+            c10 += c11;
+            // column j + 6 holds P l of column j: lanes of columns 0..5 add it
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float p0 = __shfl(c00[e], l + 6), p1 = __shfl(c10[e], l + 6);
+                const int r = (l >> 4) * 4 + e, j = l & 15;
+                if (j < bs) {
+                    V[(int64_t)S.out * vs + (int64_t)(rb * 16 + r) * 6 + j] = c00[e] + p0;
+                    if (two) V[(int64_t)S.out * vs + (int64_t)(rb2 * 16 + r) * 6 + j] = c10[e] + p1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+int finish_launches(const FinishArgs &fa) {
+    const int products = fa.nfinal == 0 ? 1 : (fa.nfinal == 1 ? 3 : 9);
+    return (fa.prec == NOLSM_FP16 && !fa.rows) ? 1 : products;
+}
+
 hipError_t launch_finish(const ChunkDev &cd, char *ws, const FinishArgs &fa, hipStream_t st) {
     const int bs = 6;
     switch (fa.prec) {
         case NOLSM_FP64: return run_finish<double, double>(cd, ws, 0, bs, st);
         case NOLSM_FP32: return run_finish<float, float>(cd, ws, 0, bs, st);
-        case NOLSM_FP16: return run_finish<F16, float>(cd, ws, fa.nfinal, bs, st);
+        case NOLSM_FP16:
+            if (!fa.rows) {
+                size_t lds = (size_t)16 * (cd.max_np + 8) * 2;
+                if (lds < FIN_LDS_MIN) lds = FIN_LDS_MIN;
+                const int nsteps = fa.nfinal == 0 ? 1 : (fa.nfinal == 1 ? 3 : 9);
+                hipLaunchKernelGGL(k_finish_f16, dim3(cd.nsub, cd.max_own), dim3(FIN_THREADS), lds, st, cd, ws,
+                                   nsteps, bs);
+                return hipGetLastError();
+            }
+            return run_finish<F16, float>(cd, ws, fa.nfinal, bs, st);
         default: return run_finish<BF16, float>(cd, ws, fa.nfinal, bs, st);
     }
 }
@@ -427,7 +548,7 @@ hipError_t nolsm_finish_init() {
     const void *fns[] = {(const void *)k_extract<double>,          (const void *)k_extract<float>,
                          (const void *)k_skinny<double, double>,   (const void *)k_skinny<float, float>,
                          (const void *)k_skinny<F16, float>,       (const void *)k_skinny<BF16, float>,
-                         (const void *)k_wcols};
+                         (const void *)k_wcols,                (const void *)k_finish_f16};
     for (const void *f : fns)
         if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
             return hipErrorInvalidValue;

@@ -57,6 +57,8 @@ struct InvArgs {
 struct FinishArgs {
     int32_t prec;
     int32_t nfinal;        // 0, 1, 2 column-restricted finishing iterations
+    int32_t rows;          // FP16: the row-streaming kernel instead of the fused one
+    int32_t pad_;
 };
 
 struct ExtractArgs {
@@ -86,6 +88,7 @@ hipError_t launch_subst(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st)
 // symmetric sign iteration: [W | y] = L^-1 [K | E], then A~ = W L^-T - mu I in place
 hipError_t launch_subst_sym(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st);
 hipError_t launch_set_header(char *ws, double mu, hipStream_t st);
+int finish_launches(const FinishArgs &fa);
 hipError_t launch_trace_sums(const void *stats, int32_t nb, char *ws, hipStream_t st);
 hipError_t launch_bounds(const ChunkDev &cd, char *ws, const BoundsArgs &ba, int prec, hipStream_t st);
 hipError_t launch_convert(const ChunkDev &cd, char *ws, int prec, int use_scale_g, int sym, hipStream_t st);

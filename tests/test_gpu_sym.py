@@ -171,3 +171,29 @@ def test_symmetric_rejects_outputs_defined_on_a(torch, box64):
     with pytest.raises(NolsmError) as e:
         sv.run()
     assert e.value.code == L.E_ARG
+
+
+@pytest.mark.parametrize("sym", [1, 0])
+def test_fused_finishing_matches_row_kernel(torch, box64, ref1, sym):
+    # the FP16 finishing products on the matrix cores (P [h | l], the input
+    # split into FP16 high and low parts) against the row-streaming FP32
+    # vector kernel on the same iterate: both FP32-accurate, so they agree far
+    # below the 16-bit floor; both stay within the stated bounds of the oracle
+    from paper_2104_08245_amd import Solver
+    out = {}
+    for rows in (0, 1):
+        sv = Solver(box64, prec="fp16", device="cuda:0", sym_sign=sym, finish_rows=rows)
+        sv.run()
+        torch.cuda.synchronize()
+        st = sv.host_stats()
+        assert np.all(st["status"] == 0) and np.all(st["iters_fp32"] == 2)
+        out[rows] = (sv.host_dcols(), st)
+    (d0, s0), (d1, s1) = out[0], out[1]
+    assert np.array_equal(s0["iters"], s1["iters"])
+    diff = max(rel(d0[J], d1[J]) for J in range(box64.nmol))
+    dE = np.abs(s0["energy_KD"] - s1["energy_KD"]).max()
+    say(f"fused vs row finishing (sym={sym}): worst Dcols rel-F {diff:.3e}, max |dE| {dE:.3e}")
+    assert diff <= 2e-5 and dE <= 1e-5
+    errs = np.array([rel(d0[J], ref1.Dcols[J]) for J in range(box64.nmol)])
+    assert errs.max() <= MIXED["fp16"]["dcols"]
+    assert np.abs(s0["energy_KD"] - ref1.E).max() <= MIXED["fp16"]["energy"]
