@@ -210,6 +210,11 @@ typedef struct {
                                 the fused one splits each n x bs block into
                                 FP16 high and low parts). BF16 always uses the
                                 vector kernel. Default 0.                      */
+    int32_t debug_force_stall;/* >= 0: molecule whose sign iteration is taken as
+                                diverged after its residual at iteration 2, so
+                                the guard restarts it from the Gershgorin scale
+                                (fallback = 1, same result); -1: none        */
+    int32_t reserved_;       /* 0                                                */
 } nolsm_solve_opts;
 
 /* Fills *o with the defaults above for precision `prec`. */

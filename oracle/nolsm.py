@@ -176,10 +176,13 @@ class SubResult:
     Wcols: np.ndarray | None = None   # (n_J, bs), only when asked for
 
 
-def newton_schulz_sign(A, c, tol=1e-10, max_iter=100):
+def newton_schulz_sign(A, c, tol=1e-10, max_iter=100, restart_at=None):
     """X_0 = c A; X_{k+1} = X_k (3I - X_k^2)/2 (Eq. NS1); returns the first
     X_k with ||X_k^2 - I||_F < tol, the number of updates taken, and that
-    residual. Reaching max_iter means no convergence."""
+    residual. Reaching max_iter means no convergence.
+    restart_at = k (the injected stall of the divergence guard, not in the
+    paper): after the residual of X_k, X_{k+1} = c A instead of the update,
+    the guard's restart from the initial scale; the sign reached is the same."""
     n = A.shape[0]
     I = np.eye(n)
     X = c * A
@@ -187,6 +190,9 @@ def newton_schulz_sign(A, c, tol=1e-10, max_iter=100):
     for k in range(max_iter):
         T = X @ X
         r = float(np.linalg.norm(T - I, "fro"))
+        if k == restart_at:
+            X = c * A
+            continue
         if r < tol:
             return X, k, r, True
         X = 0.5 * (X @ (3.0 * I - T))
@@ -216,7 +222,7 @@ def coupled_ns_inverse(S, c, tol=1e-12, max_iter=100):
 
 
 def solve_submatrix(KJ, SJ, p, bs, mu, tol=1e-10, max_iter=100, scale=None, want_w=False,
-                    inverse="cholesky"):
+                    inverse="cholesky", restart_at=None):
     """Everything inside one submatrix, for the molecule at block position p.
     inverse="coupled_ns" applies T_J(S)^-1 from the coupled Newton-Schulz
     iteration (Eq. inv1-inv3, FP64, converged to 1e-12) instead of the
@@ -247,7 +253,7 @@ def solve_submatrix(KJ, SJ, p, bs, mu, tol=1e-10, max_iter=100, scale=None, want
     E[p * bs:(p + 1) * bs, :] = np.eye(bs)
     Y = s_inv(E)
     c = 1.0 / np.abs(A).sum(axis=1).max() if scale is None else scale
-    X, iters, r, conv = newton_schulz_sign(A, c, tol, max_iter)
+    X, iters, r, conv = newton_schulz_sign(A, c, tol, max_iter, restart_at)
     Dcols = 0.5 * (Y - X @ Y)
     rows = slice(p * bs, (p + 1) * bs)
     N_J = float(np.trace(SJ[rows, :] @ Dcols))
@@ -409,12 +415,14 @@ def submatrix(system, J, mu=None):
     return KJ, SJ, idx, int(self_pos[J])
 
 
-def solve_molecule(system, J, mu=None, tol=1e-10, max_iter=100, want_w=False, inverse="cholesky"):
+def solve_molecule(system, J, mu=None, tol=1e-10, max_iter=100, want_w=False, inverse="cholesky",
+                   restart_at=None):
     """Steps 3-8 and 10 for one column block J, without assembling D (for
     sampled checks on systems too large for the whole-batch oracle)."""
     mu = system.mu if mu is None else mu
     KJ, SJ, idx, p = submatrix(system, J)
-    return solve_submatrix(KJ, SJ, p, system.K.bs, mu, tol, max_iter, want_w=want_w, inverse=inverse)
+    return solve_submatrix(KJ, SJ, p, system.K.bs, mu, tol, max_iter, want_w=want_w, inverse=inverse,
+                           restart_at=restart_at)
 
 
 def dense(csr):

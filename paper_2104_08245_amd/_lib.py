@@ -6,7 +6,10 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libnolsm.so")
+# NOLSM_LIB names another build of the library (the AddressSanitizer build
+# of the host plan code used by a CPU test): only the symbols it has are bound
+LIB_OVERRIDE = os.environ.get("NOLSM_LIB")
+LIB_PATH = LIB_OVERRIDE or os.path.join(HERE, "libnolsm.so")
 
 NOLSM_OK = 0
 E_ARG, E_PATTERN, E_WORKSPACE, E_HIP, E_STATE, E_NOT_SPD, E_NOCONV, E_NOMEM = range(-1, -9, -1)
@@ -43,7 +46,8 @@ class SolveOpts(C.Structure):
                 ("debug_poison_mol", C.c_int32), ("profile", C.c_int32),
                 ("ns_small_tile_mask", C.c_uint64), ("d_wcols", C.c_void_p),
                 ("inverse", C.c_int32), ("inv_max_iter", C.c_int32),
-                ("sym_sign", C.c_int32), ("finish_rows", C.c_int32)]
+                ("sym_sign", C.c_int32), ("finish_rows", C.c_int32),
+                ("debug_force_stall", C.c_int32), ("reserved_", C.c_int32)]
 
 
 class MolStats(C.Structure):
@@ -94,34 +98,35 @@ def lib():
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, sz, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t, C.c_double
     p_i32 = C.POINTER(C.c_int32)
-    L.nolsm_default_opts.argtypes = [C.POINTER(SolveOpts), i32]
-    L.nolsm_default_opts.restype = None
-    L.nolsm_switch_tol.argtypes = [i32, i32, dbl]
-    L.nolsm_switch_tol.restype = dbl
-    L.nolsm_build_submatrices.argtypes = [C.POINTER(Pattern), C.POINTER(Pattern), i32, C.POINTER(vp)]
-    L.nolsm_plan_info.argtypes = [vp, C.POINTER(PlanSizes)]
-    L.nolsm_plan_export.argtypes = [vp, p_i32, p_i32, p_i32, p_i32, p_i32, p_i32]
-    L.nolsm_plan_groups.argtypes = [vp, p_i32, p_i32, p_i32, p_i32]
-    L.nolsm_plan_configure.argtypes = [vp, C.POINTER(SolveOpts), sz, C.POINTER(sz)]
-    L.nolsm_plan_bind.argtypes = [vp, vp, sz, vp]
-    L.nolsm_sign_batch.argtypes = [vp, vp, vp, dbl, C.POINTER(SolveOpts), vp, sz, vp, vp, vp, vp]
-    L.nolsm_sign_batch_noalloc.argtypes = [vp, vp, vp, dbl, C.POINTER(SolveOpts), vp, vp, vp, vp]
-    L.nolsm_assemble_D.argtypes = [vp, vp, vp, vp]
-    L.nolsm_plan_destroy.argtypes = [vp]
-    L.nolsm_plan_destroy.restype = None
-    L.nolsm_strerror.argtypes = [C.c_int]
-    L.nolsm_strerror.restype = C.c_char_p
-    L.nolsm_profile_last.argtypes = [vp, C.POINTER(Profile)]
-    L.nolsm_trace_sums.argtypes = [vp, vp, vp, C.POINTER(C.c_double), vp]
-    L.nolsm_mu_bisect.argtypes = [vp, vp, vp, dbl, dbl, dbl, dbl, i32, C.POINTER(SolveOpts), vp, sz, vp, vp,
-                                  vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32)]
-    L.nolsm_mlp_forward.argtypes = [vp, vp, vp, i32, vp, vp]
-    L.nolsm_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
-    L.nolsm_mlp_adam.argtypes = [vp, vp, vp, vp, i32, C.c_double, C.c_double, C.c_double, C.c_double, vp]
+    sigs = {
+        "nolsm_default_opts": ([C.POINTER(SolveOpts), i32], None),
+        "nolsm_switch_tol": ([i32, i32, dbl], dbl),
+        "nolsm_build_submatrices": ([C.POINTER(Pattern), C.POINTER(Pattern), i32, C.POINTER(vp)], C.c_int),
+        "nolsm_plan_info": ([vp, C.POINTER(PlanSizes)], C.c_int),
+        "nolsm_plan_export": ([vp, p_i32, p_i32, p_i32, p_i32, p_i32, p_i32], C.c_int),
+        "nolsm_plan_groups": ([vp, p_i32, p_i32, p_i32, p_i32], C.c_int),
+        "nolsm_plan_configure": ([vp, C.POINTER(SolveOpts), sz, C.POINTER(sz)], C.c_int),
+        "nolsm_plan_bind": ([vp, vp, sz, vp], C.c_int),
+        "nolsm_sign_batch": ([vp, vp, vp, dbl, C.POINTER(SolveOpts), vp, sz, vp, vp, vp, vp], C.c_int),
+        "nolsm_sign_batch_noalloc": ([vp, vp, vp, dbl, C.POINTER(SolveOpts), vp, vp, vp, vp], C.c_int),
+        "nolsm_assemble_D": ([vp, vp, vp, vp], C.c_int),
+        "nolsm_plan_destroy": ([vp], None),
+        "nolsm_strerror": ([C.c_int], C.c_char_p),
+        "nolsm_profile_last": ([vp, C.POINTER(Profile)], C.c_int),
+        "nolsm_trace_sums": ([vp, vp, vp, C.POINTER(C.c_double), vp], C.c_int),
+        "nolsm_mu_bisect": ([vp, vp, vp, dbl, dbl, dbl, dbl, i32, C.POINTER(SolveOpts), vp, sz, vp, vp,
+                             vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32)],
+                            C.c_int),
+        "nolsm_mlp_forward": ([vp, vp, vp, i32, vp, vp], C.c_int),
+        "nolsm_mlp_loss_grad": ([vp, vp, vp, vp, i32, vp, vp, vp], C.c_int),
+        "nolsm_mlp_adam": ([vp, vp, vp, vp, i32, C.c_double, C.c_double, C.c_double, C.c_double, vp], C.c_int),
+    }
+    assert set(sigs) == set(EXPORTED)
     for name in EXPORTED:
-        f = getattr(L, name)
-        if name not in ("nolsm_default_opts", "nolsm_plan_destroy", "nolsm_strerror", "nolsm_switch_tol"):
-            f.restype = C.c_int
+        if LIB_OVERRIDE and not hasattr(L, name):
+            continue
+        f = getattr(L, name)   # the library itself must export every symbol
+        f.argtypes, f.restype = sigs[name]
     _lib = L
     return L
 

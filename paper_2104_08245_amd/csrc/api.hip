@@ -160,7 +160,7 @@ static LaunchArgs make_args(const nolsm_plan *pl, const BatchArgs &b) {
     na.persistent = o.sched == NOLSM_SCHED_PERSISTENT;
     na.pgrid = pl->pgrid;
     na.sym = o.sym_sign ? 1 : 0;
-    na.pad_ = 0;
+    na.force_stall = o.debug_force_stall;
     InvArgs &ia = A.ia;
     ia.prec = o.prec;
     ia.max_iter = o.inv_max_iter;

@@ -37,7 +37,12 @@ __device__ int ns_decide(const NsArgs &na, const SubMeta &M, SubCtl *ctl, const 
         stop = r < na.tol;
     else
         stop = (na.tol > 0.0 && r < na.tol) || (it >= 1 && r < na.rmax && r > na.theta * rprev);
-    const bool diverge = !isfinite(r) || (it >= 1 && r > 2.0 * rprev && r > 1.0);
+    // a stall injected from the host for one molecule counts as divergence
+    // at one iteration, so that the restart path can be checked (every
+    // workgroup of the submatrix takes the same decision from `it` alone;
+    // restart_at may already hold it + 1 from the tile-0 workgroup)
+    const bool forced = na.force_stall >= 0 && M.J == na.force_stall && it == NOLSM_STALL_IT;
+    const bool diverge = forced || !isfinite(r) || (it >= 1 && r > 2.0 * rprev && r > 1.0);
     const int ra = ctl->restart_at;
     int act;
     bool noconv = false;

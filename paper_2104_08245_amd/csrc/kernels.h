@@ -41,8 +41,9 @@ struct NsArgs {
     int32_t persistent;    // queue-driven fixed grid instead of one workgroup per tile
     int32_t pgrid;         // workgroups of a persistent launch
     int32_t sym;           // symmetric sign iteration: upper tiles, mirrored (FP16/BF16)
-    int32_t pad_;
+    int32_t force_stall;   // molecule taken as diverged at iteration NOLSM_STALL_IT (-1: none)
 };
+#define NOLSM_STALL_IT 2
 
 // Coupled Newton-Schulz inverse (Eq. inv1-inv3), stop rule as for the sign
 // iteration in 16 bits: stagnation r_k > theta r_{k-1} with r_k < rmax.

@@ -337,6 +337,8 @@ extern "C" void nolsm_default_opts(nolsm_solve_opts *o, int32_t prec) {
     o->inv_max_iter = 40;
     o->sym_sign = 0;
     o->finish_rows = 0;
+    o->debug_force_stall = -1;
+    o->reserved_ = 0;
 }
 
 extern "C" int nolsm_plan_info(const nolsm_plan *p, nolsm_plan_sizes *o) {

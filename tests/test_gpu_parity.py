@@ -218,6 +218,30 @@ def test_divergence_restarts_from_gershgorin(torch, box64, ref1):
     assert worst <= 1e-10
 
 
+@pytest.mark.parametrize("prec,kw", [("fp64", {}), ("fp16", {"sym_sign": 1})])
+def test_forced_stall_restarts_one_molecule(torch, box64, ref1, prec, kw):
+    # the stall injected for molecule 11 is taken as divergence at iteration
+    # 2: only that molecule restarts from the Gershgorin scale (fallback = 1)
+    # and it reaches the same result as the oracle with the same injected
+    # restart (and as without it)
+    J = 11
+    sv = solve(box64, prec, debug_force_stall=J, **kw)
+    st = sv.host_stats()
+    assert st["fallback"][J] == 1
+    assert np.all(np.delete(st["fallback"], J) == 0)
+    assert np.all(st["status"] == 0)
+    ref = o.solve_molecule(box64, J, restart_at=2)
+    dc = sv.host_dcols()
+    tol = 1e-10 if prec == "fp64" else MIXED["fp16"]["dcols"]
+    assert rel(dc[J], ref.Dcols) <= tol
+    assert rel(dc[J], ref1.Dcols[J]) <= tol
+    # the others take the unperturbed iteration
+    plain = solve(box64, prec, **kw)
+    assert np.array_equal(np.delete(plain.host_stats()["iters"], J), np.delete(st["iters"], J))
+    if prec == "fp64":
+        assert st["iters"][J] >= plain.host_stats()["iters"][J] + 2
+
+
 def test_noconv_flag(torch, box64):
     from paper_2104_08245_amd import _lib as L, NolsmError
     sv = solve(box64, "fp64", max_iter=3)

@@ -255,3 +255,14 @@ def test_vectorized_gather_equals_plain_gather(box64):
         a = o.gather(lists[J], 6, s.K.row_ptr, s.K.col_idx, s.K.val)
         b = o.gather_vectorized(lists[J], 6, s.K.row_ptr, s.K.col_idx, s.K.val)
         assert np.array_equal(a, b)
+
+
+def test_forced_restart_reaches_the_same_sign(box64):
+    # the divergence guard's restart (X_{k+1} = c A instead of the update,
+    # injected at k = 2) delays the iteration but converges to the same sign
+    J = 9
+    a = o.solve_molecule(box64, J)
+    b = o.solve_molecule(box64, J, restart_at=2)
+    assert a.status == b.status == 0
+    assert b.iters == a.iters + 3
+    assert np.linalg.norm(a.Dcols - b.Dcols) <= 1e-12 * np.linalg.norm(a.Dcols)
