@@ -305,6 +305,12 @@ def main():
     ap.add_argument("--finish-rows", action="store_true",
                     help="FP16: the finishing products with the row-streaming vector kernel (one "
                          "launch per product) instead of the fused matrix-core kernel")
+    ap.add_argument("--tiles", default="cache", choices=["cache", "tune", "default"],
+                    help="16-bit NS tile per size bucket: the autotuned choices of the tile cache "
+                         "(buckets it lacks keep the default), tune them now before the warm-up "
+                         "(untimed; written to --tile-cache), or the library's default mask")
+    ap.add_argument("--tile-cache", default=None,
+                    help="tile cache JSON (default: the package's tile_cache.json)")
     ap.add_argument("--combine", action="store_true",
                     help="combine submatrices (cubic criterion) before solving")
     ap.add_argument("--legs", action=argparse.BooleanOptionalAction, default=True,
@@ -363,8 +369,29 @@ def main():
            "cholesky_fp32": L.INV_CHOLESKY_FP32, "coupled_ns": L.INV_COUPLED_NS}[args.inverse]
     sym = 1 if (args.sym and args.prec in ("fp16", "bf16") and args.inverse != "coupled_ns"
                 and not args.want_w) else 0
+    lowp = args.prec in ("fp16", "bf16")
+    tiles, masks = None, {}
+    if lowp:
+        from paper_2104_08245_amd import autotune
+        cache = args.tile_cache or autotune.CACHE
+        if args.tiles == "tune":
+            autotune.tune(system, args.prec, bool(sym), log=log, cache=cache, inverse=inv,
+                          combine=args.combine, ws_budget=int(args.ws_gb * (1 << 30)))
+            torch.cuda.empty_cache()
+        for v in (True, False):
+            if args.tiles == "default":
+                masks[v] = (L.default_opts(args.prec).ns_small_tile_mask, [], autotune.buckets_of(system))
+            else:
+                masks[v] = autotune.mask_for(system, args.prec, v, cache=cache)
+        mask, tuned, buckets = masks[bool(sym)]
+        tiles = {"mask": hex(mask), "source": "library default" if args.tiles == "default" else
+                 "autotuned" if args.tiles == "tune" else "tile cache",
+                 "buckets_tuned": f"{len(tuned)}/{len(buckets)}"}
+        log(f"NS tiles: mask {mask:#x}, {tiles['source']}, {tiles['buckets_tuned']} buckets tuned")
+    tile_kw = {"ns_small_tile_mask": masks[bool(sym)][0]} if lowp else {}
     sv = Solver(system, prec=args.prec, device=dev, ws_budget=int(args.ws_gb * (1 << 30)), sched=sched,
-                inverse=inv, combine=args.combine, sym_sign=sym, finish_rows=1 if args.finish_rows else 0)
+                inverse=inv, combine=args.combine, sym_sign=sym, finish_rows=1 if args.finish_rows else 0,
+                **tile_kw)
     if args.want_w:
         sv.want_w()
     info = sv.plan.info()
@@ -461,6 +488,7 @@ def main():
                    "combined": bool(args.combine), "symmetric_sign": bool(sym), "submatrices": int(len(n)),
                    "finishing": "row kernel" if (args.finish_rows or args.prec == "bf16") else
                    ("fused matrix-core kernel" if args.prec == "fp16" else "none"),
+                   **({"ns_tiles": tiles} if tiles else {}),
                    "parallelism": "single GPU"},
         "submatrices_per_s": round(system.nmol / (ms / 1e3), 1),
         "tflops_paper_count": round(tflops_paper, 3),
@@ -485,7 +513,6 @@ def main():
                            "GB_per_s": round(wbytes / (prof["ms_wmat"] / 1e3) / 1e9, 1) if prof["ms_wmat"] > 0 else None,
                            "bytes": wbytes}
     E_main = st["energy_KD"].copy()
-    lowp = args.prec in ("fp16", "bf16")
     ex = sv.plan.export() if (args.density and lowp) else None
     Dm_host = sv.host_D() if ex is not None else None
     # the legs get the same workspace budget: the timed solver's goes first
@@ -495,7 +522,7 @@ def main():
         legs = {}
         if sym:
             leg, lms = time_leg(system, dev, args, "no_sym", args.leg_steps, prec=args.prec, sched=sched,
-                                inverse=inv, sym_sign=0)
+                                inverse=inv, sym_sign=0, ns_small_tile_mask=masks[False][0])
             lf = paper_and_exec_flops(leg, 0, system)
             legs["iteration_on_A"] = {
                 "what": "the sign iteration on A_J = S_J^-1 K_J - mu I (no symmetric form), same batch",
@@ -505,6 +532,33 @@ def main():
                 "ns_iters_mean": round(float(lf["it"].mean()), 2),
                 "energy_max_diff_vs_main": float(np.abs(lf["st"]["energy_KD"] - E_main).max())}
             del leg
+            torch.cuda.empty_cache()
+        if sym and not args.combine:
+            # the rescaling with learned spectral bounds (Sec. III-B.2): the
+            # MLP is trained (untimed) with the library's kernels on the
+            # stored, eigensolve-labelled features of a 4,096-molecule
+            # trajectory of the same water-like model, then predicts the
+            # bounds of every submatrix of this batch inside each step
+            from paper_2104_08245_amd import learned
+            ts = np.load(os.path.join(ROOT, "tests", "golden", "mlp_train_sym.npz"))
+            tr = learned.train(ts["features"], ts["labels"], epochs=200, device=dev)
+            torch.cuda.synchronize()
+            leg, lms = time_leg(system, dev, args, "learned", args.leg_steps, prec=args.prec, sched=sched,
+                                inverse=inv, sym_sign=1, ns_small_tile_mask=masks[True][0],
+                                bounds=L.BOUNDS_LEARNED, d_mlp=tr["params"].data_ptr(),
+                                d_mlp_norm=tr["norm"].data_ptr())
+            lf = paper_and_exec_flops(leg, 1, system)
+            legs["learned_bounds"] = {
+                "what": "the main line with learned spectral bounds (MLP trained on stored eigensolve "
+                        "labels of a 4,096-molecule trajectory of the same model), same batch",
+                "steps": args.leg_steps, "ms_per_step": round(lms, 3),
+                "submatrices_per_s": round(system.nmol / (lms / 1e3), 1),
+                "ns_iters_mean": round(float(lf["it"].mean()), 2),
+                "restarts": int(lf["st"]["fallback"].sum()),
+                "status_ok": int((lf["st"]["status"] == 0).sum()),
+                "energy_max_diff_vs_main": float(np.abs(lf["st"]["energy_KD"] - E_main).max())}
+            E_learned = lf["st"]["energy_KD"].copy()
+            del leg, tr
             torch.cuda.empty_cache()
         ref, fms = time_leg(system, dev, args, "fp64", args.fp64_steps, prec="fp64", sched=sched)
         rf = paper_and_exec_flops(ref, 0, system)
@@ -521,6 +575,8 @@ def main():
         out["speedup_vs_fp64_gpu"] = round(fms / ms, 2)
         out["energy_error_vs_fp64_gpu"] = {"max": float(dE.max()), "mean": float(dE.mean()),
                                            "molecules": int(len(dE))}
+        if "learned_bounds" in legs:
+            legs["learned_bounds"]["energy_error_vs_fp64_gpu_max"] = float(np.abs(E_learned - e64).max())
         out["legs"] = legs
         if ex is not None:
             out["density_checks"] = density_against_fp64(system, ex, Dm_host, ref)

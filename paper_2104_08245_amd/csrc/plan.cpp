@@ -486,8 +486,12 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
             return NOLSM_E_WORKSPACE;
         }
         pl->ws_bytes = ws_bytes;
-        // greedy chunks; the per-bucket schedule also cuts at bucket changes
-        // (buckets of 64 rows, i.e. equal np)
+        // greedy chunks in decreasing size. The per-bucket schedule also cuts
+        // at bucket changes (buckets of 64 rows, i.e. equal np); the others
+        // cut where np falls below 4/5 of the chunk's largest, because the
+        // serial setup launches (Cholesky panels, right-solve row blocks) of
+        // a chunk run to the depth of its largest submatrix while smaller
+        // ones idle
         size_t i = 0;
         while (i < order.size()) {
             HostChunk ch;
@@ -497,6 +501,7 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
             while (i < order.size() && js.size() < 65535) {
                 const int32_t J = order[i];
                 if (pl->sched == NOLSM_SCHED_PER_BUCKET && np_of(J) != bucket) break;
+                if (pl->sched != NOLSM_SCHED_PER_BUCKET && 5 * np_of(J) < 4 * bucket) break;
                 const size_t sb = slot_bytes(J);
                 if (used + sb + 256 + qbytes > region) break;
                 used += sb;

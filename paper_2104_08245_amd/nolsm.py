@@ -132,6 +132,14 @@ class Solver:
         for k, v in kw.items():
             setattr(self.opts, k, v)
 
+    def reconfigure(self, **kw):
+        """Options that change the plan's task lists or layout (the NS tile
+        mask, the schedule): configure again within the same workspace and
+        upload the new metadata."""
+        self.set_opts(**kw)
+        mb = self.plan.configure(self.opts, self.ws_bytes)
+        self.plan.bind(mb, self.device)
+
     def want_w(self):
         """Also compute the owned columns of the energy-weighted density
         matrix T_J(W) = T_J(D) T_J(K) T_J(D) on every run (Sec. III-B.2)."""

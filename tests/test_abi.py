@@ -144,7 +144,14 @@ def test_configure_chunks_and_workspace_errors(L, box64):
     opts = L.default_opts("fp16")
     mb = p.configure(opts, 1 << 40)
     inf = p.info()
-    assert inf["nchunks"] == 1 and mb == inf["meta_bytes"] > 0
+    # with room for everything, a chunk is cut only where the padded size
+    # falls below 4/5 of the chunk's largest
+    nps = sorted((((np.diff(s.K.row_ptr) * 6) + 63) // 64 * 64).tolist(), reverse=True)
+    ranges, lead = 0, None
+    for v in nps:
+        if lead is None or 5 * v < 4 * lead:
+            ranges, lead = ranges + 1, v
+    assert inf["nchunks"] == ranges and mb == inf["meta_bytes"] > 0
     full = inf["ws_full_bytes"]
     p.configure(opts, full // 3)
     assert p.info()["nchunks"] >= 3
@@ -284,7 +291,7 @@ def test_noalloc_refuses_plans_beyond_its_array(L, box64):
     p = Plan(s.K.nb, s.K.bs, s.K.row_ptr, s.K.col_idx)
     opts = L.default_opts("fp16")
     p.configure(opts, 1 << 30)
-    assert p.info()["nchunks"] == 1
+    assert p.info()["ws_full_bytes"] > L.NOALLOC_WS_BYTES
     rc = L.lib().nolsm_sign_batch_noalloc(p.h, None, None, 0.0, C.byref(opts), None, None, None, None)
     assert rc == L.E_WORKSPACE
     assert b"scratch array" in L.lib().nolsm_strerror(rc)
