@@ -121,6 +121,23 @@ template <typename T, typename G> __device__ __forceinline__ void g2s_tile(T (*s
         }
     }
 }
+// the same copy, transposed: s[c][r] = g[r][c]
+template <typename T, typename G> __device__ __forceinline__ void g2s_tile_t(T (*s)[LDP], const G *g, int64_t ld) {
+    const int t = threadIdx.x;
+    const int c4 = (t & 15) * 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = i * 16 + (t >> 4);
+        if constexpr (sizeof(G) == 8) {
+            const double2 *p = (const double2 *)(g + (int64_t)r * ld + c4);
+            const double2 x = p[0], y = p[1];
+            s[c4][r] = (T)x.x; s[c4 + 1][r] = (T)x.y; s[c4 + 2][r] = (T)y.x; s[c4 + 3][r] = (T)y.y;
+        } else {
+            const float4 x = *(const float4 *)(g + (int64_t)r * ld + c4);
+            s[c4][r] = (T)x.x; s[c4 + 1][r] = (T)x.y; s[c4 + 2][r] = (T)x.z; s[c4 + 3][r] = (T)x.w;
+        }
+    }
+}
 template <typename T, typename G> __device__ __forceinline__ void s2g_tile(G *g, int64_t ld, const T (*s)[LDP]) {
     const int t = threadIdx.x;
     const int c4 = (t & 15) * 4;

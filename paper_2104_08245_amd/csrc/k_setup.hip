@@ -553,13 +553,16 @@ __global__ __launch_bounds__(256, OCC) void k_subst(ChunkDev cd, char *ws) {
 // X_ij = (W_ij - sum_{k<j} X_ik L_jk^T) Dinv_j^T over the column tiles
 // j >= i in order. The tiles left of the diagonal are not solved again:
 // A~ is symmetric, so X_ik = X_ki^T for k < i, final since the launch of row
-// block k; they are copied into place and feed the recursion, which saves a
-// third of the right solve's products. A~ - mu I has the spectrum of A_J;
-// being symmetric, its column sums are its row sums. Emits the bounds inputs
-// in the layout of k_subst (row sums per column tile, column sums, Frobenius
-// partials, here per row block) and takes mu off the diagonal once the row
-// block is complete. RR column tiles per pass with their accumulators in
-// registers.
+// block k, which saves a third of the right solve's products; they are read
+// transposed from the upper triangle and never stored below it (nothing after
+// this kernel reads A~ below its diagonal tiles). A~ - mu I has the spectrum
+// of A_J. Bounds inputs in the layout of k_subst: each tile writes the row
+// sums of its rows, and an off-diagonal tile also its column sums, which are
+// the row sums of its mirror X_ji; the Frobenius partial of row block i
+// counts every off-diagonal tile twice. Being symmetric, the matrix's column
+// sums are its row sums, which the bounds kernel takes from the row sums. mu
+// is taken off the diagonal once the row block is complete. RR column tiles
+// per pass with their accumulators in registers.
 // ---------------------------------------------------------------------------
 template <typename T, int RR, int OCC>
 __global__ __launch_bounds__(256, OCC) void k_rsolve(ChunkDev cd, char *ws, int i) {
@@ -579,36 +582,18 @@ __global__ __launch_bounds__(256, OCC) void k_rsolve(ChunkDev cd, char *ws, int 
     const T *L = (const T *)(ws + (l32 ? M.offL32 : M.offL));
     const T *Dinv = (const T *)(ws + (l32 ? M.offDinv32 : M.offDinv));
     double *Kb = (double *)(ws + M.offK);
+    double *rowp = (double *)(ws + M.offRow);
     auto Lt = [&](int r, int c) { return L + (int64_t)(r * 64) * ldl + c * 64; };
-    auto Xt = [&](int j) { return Kb + (int64_t)(i * 64) * ldk + j * 64; };   // tile (i, j)
+    auto Xt = [&](int j) { return Kb + (int64_t)(i * 64) * ldk + j * 64; };   // tile (i, j), j >= i
+    auto Ut = [&](int k) { return Kb + (int64_t)(k * 64) * ldk + i * 64; };   // tile (k, i) = X_ik^T
+    // X_ik into LDS: the tile itself on and right of the diagonal, the
+    // transpose of X_ki left of it
+    auto load_x = [&](int k) {
+        if (k < i) g2s_tile_t(sX, Ut(k), ldk);
+        else g2s_tile(sX, Xt(k), ldk);
+    };
     const int t = threadIdx.x;
-    double rtot = 0.0, frob = 0.0;
-    // tiles k < i: X_ik = X_ki^T (off the diagonal, never shifted by mu)
-    for (int k = 0; k < i; ++k) {
-        g2s_tile(sX, Kb + (int64_t)(k * 64) * ldk + i * 64, ldk);   // tile (k, i)
-        __syncthreads();
-        double *dst = Xt(k);
-        for (int f = t; f < 4096; f += 256) {
-            const int rr = f >> 6, q = f & 63;
-            dst[(int64_t)rr * ldk + q] = (double)sX[q][rr];
-        }
-        if (t < 64) {
-            const int gr = i * 64 + t;
-            double rs = 0.0;
-            for (int q = 0; q < 64; ++q)
-                if (k * 64 + q < n) rs += fabs((double)sX[q][t]);
-            double *rowp = (double *)(ws + M.offRow);
-            rowp[(int64_t)k * np + gr] = (gr < n) ? rs : 0.0;
-            rtot += rs;
-        }
-        double fs = 0.0;
-        for (int f = t; f < 4096; f += 256) {
-            const int rr = f >> 6, q = f & 63;
-            if (i * 64 + rr < n && k * 64 + q < n) fs += (double)sX[q][rr] * (double)sX[q][rr];
-        }
-        frob += fs;
-        __syncthreads();
-    }
+    double frob = 0.0;
     for (int j0 = i; j0 < P; j0 += RR) {
         const int nr = min(RR, P - j0);
         AccT<T> acc[RR];
@@ -623,7 +608,7 @@ __global__ __launch_bounds__(256, OCC) void k_rsolve(ChunkDev cd, char *ws, int 
             g2r_tile(pl, Lt(j0, 0), ldl);
             r2s_tile(sL, pl);
             for (int k = 0; k < j0; ++k) {
-                g2s_tile(sX, Xt(k), ldk);
+                load_x(k);
                 __syncthreads();
 #pragma unroll
                 for (int r = 0; r < RR; ++r) {
@@ -663,16 +648,21 @@ __global__ __launch_bounds__(256, OCC) void k_rsolve(ChunkDev cd, char *ws, int 
                         double rs = 0.0;
                         for (int q = 0; q < 64; ++q)
                             if (j * 64 + q < n) rs += fabs(a(t, q));
-                        double *rowp = (double *)(ws + M.offRow);
                         rowp[(int64_t)j * np + gr] = (gr < n) ? rs : 0.0;
-                        rtot += rs;
+                    } else if (t < 128 && j > i) {
+                        // row sums of the mirror tile X_ji over column tile i
+                        const int gc = j * 64 + t - 64;
+                        double cs = 0.0;
+                        for (int rr = 0; rr < 64; ++rr)
+                            if (i * 64 + rr < n) cs += fabs(a(rr, t - 64));
+                        rowp[(int64_t)i * np + gc] = (gc < n) ? cs : 0.0;
                     }
                     double fs = 0.0;
                     for (int f = t; f < 4096; f += 256) {
                         const int rr = f >> 6, q = f & 63;
                         if (i * 64 + rr < n && j * 64 + q < n) fs += a(rr, q) * a(rr, q);
                     }
-                    frob += fs;
+                    frob += (j > i) ? 2.0 * fs : fs;
                 }
                 s2g_tile(Xt(j), ldk, sX);   // X_ij, kept in sX for the tiles to its right
 #pragma unroll
@@ -688,13 +678,8 @@ __global__ __launch_bounds__(256, OCC) void k_rsolve(ChunkDev cd, char *ws, int 
             }
         }
     }
-    // the row block is final: take mu off its diagonal; column sums of the
-    // symmetric matrix are its row sums
-    if (t < 64) {
-        Kb[(int64_t)(i * 64 + t) * ldk + i * 64 + t] -= mu;
-        double *colp = (double *)(ws + M.offCol);
-        colp[i * 64 + t] = (i * 64 + t < n) ? rtot : 0.0;
-    }
+    // the row block is final: take mu off its diagonal
+    if (t < 64) Kb[(int64_t)(i * 64 + t) * ldk + i * 64 + t] -= mu;
     const double fsum = block_sum(frob, red);
     if (t == 0) ((double *)(ws + M.offCol))[np + i] = fsum;
 }
@@ -731,7 +716,8 @@ __global__ __launch_bounds__(256) void k_bounds(ChunkDev cd, char *ws, BoundsArg
         double rs = 0;
         for (int c = 0; c < P; ++c) rs += rowp[(int64_t)c * np + r];
         const double R = rs - fabs(d);
-        const double C = colp[r] - fabs(d);
+        // symmetric route: the column sums are the row sums
+        const double C = (ba.sym ? rs : colp[r]) - fabs(d);
         dsum += d; dsq += d * d; dmin = fmin(dmin, d); dmax = fmax(dmax, d);
         rsum += R; rmax = fmax(rmax, R);
         rlo = fmin(rlo, d - R); rhi = fmax(rhi, d + R);
