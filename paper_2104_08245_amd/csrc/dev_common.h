@@ -211,6 +211,12 @@ template <typename T, typename G> __device__ __forceinline__ void g2acc(AccT<T> 
             for (int e = 0; e < 4; ++e) a.c[i][j][e] = (T)g[(int64_t)acc_row<T>(i, e) * ld + acc_col(j)];
 }
 
+// element idx of a slot's K buffer, stored in FP32 when the substitution
+// runs in FP32 arithmetic (SubMeta::kf32), else in FP64
+__device__ __forceinline__ double kbuf_get(const SubMeta &M, const char *ws, int64_t idx) {
+    return M.kf32 ? (double)((const float *)(ws + M.offK))[idx] : ((const double *)(ws + M.offK))[idx];
+}
+
 // deterministic block reductions (256 threads); `red` is LDS scratch of 256
 __device__ __forceinline__ double block_sum(double v, double *red) {
     const int t = threadIdx.x;

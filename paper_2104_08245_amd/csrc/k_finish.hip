@@ -44,7 +44,7 @@ __device__ __forceinline__ TV vec_in(const SkinnyArgs &a, const SubMeta &M, cons
     const int64_t vs = (int64_t)np * 6 * 8 / sizeof(TV);   // stride between vectors
     const TV *V = (const TV *)(ws + M.offVec) + (int64_t)o * NOLSM_NVEC * vs;
     auto get = [&](int idx) -> TV {
-        if (idx == -1) return (TV)((const double *)(ws + M.offK))[(int64_t)row * (np + 64) + np + o * bs + j];
+        if (idx == -1) return (TV)kbuf_get(M, ws, (int64_t)row * (np + 64) + np + o * bs + j);
         return V[(int64_t)idx * vs + (int64_t)row * 6 + j];
     };
     TV v = (TV)a.alpha * get(a.ina);
@@ -169,7 +169,6 @@ __global__ __launch_bounds__(FIN_THREADS, 1) void k_finish_f16(ChunkDev cd, char
     const uint16_t *P = (const uint16_t *)(ws + ((ctl->iters & 1) ? M.offX1 : M.offX0));
     const int64_t vs = (int64_t)np * 12;   // floats per vector slot (np x 6 doubles reserved)
     float *V = (float *)(ws + M.offVec) + (int64_t)o * NOLSM_NVEC * vs;
-    const double *Kb = (const double *)(ws + M.offK);
     for (int f = t; f < 4 * ldb; f += FIN_THREADS) vb[12 * ldb + f] = 0;   // columns 12..15 of B
     for (int step = 0; step < nsteps; ++step) {
         const FinStep S = fin_steps[step];
@@ -179,7 +178,7 @@ __global__ __launch_bounds__(FIN_THREADS, 1) void k_finish_f16(ChunkDev cd, char
             float v = 0.0f;
             if (j < bs) {
                 auto get = [&](int idx) -> float {
-                    if (idx == -1) return (float)Kb[(int64_t)r * (np + 64) + np + o * bs + j];
+                    if (idx == -1) return (float)kbuf_get(M, ws, (int64_t)r * (np + 64) + np + o * bs + j);
                     return V[(int64_t)idx * vs + (int64_t)r * 6 + j];
                 };
                 v = S.alpha * get(S.ina);
@@ -332,7 +331,6 @@ __global__ __launch_bounds__(256) void k_extract(ChunkDev cd, char *ws, ExtractA
     int *rows = (int *)(smem + (size_t)cd.max_np * bs);   // row blocks of the submatrix
     for (int i = t; i < M.m; i += 256) rows[i] = ea.grp_blk[M.sub_off + i];
     const bool ok = ctl->status != NOLSM_MOL_NOT_SPD;
-    const double *Kb = (const double *)(ws + M.offK);
     const int64_t vs = (int64_t)np * 6 * 8 / sizeof(TV);
     for (int o = 0; o < M.nown; ++o) {
         const int J = ea.own_J[M.own_off + o];
@@ -343,7 +341,7 @@ __global__ __launch_bounds__(256) void k_extract(ChunkDev cd, char *ws, ExtractA
             const int r = f / bs, c = f % bs;
             double v = 0.0;
             if (ok && r < n) {
-                const double y = Kb[(int64_t)r * (np + 64) + np + o * bs + c];
+                const double y = kbuf_get(M, ws, (int64_t)r * (np + 64) + np + o * bs + c);
                 const int64_t q = (int64_t)r * 6 + c;
                 double z;
                 if (ea.nfinal == 0)
@@ -451,14 +449,18 @@ __global__ __launch_bounds__(256) void k_wcols(ChunkDev cd, char *ws, ExtractArg
 #pragma unroll
     for (int j = 0; j < BSMAX; ++j) acc[j] = 0.0;
     if (ok) {
-        const double *arow = (const double *)(ws + M.offK) + (int64_t)gr * (np + 64);
+        auto row_times = [&](auto arow) {
 #pragma unroll 4
-        for (int k = 0; k < n; k += 2) {   // n = bs m is even for bs = 6
-            const double2 a = *(const double2 *)(arow + k);
+            for (int k = 0; k < n; k += 2) {   // n = bs m is even for bs = 6
+                const double ax = arow[k], ay = arow[k + 1];
 #pragma unroll
-            for (int j = 0; j < BSMAX; ++j)
-                if (j < bs) acc[j] += a.x * dcs[k * bs + j] + a.y * dcs[(k + 1) * bs + j];
-        }
+                for (int j = 0; j < BSMAX; ++j)
+                    if (j < bs) acc[j] += ax * dcs[k * bs + j] + ay * dcs[(k + 1) * bs + j];
+            }
+        };
+        // A_J row gr of the K buffer, FP32 or FP64 storage
+        if (M.kf32) row_times((const float *)(ws + M.offK) + (int64_t)gr * (np + 64));
+        else row_times((const double *)(ws + M.offK) + (int64_t)gr * (np + 64));
 #pragma unroll
         for (int j = 0; j < BSMAX; ++j)
             if (j < bs) acc[j] += mu * dcs[gr * bs + j];

@@ -86,14 +86,13 @@ template <typename T> __device__ __forceinline__ T to_t_d(double x) { return (T)
 template <typename T, typename Cvt>
 __device__ void restart_tile(const SubMeta &M, const SubCtl *ctl, const char *ws, T *Xn, int r0, int c0,
                              int rows, int cols, Cvt cvt, bool sym = false) {
-    const double *A = (const double *)(ws + M.offK);
     const int64_t ldk = M.np + 64;
     const double c = ctl->scale_g;
     for (int f = threadIdx.x; f < rows * cols; f += blockDim.x) {
         const int r = r0 + f / cols, q = c0 + f % cols;
         if (r >= M.np || q >= M.np) continue;
         const int ra = sym ? min(r, q) : r, qa = sym ? max(r, q) : q;
-        const double v = (r < M.n && q < M.n) ? c * A[(int64_t)ra * ldk + qa] : (r == q ? 1.0 : 0.0);
+        const double v = (r < M.n && q < M.n) ? c * kbuf_get(M, ws, (int64_t)ra * ldk + qa) : (r == q ? 1.0 : 0.0);
         Xn[(int64_t)r * M.ldx + q] = cvt(v);
     }
 }

@@ -56,7 +56,12 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
         }
     }
     __syncthreads();
-    double *Kd = (double *)(ws + M.offK);
+    double *Kd = (double *)(ws + M.offK);   // T_J(K) in FP64, or
+    float *Kf = (float *)(ws + M.offK);     // in FP32 when the substitution runs in FP32
+    auto put_k = [&](int64_t idx, double v) {
+        if (M.kf32) Kf[idx] = (float)v;
+        else Kd[idx] = v;
+    };
     double *Sd = (double *)(ws + M.offL);   // T_J(S) in FP64, or
     float *Sf = (float *)(ws + M.offL);     // in FP32 for the FP32 Cholesky route
     auto put_s = [&](int64_t idx, double v) {
@@ -83,7 +88,7 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
             if (ws_ && es >= 0) vs = ga.Sval[(int64_t)es * bb + r * bs + cc];
         }
         if (poison && i == 0) vs = -1.0;
-        if (wk) Kd[(int64_t)(a * bs + r) * ldk + c] = vk;
+        if (wk) put_k((int64_t)(a * bs + r) * ldk + c, vk);
         if (ws_) put_s((int64_t)(a * bs + r) * lds + c, vs);
     }
     // E tile: columns np..np+63 of the K buffer; owned molecule o (block
@@ -93,7 +98,7 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
         if (ga.own_pos[M.own_off + o] == a) own_here = o;
     for (int i = t; i < bs * 64; i += 256) {
         const int r = i / 64, c = i % 64;
-        Kd[(int64_t)(a * bs + r) * ldk + np + c] = (own_here >= 0 && c == own_here * bs + r) ? 1.0 : 0.0;
+        put_k((int64_t)(a * bs + r) * ldk + np + c, (own_here >= 0 && c == own_here * bs + r) ? 1.0 : 0.0);
     }
     // padding rows (one workgroup per submatrix does it)
     if (a == 0 && np > n) {
@@ -104,7 +109,7 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
         }
         for (int i = t; i < rows * (np + 64); i += 256) {
             const int r = n + i / (np + 64), c = i % (np + 64);
-            Kd[(int64_t)r * (np + 64) + c] = 0.0;
+            put_k((int64_t)r * (np + 64) + c, 0.0);
         }
     }
 }
@@ -335,7 +340,8 @@ __global__ __launch_bounds__(256, OCC) void k_subst(ChunkDev cd, char *ws) {
     const bool l32 = sizeof(T) == 4 && M.offL32;
     const T *L = (const T *)(ws + (l32 ? M.offL32 : M.offL));
     const T *Dinv = (const T *)(ws + (l32 ? M.offDinv32 : M.offDinv));
-    double *Kb = (double *)(ws + M.offK);
+    // the K buffer is stored in the arithmetic type (SubMeta::kf32 <=> FP32)
+    T *Kb = (T *)(ws + M.offK);
     auto Lt = [&](int r, int c) { return L + (int64_t)(r * 64) * ldl + c * 64; };
     auto Bt = [&](int c, int r) {   // row tile r of this task's column c
         const int col0 = (cc + c < P) ? (cc + c) * 64 : np;
@@ -581,7 +587,7 @@ __global__ __launch_bounds__(256, OCC) void k_rsolve(ChunkDev cd, char *ws, int 
     const bool l32 = sizeof(T) == 4 && M.offL32;
     const T *L = (const T *)(ws + (l32 ? M.offL32 : M.offL));
     const T *Dinv = (const T *)(ws + (l32 ? M.offDinv32 : M.offDinv));
-    double *Kb = (double *)(ws + M.offK);
+    T *Kb = (T *)(ws + M.offK);   // in the arithmetic type (SubMeta::kf32 <=> FP32)
     double *rowp = (double *)(ws + M.offRow);
     auto Lt = [&](int r, int c) { return L + (int64_t)(r * 64) * ldl + c * 64; };
     auto Xt = [&](int j) { return Kb + (int64_t)(i * 64) * ldk + j * 64; };   // tile (i, j), j >= i
@@ -705,14 +711,13 @@ __global__ __launch_bounds__(256) void k_bounds(ChunkDev cd, char *ws, BoundsArg
     SubCtl *ctl = cd.ctl + s;
     if (ctl->status != NOLSM_MOL_OK) return;
     const int n = M.n, np = M.np, P = M.P, t = threadIdx.x;
-    const double *Kb = (const double *)(ws + M.offK);
     const double *rowp = (const double *)(ws + M.offRow);
     const double *colp = (const double *)(ws + M.offCol);
     const int64_t ldk = np + 64;
     double dsum = 0, dsq = 0, dmin = 1e300, dmax = -1e300;
     double rsum = 0, rmax = -1e300, rlo = 1e300, rhi = -1e300, clo = 1e300, chi = -1e300;
     for (int r = t; r < n; r += 256) {
-        const double d = Kb[(int64_t)r * ldk + r];
+        const double d = kbuf_get(M, ws, (int64_t)r * ldk + r);
         double rs = 0;
         for (int c = 0; c < P; ++c) rs += rowp[(int64_t)c * np + r];
         const double R = rs - fabs(d);
@@ -816,13 +821,12 @@ __global__ __launch_bounds__(256) void k_convert(ChunkDev cd, char *ws, int use_
     if (ctl->status != NOLSM_MOL_OK) return;
     const double c = use_scale_g ? ctl->scale_g : ctl->scale;
     const int n = M.n, np = M.np;
-    const double *A = (const double *)(ws + M.offK);
     T *X = (T *)(ws + M.offX0);
     const int64_t ldk = np + 64;
     for (int f = threadIdx.x; f < 4096; f += 256) {
         const int r = ti * 64 + (f >> 6), q = tj * 64 + (f & 63);
         const int ra = (SYM && r > q) ? q : r, qa = (SYM && r > q) ? r : q;
-        const double v = (r < n && q < n) ? c * A[(int64_t)ra * ldk + qa] : (r == q ? 1.0 : 0.0);
+        const double v = (r < n && q < n) ? c * kbuf_get(M, ws, (int64_t)ra * ldk + qa) : (r == q ? 1.0 : 0.0);
         const T x = cvt<T>(v);
         X[(int64_t)r * M.ldx + q] = x;
         if constexpr (SYM) tt[f & 63][f >> 6] = x;

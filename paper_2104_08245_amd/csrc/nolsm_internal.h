@@ -26,8 +26,11 @@ struct SubMeta {
     int32_t own_off;  // their offset in the owned-molecule list
     int32_t pmin;     // smallest block position of an owned molecule (first
                       // nonzero row block of the E columns)
+    int32_t kf32;     // the K buffer holds FP32 values (the substitution runs
+                      // in FP32 arithmetic), else FP64
+    int32_t pad_;
     int64_t offL;     // np*np doubles (FP32 Cholesky route: floats): S -> L; later X buffer 0
-    int64_t offK;     // np*(np+64) doubles: K -> W -> [A | Y]
+    int64_t offK;     // np*(np+64) values (FP64, or FP32 if kf32): K -> W -> [A | Y]
     int64_t offDinv;  // P*64*64 doubles (or floats): inverses of the diagonal tiles of L
     int64_t offRow;   // (P+1)*np doubles: partial |A| row sums per column tile
     int64_t offCol;   // np doubles col sums of |A|, then 64 more: P frob partials

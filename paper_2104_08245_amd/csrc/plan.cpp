@@ -64,7 +64,9 @@ size_t nolsm_slot_bytes(int32_t np, int32_t ns_tile, int32_t elem, int32_t max_i
     const size_t nt = (n + ns_tile - 1) / ns_tile;
     size_t b = 0;
     b += align256(n * n * 8);                 // L / X0
-    b += align256(n * (n + 64) * 8);          // K / W / A|Y
+    // K / W / A|Y: FP32 when the substitution runs in FP32 arithmetic
+    const bool kf32 = inverse == NOLSM_INV_CHOLESKY_FP32 || inverse == NOLSM_INV_CHOLESKY_APPLY_FP32;
+    b += align256(n * (n + 64) * (kf32 ? 4 : 8));
     b += align256(P * 64 * 64 * 8);           // Dinv
     b += align256((P + 1) * n * 8);           // row partials
     b += align256((n + 64) * 8);              // col sums + frob partials
@@ -540,7 +542,9 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
                 m.ntile_ns = nt * nt;
                 const size_t n = (size_t)m.np;
                 m.offL = (int64_t)off; off += align256(n * n * 8);
-                m.offK = (int64_t)off; off += align256(n * (n + 64) * 8);
+                m.kf32 = (pl->inverse == NOLSM_INV_CHOLESKY_FP32 || pl->inverse == NOLSM_INV_CHOLESKY_APPLY_FP32) ? 1 : 0;
+                m.pad_ = 0;
+                m.offK = (int64_t)off; off += align256(n * (n + 64) * (m.kf32 ? 4 : 8));
                 m.offDinv = (int64_t)off; off += align256((size_t)m.P * 4096 * 8);
                 m.offRow = (int64_t)off; off += align256((size_t)(m.P + 1) * n * 8);
                 m.offCol = (int64_t)off; off += align256((n + 64) * 8);
