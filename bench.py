@@ -279,7 +279,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--prec", default="fp16", choices=list(PEAK_TFLOPS))
-    ap.add_argument("--ws-gb", type=float, default=96.0)
+    ap.add_argument("--ws-gb", type=float, default=160.0)
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")

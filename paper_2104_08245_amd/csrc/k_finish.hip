@@ -356,7 +356,11 @@ __global__ __launch_bounds__(256) void k_extract(ChunkDev cd, char *ws, ExtractA
         }
         __syncthreads();
         if (ea.sym && ok) {
+            // the FP32 factor, or the FP32 copy of the FP64 factor where the
+            // route applies it in FP32, else the FP64 factor
             if (ea.L_fp32) back_solve_lt((const float *)(ws + M.offL), (const float *)(ws + M.offDinv), M, Df, tmp, bs);
+            else if (M.offL32)
+                back_solve_lt((const float *)(ws + M.offL32), (const float *)(ws + M.offDinv32), M, Df, tmp, bs);
             else back_solve_lt((const double *)(ws + M.offL), (const double *)(ws + M.offDinv), M, Df, tmp, bs);
         }
         // the owned columns on the rows N(J) (the pattern of D), through
