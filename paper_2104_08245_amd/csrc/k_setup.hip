@@ -211,6 +211,190 @@ template <typename T> __device__ void trinv64_reg(const T (*Lt)[LDP], T *Dg, T *
         for (int i = 0; i < 16; ++i) Df[(w + 4 * i) * 64 + c] = (float)b[i];
 }
 
+// FP64 Cholesky and inverse of the 64x64 tile in LDS by 16x16 blocks,
+// right-looking. For block column b: wave 0 factors the diagonal block and
+// inverts it in registers (M_b = L_bb^-1; a chain of 16 steps whose
+// exchanges are lane shuffles, with no workgroup barrier); the blocks below
+// become L_ib = A_ib M_b^T (one wave each), then the trailing blocks take
+// A_ij -= L_ib L_jb^T (round robin over the waves), all on the FP64 matrix
+// cores (v_mfma_f64_16x16x4). The inverse of L follows by block columns, one
+// wave each: (L^-1)_bb = M_b, (L^-1)_ib = -M_i sum_{b<=k<i} L_ik (L^-1)_kb.
+// A block in registers uses the accumulator layout of the FP64 16x16x4
+// product: lane l, element e holds row (l >> 4) + 4e, column l & 15. That is
+// also the layout of a B operand chunk (rows 4kk + (l >> 4) in element kk),
+// so a block in registers multiplies from the right without staging. The
+// upper blocks of the tile (zero in L) keep M_0..M_3 until the end. The
+// factor (zeros above the diagonal) is left in sA; the inverse goes from
+// registers to the global 64x64 row-major Dg (and its FP32 copy to Df). A
+// non-positive pivot sets *fail.
+__device__ __forceinline__ void mblk_pos(int b, int &bi, int &bj) {
+    bi = (b == 3) ? 1 : 0;
+    bj = (b == 3) ? 2 : b + 1;
+}
+__device__ void chol16_wave(double v[4], int &bad) {
+    const int l = threadIdx.x & 63, g = l >> 4, q = l & 15;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const double d = __shfl(v[c >> 2], c + 16 * (c & 3), 64);   // A[c][c]
+        bad |= !(d > 0.0);
+        const double piv = sqrt(fmax(d, 1e-300));
+        const double rp = 1.0 / piv;
+        double colr[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) colr[e] = __shfl(v[e], c + 16 * g, 64);   // A[g + 4e][c]
+        // A[c][q], equal to A[q][c]: the trailing matrix is updated on both
+        // sides of its diagonal, so it stays symmetric
+        const double lq = __shfl(v[c >> 2], q + 16 * (c & 3), 64) * rp;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = g + 4 * e;
+            const double lr = colr[e] * rp;
+            if (q == c) {
+                if (r > c) v[e] = lr;
+                else if (r == c) v[e] = piv;
+            } else if (q > c && r > c) {
+                v[e] -= lr * lq;
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (g + 4 * e < q) v[e] = 0.0;
+}
+// M = L^-1 for the lower-triangular 16x16 L in registers: M = I, then for
+// each pivot row p, row p of M is scaled by 1 / L[p][p] (final) and taken
+// off the rows below it, L[r][p] times.
+__device__ void inv16_wave(const double v[4], double m[4]) {
+    const int l = threadIdx.x & 63, g = l >> 4, q = l & 15;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) m[e] = (g + 4 * e == q) ? 1.0 : 0.0;
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+        const double lpp = __shfl(v[p >> 2], p + 16 * (p & 3), 64);
+        if (g == (p & 3)) m[p >> 2] /= lpp;
+        const double xq = __shfl(m[p >> 2], q + 16 * (p & 3), 64);   // M[p][q], final
+        double lrp[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) lrp[e] = __shfl(v[e], p + 16 * g, 64);   // L[g + 4e][p]
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (g + 4 * e > p) m[e] -= lrp[e] * xq;
+    }
+}
+__device__ void chol_inv64_blocked(double (*sA)[LDP], double *Dg, float *Df, int *fail) {
+    const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), l = t & 63, g = l >> 4, q = l & 15;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        if (w == 0) {
+            double v[4], m[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = sA[16 * b + g + 4 * e][16 * b + q];
+            int bad = 0;
+            chol16_wave(v, bad);
+            inv16_wave(v, m);
+            int bi, bj;
+            mblk_pos(b, bi, bj);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                sA[16 * b + g + 4 * e][16 * b + q] = v[e];
+                sA[16 * bi + g + 4 * e][16 * bj + q] = m[e];
+            }
+            if (bad && l == 0) *fail = 1;
+        }
+        __syncthreads();
+        if (b == 3) break;
+        {
+            // L_ib = A_ib M_b^T: B[k][q] = M_b[q][k]
+            const int i = b + 1 + w;
+            if (i < 4) {
+                int bi, bj;
+                mblk_pos(b, bi, bj);
+                v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = 4 * kk + g;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[16 * i + q][16 * b + k],
+                                                               sA[16 * bi + q][16 * bj + k], acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) sA[16 * i + g + 4 * e][16 * b + q] = acc[e];
+            }
+        }
+        __syncthreads();
+        {
+            // A_ij -= L_ib L_jb^T, b < j <= i: B[k][q] = L_jb[q][k]
+            int task = 0;
+#pragma unroll
+            for (int i = b + 1; i < 4; ++i)
+#pragma unroll
+                for (int j = b + 1; j <= i; ++j, ++task) {
+                    if ((task & 3) != w) continue;
+                    v4d acc;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[e] = sA[16 * i + g + 4 * e][16 * j + q];
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        const int k = 4 * kk + g;
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-sA[16 * i + q][16 * b + k],
+                                                                   sA[16 * j + q][16 * b + k], acc, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) sA[16 * i + g + 4 * e][16 * j + q] = acc[e];
+                }
+        }
+        __syncthreads();
+    }
+    {
+        // block column w of L^-1, kept in registers
+        v4d X[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) X[i] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (b != w) continue;
+            int bi, bj;
+            mblk_pos(b, bi, bj);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) X[b][e] = sA[16 * bi + g + 4 * e][16 * bj + q];
+#pragma unroll
+            for (int i = b + 1; i < 4; ++i) {
+                v4d s = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int k = b; k < i; ++k)
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+                        s = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[16 * i + q][16 * k + 4 * kk + g], X[k][kk], s,
+                                                                 0, 0, 0);
+                int ni, nj;
+                mblk_pos(i, ni, nj);
+                v4d r = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    r = __builtin_amdgcn_mfma_f64_16x16x4f64(-sA[16 * ni + q][16 * nj + 4 * kk + g], s[kk], r, 0, 0, 0);
+                X[i] = r;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = 16 * i + g + 4 * e, col = 16 * w + q;
+                const double x = (i >= w) ? X[i][e] : 0.0;
+                Dg[row * 64 + col] = x;
+                if (Df) Df[row * 64 + col] = (float)x;
+            }
+    }
+    __syncthreads();
+    // the upper blocks are zero in L
+    for (int f = t; f < 6 * 256; f += 256) {
+        const int blk = f >> 8, e = f & 255;
+        const int bi = (blk < 3) ? 0 : (blk < 5 ? 1 : 2);
+        const int bj = (blk < 3) ? blk + 1 : (blk < 5 ? blk - 1 : 3);
+        sA[16 * bi + (e >> 4)][16 * bj + (e & 15)] = 0.0;
+    }
+    __syncthreads();
+}
+
 // Panel j, diagonal tile: L_jj L_jj^T = S_jj - sum_{k<j} L_jk L_jk^T, and
 // its inverse. One workgroup per submatrix with P > j. A non-positive pivot
 // marks the submatrix NOT_SPD; its later launches then skip it.
@@ -242,15 +426,23 @@ __global__ __launch_bounds__(256, 3) void k_chol_diag(ChunkDev cd, char *ws, int
     }
     acc2s(sA, acc);
     __syncthreads();
-    potrf64_reg(sA, cb, &fail);
-    if (fail) {
-        if (threadIdx.x == 0) { ctl->status = NOLSM_MOL_NOT_SPD; ctl->done = 1; }
-        return;
-    }
     // FP64 factor applied in FP32: the tile and its inverse also in FP32
     float *L32 = M.offL32 ? (float *)(ws + M.offL32) : nullptr;
     float *D32 = M.offDinv32 ? (float *)(ws + M.offDinv32) + (int64_t)j * 4096 : nullptr;
-    trinv64_reg(sA, Dinv + (int64_t)j * 4096, rd, cb, D32);
+    if constexpr (sizeof(T) == 8) {
+        chol_inv64_blocked(sA, Dinv + (int64_t)j * 4096, D32, &fail);
+        if (fail) {
+            if (threadIdx.x == 0) { ctl->status = NOLSM_MOL_NOT_SPD; ctl->done = 1; }
+            return;
+        }
+    } else {
+        potrf64_reg(sA, cb, &fail);
+        if (fail) {
+            if (threadIdx.x == 0) { ctl->status = NOLSM_MOL_NOT_SPD; ctl->done = 1; }
+            return;
+        }
+        trinv64_reg(sA, Dinv + (int64_t)j * 4096, rd, cb, D32);
+    }
     s2g_tile(Lt(j, j), ld, sA);
     if (L32) s2g_tile(L32 + (int64_t)(j * 64) * ld + j * 64, ld, sA);
 }
