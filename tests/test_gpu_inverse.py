@@ -10,7 +10,11 @@ iteration); the sign of A_J amplifies the error of A_J by about 1 / gap
 (gap ~ 0.23 for this generator, a factor ~4), so Dcols is held to 3e-2
 relative in FP16 and 8x that in BF16 (3 fewer mantissa bits): 2.5e-1. The
 energies follow from Dcols: |dE_J| = |tr(K_J[cJ, :] dDcols_J)| <=
-||K_J[cJ, :]||_F ||dDcols_J||_F, checked with the same relative bound.
+||K_J[cJ, :]||_F ||dDcols_J||_F, checked with the same relative bound, and
+held besides to an absolute per-molecule bound: measured on the 64-molecule
+box, max |dE_J| is 0.168 (mean 0.037) in FP16 and 0.951 (mean 0.308) in
+BF16, about a hundred times the Cholesky route's; the bounds are twice the
+measured maxima and means.
 """
 import sys
 
@@ -22,6 +26,7 @@ from oracle import nolsm as o
 pytestmark = pytest.mark.gpu
 
 BOUNDS = {"fp16": 3e-2, "bf16": 2.5e-1}
+ENERGY_ABS = {"fp16": dict(max=0.34, mean=0.074), "bf16": dict(max=1.9, mean=0.62)}
 
 
 def say(*a):
@@ -68,6 +73,7 @@ def test_coupled_inverse_route_matches_oracle(torch, box64, ref1, prec):
         f"|dE| max {dE.max():.3e} mean {dE.mean():.3e}; inverse iterations "
         f"{st['iters_inv'].min()}..{st['iters_inv'].max()}")
     assert errs.max() <= BOUNDS[prec]
+    assert dE.max() <= ENERGY_ABS[prec]["max"] and dE.mean() <= ENERGY_ABS[prec]["mean"]
     for J in range(box64.nmol):
         KJ, _, _, p = o.submatrix(box64, J)
         krows = KJ[6 * p:6 * p + 6, :]
