@@ -399,9 +399,10 @@ __device__ void chol_inv64_blocked(double (*sA)[LDP], double *Dg, float *Df, int
 // its inverse. One workgroup per submatrix with P > j. A non-positive pivot
 // marks the submatrix NOT_SPD; its later launches then skip it.
 template <typename T>
-__global__ __launch_bounds__(256, 3) void k_chol_diag(ChunkDev cd, char *ws, int j) {
-    // one tile (33 KB in FP64) plus small buffers: three workgroups share a
-    // CU, so that the 64-step column chains of one hide those of another
+__global__ __launch_bounds__(256, 4) void k_chol_diag(ChunkDev cd, char *ws, int j) {
+    // one tile (33 KB in FP64) plus small buffers, and at most 128 VGPRs:
+    // four workgroups share a CU, so that the serial chains of one (the
+    // diagonal blocks) hide behind the others
     __shared__ T sA[64][LDP];
     __shared__ T cb[2][64];
     __shared__ T rd[64];
