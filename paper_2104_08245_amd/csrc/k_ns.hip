@@ -305,7 +305,9 @@ template <int BM> __device__ __forceinline__ void sym_store_diag(uint16_t *X, in
 // the tile's share of ||R||_F^2, mode 2 decides stop / continue / restart and
 // forms X_{k+1} = X_k + X_k R / 2. SYM: X_k and R are symmetric, only tiles
 // ti <= tj are launched and each writes its mirror too.
-template <typename T, int BM, bool SYM>
+// DIAG1: the diagonal tiles of X_k^2 take the one-operand product (kept out
+// of the persistent kernel, whose loop would spill with both copies inlined)
+template <typename T, int BM, bool SYM, bool DIAG1 = false>
 __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, char *ws, const NsArgs &na, int it,
                                            int mode) {
     __shared__ double red[256];
@@ -338,7 +340,9 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
     const int row0 = ti * BM, col0 = tj * BM, ldx = M.ldx;
     const int nrec = ldx * ldx * 2;
     v16f acc[NB][NB];
-    lp_tile_product<T, BM, SYM>(Xc, (mode == 1) ? Xc : Bb, ldx, np, row0, col0, acc);
+    // a diagonal tile of X_k^2 (symmetric route) loads its one operand tile once
+    if (DIAG1 && SYM && mode == 1 && ti == tj) lp_tile_product<T, BM, SYM, DIAG1 && SYM>(Xc, Xc, ldx, np, row0, col0, acc);
+    else lp_tile_product<T, BM, SYM>(Xc, (mode == 1) ? Xc : Bb, ldx, np, row0, col0, acc);
     // Epilogue over the whole tile, padding included: rows and columns in
     // [np, ldx) of R and X_{k+1} only ever feed outputs that are never used,
     // so the accesses need no bounds test and the X_k reads of the update
@@ -445,7 +449,7 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
 template <typename T, int BM, bool SYM>
 __global__ __launch_bounds__(256, 3) void k_ns_lp(ChunkDev cd, const uint32_t *tasks, char *ws, NsArgs na, int it,
                                                int mode) {
-    ns_lp_tile<T, BM, SYM>(cd, xcd_task(tasks), ws, na, it, mode);
+    ns_lp_tile<T, BM, SYM, true>(cd, xcd_task(tasks), ws, na, it, mode);
 }
 
 template <typename T, int BM, bool SYM>

@@ -58,10 +58,14 @@ template <int BM> __device__ __forceinline__ uint16_t *lp_lds() {
 // WT = BM / 2). All 256 threads must call it.
 // BSYM: B is symmetric, so B[k][n] = B[n][k] and its tile is loaded by rows
 // exactly like A (no transposition on the way into LDS).
-template <typename T, int BM, bool BSYM = false>
+// SAME (with BSYM): B is A and col0 = row0 (a diagonal tile of X X with X
+// symmetric), so the B tile would equal the A tile: only A is loaded, and the
+// products read both operands from it.
+template <typename T, int BM, bool BSYM = false, bool SAME = false>
 __device__ __forceinline__ void lp_tile_product(const uint16_t *Ag, const uint16_t *Bg, int ldx, int np, int row0,
                                                 int col0, v16f (&acc)[BM / 64][BM / 64]) {
     typedef typename Lp<T>::vec vec;
+    static_assert(!SAME || BSYM, "a shared operand tile needs B loaded by rows like A");
     constexpr int WT = BM / 2;          // wave tile
     constexpr int NB = WT / 32;         // 32x32 MFMA blocks per wave dimension
     constexpr int AQ = BM / 32;         // 16-byte A loads per thread
@@ -117,7 +121,8 @@ __device__ __forceinline__ void lp_tile_product(const uint16_t *Ag, const uint16
             S##a2 = NS_BUF(rsA, oa_, 2 * sa32);                                  \
             S##a3 = NS_BUF(rsA, oa_, 3 * sa32);                                  \
         }                                                                        \
-        if constexpr (BSYM) {                                                    \
+        if constexpr (SAME) {                                                    \
+        } else if constexpr (BSYM) {                                             \
             S##b0 = NS_BUF(rsB, ob_, 0);                                         \
             S##b1 = NS_BUF(rsB, ob_, sa32);                                      \
             if constexpr (AQ > 2) {                                              \
@@ -155,7 +160,8 @@ __device__ __forceinline__ void lp_tile_product(const uint16_t *Ag, const uint16
             *(uint4 *)&sA[buf_][lds_swz((t >> 3) + 64, t & 7)] = S##a2;          \
             *(uint4 *)&sA[buf_][lds_swz((t >> 3) + 96, t & 7)] = S##a3;          \
         }                                                                        \
-        if constexpr (BSYM) {                                                    \
+        if constexpr (SAME) {                                                    \
+        } else if constexpr (BSYM) {                                             \
             *(uint4 *)&sB[buf_][lds_swz(t >> 3, t & 7)] = S##b0;                 \
             *(uint4 *)&sB[buf_][lds_swz((t >> 3) + 32, t & 7)] = S##b1;          \
             if constexpr (AQ > 2) {                                              \
@@ -177,7 +183,7 @@ __device__ __forceinline__ void lp_tile_product(const uint16_t *Ag, const uint16
                 *(const vec *)&sA[bufi][lds_swz(wm * WT + i * 32 + (l & 31),     \
                                                 (kk >> 3) + (l >> 5))];          \
             _Pragma("unroll") for (int j = 0; j < NB; ++j) b[j] =                \
-                *(const vec *)&sB[bufi][lds_swz(wn * WT + j * 32 + (l & 31),     \
+                *(const vec *)&(SAME ? sA : sB)[bufi][lds_swz(wn * WT + j * 32 + (l & 31), \
                                                 (kk >> 3) + (l >> 5))];          \
             _Pragma("unroll") for (int i = 0; i < NB; ++i)                       \
                 _Pragma("unroll") for (int j = 0; j < NB; ++j)                   \
