@@ -314,7 +314,11 @@ int nolsm_plan_groups(const nolsm_plan *plan, int32_t *grp_ptr, int32_t *grp_blk
 /* Chooses the schedule for `opts` and a workspace of ws_bytes: submatrices
  * grouped into chunks that fit the workspace, tile lists per chunk. Reports
  * the device metadata size in *meta_bytes. Host work only.
- * Errors: E_ARG, E_WORKSPACE (the largest submatrix does not fit). */
+ * Submatrices have at most NOLSM_MAX_ROWS rows (the extraction keeps a
+ * submatrix's whole FP64 column block in the 160 KB of LDS of one workgroup).
+ * Errors: E_ARG (also: a submatrix above NOLSM_MAX_ROWS rows), E_WORKSPACE
+ * (the largest submatrix does not fit). */
+#define NOLSM_MAX_ROWS 3008
 int nolsm_plan_configure(nolsm_plan *plan, const nolsm_solve_opts *opts,
                          size_t ws_bytes, size_t *meta_bytes);
 

@@ -21,6 +21,7 @@ SCHED_GRAPH, SCHED_STREAM, SCHED_PER_BUCKET, SCHED_PERSISTENT, SCHED_PIPELINE = 
 INV_CHOLESKY, INV_COUPLED_NS, INV_CHOLESKY_FP32, INV_CHOLESKY_APPLY_FP32 = 0, 1, 2, 3
 PLAN_COMBINE = 1
 NOALLOC_WS_BYTES = 64 << 20   # NOLSM_NOALLOC_WS_BYTES
+MAX_ROWS = 3008               # NOLSM_MAX_ROWS
 MLP_NFEAT = 12
 MLP_NPARAM = 5122
 

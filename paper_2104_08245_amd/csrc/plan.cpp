@@ -454,8 +454,8 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
         };
         const uint64_t mask = opts->ns_small_tile_mask;
         auto tile_of = [&](int32_t J) { return nolsm_ns_tile_for(opts->prec, np_of(J), mask); };
-        if ((size_t)pl->g_m_max * bs > 4032) {
-            nolsm_set_last_error("submatrices above 4032 rows are not supported");
+        if ((size_t)pl->g_m_max * bs > NOLSM_MAX_ROWS) {
+            nolsm_set_last_error("submatrices above " + std::to_string(NOLSM_MAX_ROWS) + " rows are not supported");
             return NOLSM_E_ARG;
         }
         // order: decreasing np (largest-first keeps the tail short), then J

@@ -303,3 +303,25 @@ def test_noalloc_refuses_plans_beyond_its_array(L, box64):
     src = open(HEADER).read()
     m = re.search(r"#define NOLSM_NOALLOC_WS_BYTES \(\(size_t\)(\d+) << (\d+)\)", src)
     assert m and int(m.group(1)) << int(m.group(2)) == L.NOALLOC_WS_BYTES
+
+
+def test_largest_submatrix_limit(L):
+    # full cells: every submatrix is the whole matrix, 6 rows per molecule;
+    # 501 molecules give 3006 rows (accepted), 502 give 3012 (refused)
+    import synth
+    from paper_2104_08245_amd import Plan, NolsmError
+    src = open(HEADER).read()
+    m = re.search(r"#define NOLSM_MAX_ROWS (\d+)", src)
+    assert m and int(m.group(1)) == L.MAX_ROWS
+    for nmol, ok in ((501, True), (502, False)):
+        s = synth.water_cube(nmol, 2.2, config_id=111)
+        assert s.K.nnzb == nmol * nmol
+        p = Plan(s.K.nb, s.K.bs, s.K.row_ptr, s.K.col_idx)
+        opts = L.default_opts("fp16")
+        if ok:
+            p.configure(opts, 1 << 40)
+            assert p.info()["m_max"] * 6 == 3006 <= L.MAX_ROWS
+        else:
+            with pytest.raises(NolsmError) as e:
+                p.configure(opts, 1 << 40)
+            assert e.value.code == L.E_ARG

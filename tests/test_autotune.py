@@ -38,11 +38,11 @@ def test_mask_from_cache(tmp_path, box64):
 
 
 def test_committed_cache_is_well_formed():
-    from paper_2104_08245_amd import autotune as at
+    from paper_2104_08245_amd import autotune as at, _lib as L
     import os
     if not os.path.exists(at.CACHE):
         pytest.skip("no tile cache committed")
     for k, v in at.load_table().items():
         arch, prec, variant, npd = k.split("/")
         assert arch == at.ARCH and prec in ("fp16", "bf16") and variant in ("sym", "plain")
-        assert int(npd) % 64 == 0 and 64 <= int(npd) <= 4032 and v in (64, 128)
+        assert int(npd) % 64 == 0 and 64 <= int(npd) <= L.MAX_ROWS and v in (64, 128)
