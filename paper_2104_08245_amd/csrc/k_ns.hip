@@ -464,6 +464,36 @@ __global__ __launch_bounds__(256, 3) void k_ns_lp_pq(ChunkDev cd, const uint32_t
     }
 }
 
+// Late iterations, when most submatrices have converged: a small grid in
+// which every workgroup scans its share of its XCD's task segment, 256
+// tasks at a time (one per thread), keeps the tasks whose submatrix is still
+// iterating and runs those tiles. A launch after convergence then costs one
+// scan instead of one dispatched workgroup per tile. The order in which the
+// kept tiles run does not matter: each writes only its own outputs.
+template <typename T, int BM, bool SYM>
+__global__ __launch_bounds__(256, 2) void k_ns_lp_tail(ChunkDev cd, const uint32_t *tasks, int ntask, char *ws,
+                                                    NsArgs na, int it, int mode) {
+    __shared__ uint32_t kept[256];
+    __shared__ int nkept;
+    const int x = blockIdx.x & 7, seg = ntask >> 3, g8 = gridDim.x >> 3, wb = blockIdx.x >> 3;
+    const int span = (seg + g8 - 1) / g8, lo = wb * span, hi = min(seg, lo + span);
+    for (int i0 = lo; i0 < hi; i0 += 256) {
+        if (threadIdx.x == 0) nkept = 0;
+        __syncthreads();
+        const int i = i0 + (int)threadIdx.x;
+        if (i < hi) {
+            const uint32_t task = tasks[x * seg + i];
+            if (task != NOLSM_TASK_NONE && !cd.ctl[task_slot(task)].done) kept[atomicAdd(&nkept, 1)] = task;
+        }
+        __syncthreads();
+        const int nk = nkept;
+        for (int k = 0; k < nk; ++k) ns_lp_tile<T, BM, SYM>(cd, kept[k], ws, na, it, mode);
+        __syncthreads();
+    }
+}
+// iterations from this one on take the scanning launch
+#define NS_TAIL_IT 16
+
 // queue counters of one launch: [iteration][half][tile class][XCD]
 static int *launch_queue(const ChunkDev &cd, int it, int mode, int cls) {
     return cd.queues + (((size_t)it * 2 + (mode - 1)) * 2 + cls) * 8;
@@ -483,6 +513,20 @@ static void launch_lp(const ChunkDev &cd, char *ws, const NsArgs &na, int it, in
         if (cd.n_ns64 > 0)
             hipLaunchKernelGGL((k_ns_lp_pq<T, 64, SYM>), dim3(persistent_grid(na, cd.n_ns64)), dim3(256), 0, st, cd,
                                cd.t_ns64, cd.n_ns64, launch_queue(cd, it, mode, 1), ws, na, it, mode);
+        return;
+    }
+    if (it >= NS_TAIL_IT) {
+        // four scanning workgroups per CU (2 x pgrid), at most one per task
+        auto grid = [&](int ntask) {
+            const int g = (2 * na.pgrid < ntask ? 2 * na.pgrid : ntask) / 8 * 8;
+            return g < 8 ? 8 : g;
+        };
+        if (cd.n_ns > 0)
+            hipLaunchKernelGGL((k_ns_lp_tail<T, 128, SYM>), dim3(grid(cd.n_ns)), dim3(256), 0, st, cd, cd.t_ns,
+                               cd.n_ns, ws, na, it, mode);
+        if (cd.n_ns64 > 0)
+            hipLaunchKernelGGL((k_ns_lp_tail<T, 64, SYM>), dim3(grid(cd.n_ns64)), dim3(256), 0, st, cd, cd.t_ns64,
+                               cd.n_ns64, ws, na, it, mode);
         return;
     }
     if (cd.n_ns > 0)

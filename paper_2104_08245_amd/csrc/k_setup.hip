@@ -74,22 +74,29 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
     bool poison = false;
     for (int o = 0; o < M.nown; ++o)
         poison |= (a == 0 && ga.own_J[M.own_off + o] == ga.poison_J);
-    for (int i = t; i < bs * np; i += 256) {
-        const int r = i / np, c = i - r * np;
-        // 64-tile row and column of this entry: the tiles that nothing
-        // downstream reads are not written
-        const int tr = (a * bs + r) >> 6, tc = c >> 6;
-        const bool wk = !ga.k_upper || tc >= tr, ws_ = !ga.s_lower || tc <= tr;
-        double vk = 0.0, vs = 0.0;
+    // thread t takes columns t, t + 256, ..: the block column and the CSR
+    // entries are found once per column, then its bs rows follow
+    for (int c = t; c < np; c += 256) {
+        int ek = -1, es = -1, cc = 0;
         if (c < n) {
-            const int b = c / bs, cc = c - b * bs;
-            const int ek = posK[b], es = posS[b];
+            const int b = c / bs;
+            cc = c - b * bs;
+            ek = posK[b];
+            es = posS[b];
+        }
+        const int tc = c >> 6;
+        for (int r = 0; r < bs; ++r) {
+            // 64-tile row and column of this entry: the tiles that nothing
+            // downstream reads are not written
+            const int tr = (a * bs + r) >> 6;
+            const bool wk = !ga.k_upper || tc >= tr, ws_ = !ga.s_lower || tc <= tr;
+            double vk = 0.0, vs = 0.0;
             if (wk && ek >= 0) vk = ga.Kval[(int64_t)ek * bb + r * bs + cc];
             if (ws_ && es >= 0) vs = ga.Sval[(int64_t)es * bb + r * bs + cc];
+            if (poison && r == 0 && c == 0) vs = -1.0;
+            if (wk) put_k((int64_t)(a * bs + r) * ldk + c, vk);
+            if (ws_) put_s((int64_t)(a * bs + r) * lds + c, vs);
         }
-        if (poison && i == 0) vs = -1.0;
-        if (wk) put_k((int64_t)(a * bs + r) * ldk + c, vk);
-        if (ws_) put_s((int64_t)(a * bs + r) * lds + c, vs);
     }
     // E tile: columns np..np+63 of the K buffer; owned molecule o (block
     // position q_o in the rows) has its unit columns at o bs .. o bs + bs - 1

@@ -511,3 +511,27 @@ def test_pipeline_schedule_bit_identical(torch, box64, prec, sym):
             s.synchronize()
             assert np.array_equal(sv.Dcols.cpu().numpy(), ref), (ws, rep)
         assert np.all(sv.host_stats()["status"] == 0)
+
+
+@pytest.mark.parametrize("sym", [1, 0])
+def test_late_iterations_on_scanning_launches(torch, box64, ref1, sym):
+    # a 10x smaller initial scale adds about log(10)/log(1.5) ~ 6 sign
+    # iterations, so every submatrix is still iterating when the launches
+    # switch to the scanning kernel (from iteration 16 on); the sign and the
+    # stop rule are unchanged, so the mixed bounds hold, and the per-tile work
+    # is the same on every schedule (the persistent one never scans)
+    from paper_2104_08245_amd import _lib as L
+    sv = solve(box64, "fp16", sym_sign=sym, debug_scale_mult=0.1, sched=L.SCHED_STREAM)
+    st = sv.host_stats()
+    assert np.all(st["status"] == 0)
+    assert st["iters"].min() >= 17, st["iters"].min()
+    dc = sv.host_dcols()
+    errs = np.array([rel(dc[J], ref1.Dcols[J]) for J in range(box64.nmol)])
+    dE = np.abs(st["energy_KD"] - ref1.E)
+    say(f"fp16 sym={sym} scale x0.1: iterations {st['iters'].min()}..{st['iters'].max()}, Dcols max "
+        f"{errs.max():.3e}, |dE| max {dE.max():.3e}")
+    assert errs.max() <= MIXED["fp16"]["dcols"] and dE.max() <= MIXED["fp16"]["energy"]
+    ref = sv.Dcols.cpu().numpy()
+    for sched in (L.SCHED_GRAPH, L.SCHED_PERSISTENT):
+        other = solve(box64, "fp16", sym_sign=sym, debug_scale_mult=0.1, sched=sched)
+        assert np.array_equal(other.Dcols.cpu().numpy(), ref), sched
