@@ -1005,13 +1005,15 @@ template <> __device__ __forceinline__ _Float16 cvt<_Float16>(double x) { return
 template <> __device__ __forceinline__ __bf16 cvt<__bf16>(double x) { return (__bf16)(float)x; }
 
 // SYM (the symmetric iteration on A~ = L^-1 K L^-T - mu I, 16-bit): only
-// tiles ti <= tj read A~; an off-diagonal tile also writes its transpose
-// (staged in LDS), and a diagonal tile takes its lower half from its upper
-// half, so X_0 is exactly symmetric and the FP64 tiles below the diagonal
-// are never read.
+// tiles ti <= tj read A~ (the task list holds no others); an off-diagonal
+// tile also writes its transpose (staged in LDS), and a diagonal tile takes
+// its lower half from its upper half, so X_0 is exactly symmetric and the
+// tiles below the diagonal are never read. The off-diagonal tiles go 8
+// consecutive values per thread and access (wide loads and 16-byte stores);
+// every value is c a rounded through FP32 as in the element loop.
 template <typename T, bool SYM>
 __global__ __launch_bounds__(256) void k_convert(ChunkDev cd, char *ws, int use_scale_g) {
-    __shared__ T tt[SYM ? 64 : 1][SYM ? 65 : 1];
+    __shared__ __attribute__((aligned(16))) T tt[SYM ? 64 : 1][SYM ? 72 : 1];
     const uint32_t task = xcd_task(cd.t_conv);
     if (task == NOLSM_TASK_NONE) return;
     const int s = task_slot(task), ti = task_a(task), tj = task_b(task);
@@ -1023,6 +1025,49 @@ __global__ __launch_bounds__(256) void k_convert(ChunkDev cd, char *ws, int use_
     const int n = M.n, np = M.np;
     T *X = (T *)(ws + M.offX0);
     const int64_t ldk = np + 64;
+    if constexpr (SYM && sizeof(T) == 2) {
+        if (ti < tj) {   // uniform per workgroup; every entry has r < q
+            const int t = threadIdx.x;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int rr = t >> 2, q0 = ((t & 3) + 4 * h) * 8;
+                const int r = ti * 64 + rr, qb = tj * 64 + q0;
+                const int64_t off = (int64_t)r * ldk + qb;
+                double a[8];
+                if (M.kf32) {
+                    const float4 *p = (const float4 *)((const float *)(ws + M.offK) + off);
+                    const float4 u = p[0], v = p[1];
+                    a[0] = u.x; a[1] = u.y; a[2] = u.z; a[3] = u.w; a[4] = v.x; a[5] = v.y; a[6] = v.z; a[7] = v.w;
+                } else {
+                    const double2 *p = (const double2 *)((const double *)(ws + M.offK) + off);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const double2 u = p[k];
+                        a[2 * k] = u.x;
+                        a[2 * k + 1] = u.y;
+                    }
+                }
+                uint16_t o[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const double v = (r < n && qb + k < n) ? c * a[k] : 0.0;
+                    const T x = cvt<T>(v);
+                    o[k] = __builtin_bit_cast(uint16_t, x);
+                    tt[q0 + k][rr] = x;
+                }
+                *(uint4 *)(X + (int64_t)r * M.ldx + qb) =
+                    make_uint4(o[0] | ((uint32_t)o[1] << 16), o[2] | ((uint32_t)o[3] << 16),
+                               o[4] | ((uint32_t)o[5] << 16), o[6] | ((uint32_t)o[7] << 16));
+            }
+            __syncthreads();
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int qq = t >> 2, r0 = ((t & 3) + 4 * h) * 8;
+                *(uint4 *)(X + (int64_t)(tj * 64 + qq) * M.ldx + ti * 64 + r0) = *(const uint4 *)&tt[qq][r0];
+            }
+            return;
+        }
+    }
     for (int f = threadIdx.x; f < 4096; f += 256) {
         const int r = ti * 64 + (f >> 6), q = tj * 64 + (f & 63);
         const int ra = (SYM && r > q) ? q : r, qa = (SYM && r > q) ? r : q;

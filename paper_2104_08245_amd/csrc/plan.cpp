@@ -571,8 +571,10 @@ extern "C" int nolsm_plan_configure(nolsm_plan *pl, const nolsm_solve_opts *opts
                 ch.max_np = std::max(ch.max_np, m.np);
                 ch.max_own = std::max(ch.max_own, m.nown);
                 for (int32_t c = 0; c <= m.P; ++c) ch.t_subst.push_back(NOLSM_TASK(s, c, 0));
+                // X_0 tiles: the symmetric route converts the upper ones (each
+                // also writes its mirror)
                 for (int32_t a = 0; a < m.P; ++a)
-                    for (int32_t b = 0; b < m.P; ++b) ch.t_conv.push_back(NOLSM_TASK(s, a, b));
+                    for (int32_t b = pl->sym ? a : 0; b < m.P; ++b) ch.t_conv.push_back(NOLSM_TASK(s, a, b));
                 // FP16/BF16 slots with 64-row tiles get their own list
                 std::vector<uint32_t> &tl =
                     (T == 64 && (pl->prec == NOLSM_FP16 || pl->prec == NOLSM_BF16)) ? ch.t_ns64 : ch.t_ns;
