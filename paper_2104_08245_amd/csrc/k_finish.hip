@@ -276,34 +276,58 @@ static_assert(sizeof(MolStatsDev) == sizeof(nolsm_mol_stats), "stats layout");
 // Symmetric sign iteration: Df (np x bs in LDS) holds (y - sign(A~) y) / 2
 // with y = L^-1 E; the column block of D is L^-T of it. Backward
 // substitution over 64-row blocks with the factor and its diagonal-tile
-// inverses (FP64 arithmetic). Per block, thread (g, r) (g = t / 64 of 4
-// groups, r = t % 64) sums rows g, g + 4, .. of column i 64 + r of L against
-// all bs columns of the solved part (lanes read consecutive r: coalesced),
-// and the 4 partial sums meet in LDS. tmp: 4 x 64 x BSMAX doubles of LDS.
+// inverses (FP64 arithmetic). Per block i, thread (w, r, q) with wave w,
+// lane half r = l / 32 and column pair q = l % 32 sums rows 2 w + r,
+// 2 w + r + 8, .. of columns i 64 + 2 q, + 1 of L (one load of two values
+// per row) against all bs columns of the solved part; the two halves of a
+// wave meet by a lane shuffle and the four waves in LDS. tmp: 4 x 64 x BSMAX
+// doubles of LDS.
 template <typename TL>
 __device__ void back_solve_lt(const TL *L, const TL *Dinv, const SubMeta &M, double *Df, double *tmp, int bs) {
-    const int t = threadIdx.x, np = M.np, r = t & 63, g = t >> 6;
+    const int t = threadIdx.x, np = M.np, l = t & 63, w = t >> 6, q2 = (l & 31) * 2;
+    const int g = w * 2 + (l >> 5);   // row group 0..7
     for (int i = M.P - 1; i >= 0; --i) {
-        double a[BSMAX];
+        double a0[BSMAX], a1[BSMAX];
 #pragma unroll
-        for (int c = 0; c < BSMAX; ++c) a[c] = 0.0;
-        const TL *lc = L + i * 64 + r;   // column i 64 + r of L
+        for (int c = 0; c < BSMAX; ++c) a0[c] = a1[c] = 0.0;
+        const TL *lc = L + i * 64 + q2;   // columns i 64 + q2, + 1 of L
 #pragma unroll 4
-        for (int row = (i + 1) * 64 + g; row < np; row += 4) {
-            const double lv = (double)lc[(int64_t)row * np];
+        for (int row = (i + 1) * 64 + g; row < np; row += 8) {
+            double v0, v1;
+            if constexpr (sizeof(TL) == 4) {
+                const float2 x = *(const float2 *)(lc + (int64_t)row * np);
+                v0 = x.x; v1 = x.y;
+            } else {
+                const double2 x = *(const double2 *)(lc + (int64_t)row * np);
+                v0 = x.x; v1 = x.y;
+            }
 #pragma unroll
             for (int c = 0; c < BSMAX; ++c)
-                if (c < bs) a[c] += lv * Df[row * bs + c];
+                if (c < bs) {
+                    const double d = Df[row * bs + c];
+                    a0[c] += v0 * d;
+                    a1[c] += v1 * d;
+                }
         }
+        // the two row groups of the wave (lanes l and l ^ 32)
 #pragma unroll
-        for (int c = 0; c < BSMAX; ++c) tmp[(g * 64 + r) * BSMAX + c] = a[c];
+        for (int c = 0; c < BSMAX; ++c) {
+            a0[c] += __shfl_xor(a0[c], 32, 64);
+            a1[c] += __shfl_xor(a1[c], 32, 64);
+        }
+        if (l < 32)
+#pragma unroll
+            for (int c = 0; c < BSMAX; ++c) {
+                tmp[(w * 64 + q2) * BSMAX + c] = a0[c];
+                tmp[(w * 64 + q2 + 1) * BSMAX + c] = a1[c];
+            }
         __syncthreads();
         if (t < 64) {
 #pragma unroll
             for (int c = 0; c < BSMAX; ++c)
                 if (c < bs)
-                    tmp[r * BSMAX + c] = Df[(i * 64 + r) * bs + c] - tmp[r * BSMAX + c] - tmp[(64 + r) * BSMAX + c] -
-                                         tmp[(128 + r) * BSMAX + c] - tmp[(192 + r) * BSMAX + c];
+                    tmp[t * BSMAX + c] = Df[(i * 64 + t) * bs + c] - tmp[t * BSMAX + c] - tmp[(64 + t) * BSMAX + c] -
+                                         tmp[(128 + t) * BSMAX + c] - tmp[(192 + t) * BSMAX + c];
         }
         __syncthreads();
         for (int p = t; p < 64 * bs; p += 256) {
