@@ -439,7 +439,8 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(ns_tf, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(ns_tf / peak, 4), "traffic": measured_traffic(args.config, args.prec, sym, float(it.mean()),
                                                                     args.combine),
-                "kernel": ("k_ns_lp" + ("<sym>" if sym else "")) if args.prec in ("fp16", "bf16") else "k_ns64",
+                "kernel": (("k_ns_lp" + ("<sym>" if sym else "")) + " (k_ns_lp_tail from iteration 16)")
+                if args.prec in ("fp16", "bf16") else "k_ns64",
                 "launches": prof["n_ns_launches"],
                 "avg_launch_ms": round(prof["ms_ns"] / max(1, prof["n_ns_launches"]), 4)}
     phases = {k: round(v, 2) for k, v in prof.items()
