@@ -77,6 +77,28 @@ def test_w_kernel_is_the_exact_product(torch, box64, refw):
         assert rel(wc[J], ref) <= 1e-10
 
 
+@pytest.mark.parametrize("route", ["apply_fp32", "cholesky_fp32"])
+def test_w_from_the_fp32_k_buffer(torch, box64, refw, route):
+    # the routes whose substitution runs in FP32 keep A_J in FP32 in the K
+    # buffer: the W kernel's product then equals (A_J + mu I) Dcols_J from the
+    # oracle's A_J up to the FP32 rounding of A_J and of its FP32 solve
+    # (below 1e-5 relative here), and W stays within the FP16 bound
+    from paper_2104_08245_amd import _lib as L
+    inv = {"apply_fp32": L.INV_CHOLESKY_APPLY_FP32, "cholesky_fp32": L.INV_CHOLESKY_FP32}[route]
+    sv = solve_w(box64, "fp16", inverse=inv)
+    assert np.all(sv.host_stats()["status"] == 0)
+    dc, wc = sv.host_dcols(), sv.host_dcols("W")
+    worst = 0.0
+    for J in range(0, box64.nmol, 5):
+        _, A = refw.xs[J]
+        ref = (A + box64.mu * np.eye(A.shape[0])) @ dc[J]
+        worst = max(worst, rel(wc[J], ref))
+    errs = [rel(wc[J], refw.Wcols[J]) for J in range(box64.nmol)]
+    say(f"W {route}: product vs oracle A_J worst {worst:.3e}; W vs oracle max {max(errs):.3e}")
+    assert worst <= 1e-5
+    assert max(errs) <= 1e-2
+
+
 def test_w_fp16_within_stated_error(torch, box64, refw):
     sv = solve_w(box64, "fp16")
     wc = sv.host_dcols("W")
