@@ -218,7 +218,9 @@ def test_divergence_restarts_from_gershgorin(torch, box64, ref1):
     assert worst <= 1e-10
 
 
-@pytest.mark.parametrize("prec,kw", [("fp64", {}), ("fp16", {"sym_sign": 1})])
+@pytest.mark.parametrize("prec,kw", [("fp64", {}), ("fp16", {"sym_sign": 1}),
+                                     ("fp16", {"sym_sign": 1, "inverse": 3}),   # restart from the FP32 K buffer
+                                     ("bf16", {"sym_sign": 1, "inverse": 3})])
 def test_forced_stall_restarts_one_molecule(torch, box64, ref1, prec, kw):
     # the stall injected for molecule 11 is taken as divergence at iteration
     # 2: only that molecule restarts from the Gershgorin scale (fallback = 1)
@@ -232,7 +234,7 @@ def test_forced_stall_restarts_one_molecule(torch, box64, ref1, prec, kw):
     assert np.all(st["status"] == 0)
     ref = o.solve_molecule(box64, J, restart_at=2)
     dc = sv.host_dcols()
-    tol = 1e-10 if prec == "fp64" else MIXED["fp16"]["dcols"]
+    tol = 1e-10 if prec == "fp64" else MIXED[prec]["dcols"]
     assert rel(dc[J], ref.Dcols) <= tol
     assert rel(dc[J], ref1.Dcols[J]) <= tol
     # the others take the unperturbed iteration
