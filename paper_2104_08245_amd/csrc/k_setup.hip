@@ -1,11 +1,14 @@
-// FP64 setup of every submatrix: gather, Cholesky, substitution, bounds, X_0.
+// Setup of every submatrix: gather, Cholesky, substitution, bounds, X_0.
 //
 // Sec. III-B.2 (NOLSM generation step and Eq. purification_submatrix): the
 // submatrices T_J(K), T_J(S) are dense on the index list N(J); the sign
 // iteration acts on A_J = T_J(S)^-1 T_J(K) - mu I, and the owned columns of
 // T_J(D) need Y_J = T_J(S)^-1 E_cJ. Here T_J(S)^-1 is applied through an FP64
 // Cholesky factor (the paper's inverse is iterative; the FP64 factorisation
-// is this library's choice, for accuracy at these sizes).
+// is this library's choice, for accuracy at these sizes), with FP64 or, on
+// the 16-bit routes that ask for it, FP32 arithmetic in the substitutions;
+// the K buffer (K, then W, then A or A~ and Y) is stored in the type of that
+// arithmetic.
 #include "dev_common.h"
 #include "kernels.h"
 
