@@ -276,58 +276,41 @@ static_assert(sizeof(MolStatsDev) == sizeof(nolsm_mol_stats), "stats layout");
 // Symmetric sign iteration: Df (np x bs in LDS) holds (y - sign(A~) y) / 2
 // with y = L^-1 E; the column block of D is L^-T of it. Backward
 // substitution over 64-row blocks with the factor and its diagonal-tile
-// inverses (FP64 arithmetic). Per block i, thread (w, r, q) with wave w,
-// lane half r = l / 32 and column pair q = l % 32 sums rows 2 w + r,
-// 2 w + r + 8, .. of columns i 64 + 2 q, + 1 of L (one load of two values
-// per row) against all bs columns of the solved part; the two halves of a
-// wave meet by a lane shuffle and the four waves in LDS. tmp: 4 x 64 x BSMAX
-// doubles of LDS.
+// inverses (FP64 arithmetic). Per block i, the rows below the block are
+// taken off with the FP64 matrix cores: wave w forms the 16 columns
+// i 64 + 16 w .. + 15 of L^T times the solved rows of Df, four rows per
+// v_mfma_f64_16x16x4 (A from L, one value per lane; B from Df in LDS, its
+// bs columns padded to 16), four accumulators in turn; each wave owns its
+// columns, so no reduction across waves is needed. tmp: 64 x BSMAX doubles
+// of LDS (of 4 x 64 x BSMAX).
 template <typename TL>
 __device__ void back_solve_lt(const TL *L, const TL *Dinv, const SubMeta &M, double *Df, double *tmp, int bs) {
-    const int t = threadIdx.x, np = M.np, l = t & 63, w = t >> 6, q2 = (l & 31) * 2;
-    const int g = w * 2 + (l >> 5);   // row group 0..7
+    const int t = threadIdx.x, np = M.np, l = t & 63, w = t >> 6, mi = l & 15, kq = l >> 4;
     for (int i = M.P - 1; i >= 0; --i) {
-        double a0[BSMAX], a1[BSMAX];
+        v4d acc[4];
 #pragma unroll
-        for (int c = 0; c < BSMAX; ++c) a0[c] = a1[c] = 0.0;
-        const TL *lc = L + i * 64 + q2;   // columns i 64 + q2, + 1 of L
-#pragma unroll 4
-        for (int row = (i + 1) * 64 + g; row < np; row += 8) {
-            double v0, v1;
-            if constexpr (sizeof(TL) == 4) {
-                const float2 x = *(const float2 *)(lc + (int64_t)row * np);
-                v0 = x.x; v1 = x.y;
-            } else {
-                const double2 x = *(const double2 *)(lc + (int64_t)row * np);
-                v0 = x.x; v1 = x.y;
-            }
+        for (int u = 0; u < 4; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+        const TL *lc = L + i * 64 + 16 * w + mi;   // column i 64 + 16 w + mi of L
+        // 32 rows per step (np - (i + 1) 64 is a multiple of 64): the eight
+        // loads of a step are issued before its products
+        for (int row0 = (i + 1) * 64; row0 < np; row0 += 32) {
+            double a[8], b[8];
 #pragma unroll
-            for (int c = 0; c < BSMAX; ++c)
-                if (c < bs) {
-                    const double d = Df[row * bs + c];
-                    a0[c] += v0 * d;
-                    a1[c] += v1 * d;
-                }
+            for (int u = 0; u < 8; ++u) a[u] = (double)lc[(int64_t)(row0 + 4 * u + kq) * np];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) b[u] = (mi < bs) ? Df[(row0 + 4 * u + kq) * bs + mi] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc[u & 3], 0, 0, 0);
         }
-        // the two row groups of the wave (lanes l and l ^ 32)
+        // element e of lane l: column 16 w + kq + 4 e of the block, RHS column mi
 #pragma unroll
-        for (int c = 0; c < BSMAX; ++c) {
-            a0[c] += __shfl_xor(a0[c], 32, 64);
-            a1[c] += __shfl_xor(a1[c], 32, 64);
-        }
-        if (l < 32)
-#pragma unroll
-            for (int c = 0; c < BSMAX; ++c) {
-                tmp[(w * 64 + q2) * BSMAX + c] = a0[c];
-                tmp[(w * 64 + q2 + 1) * BSMAX + c] = a1[c];
-            }
+        for (int e = 0; e < 4; ++e)
+            if (mi < bs) tmp[(16 * w + kq + 4 * e) * BSMAX + mi] = (acc[0][e] + acc[1][e]) + (acc[2][e] + acc[3][e]);
         __syncthreads();
         if (t < 64) {
 #pragma unroll
             for (int c = 0; c < BSMAX; ++c)
-                if (c < bs)
-                    tmp[t * BSMAX + c] = Df[(i * 64 + t) * bs + c] - tmp[t * BSMAX + c] - tmp[(64 + t) * BSMAX + c] -
-                                         tmp[(128 + t) * BSMAX + c] - tmp[(192 + t) * BSMAX + c];
+                if (c < bs) tmp[t * BSMAX + c] = Df[(i * 64 + t) * bs + c] - tmp[t * BSMAX + c];
         }
         __syncthreads();
         for (int p = t; p < 64 * bs; p += 256) {
