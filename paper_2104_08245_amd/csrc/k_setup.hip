@@ -24,6 +24,7 @@
 // are then written straight to HBM, coalesced along the row.
 // grid (max_m, nsub), 256 threads; dynamic LDS: 3 m ints.
 // ---------------------------------------------------------------------------
+#define GATHER_BSMAX 6   // largest block size (the plan refuses larger)
 __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArgs ga) {
     extern __shared__ int gsm[];
     const int s = blockIdx.y, a = blockIdx.x;
@@ -88,17 +89,29 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
             es = posS[b];
         }
         const int tc = c >> 6;
-        for (int r = 0; r < bs; ++r) {
-            // 64-tile row and column of this entry: the tiles that nothing
-            // downstream reads are not written
-            const int tr = (a * bs + r) >> 6;
-            const bool wk = !ga.k_upper || tc >= tr, ws_ = !ga.s_lower || tc <= tr;
-            double vk = 0.0, vs = 0.0;
-            if (wk && ek >= 0) vk = ga.Kval[(int64_t)ek * bb + r * bs + cc];
-            if (ws_ && es >= 0) vs = ga.Sval[(int64_t)es * bb + r * bs + cc];
-            if (poison && r == 0 && c == 0) vs = -1.0;
-            if (wk) put_k((int64_t)(a * bs + r) * ldk + c, vk);
-            if (ws_) put_s((int64_t)(a * bs + r) * lds + c, vs);
+        // all loads of the column first (the stores below may not move above
+        // them), then the stores; 64-tile row and column of each entry: the
+        // tiles that nothing downstream reads are not written
+        double vk[GATHER_BSMAX], vs[GATHER_BSMAX];
+#pragma unroll
+        for (int r = 0; r < GATHER_BSMAX; ++r) {
+            vk[r] = vs[r] = 0.0;
+            if (r < bs) {
+                const int tr = (a * bs + r) >> 6;
+                const bool wk = !ga.k_upper || tc >= tr, ws_ = !ga.s_lower || tc <= tr;
+                if (wk && ek >= 0) vk[r] = ga.Kval[(int64_t)ek * bb + r * bs + cc];
+                if (ws_ && es >= 0) vs[r] = ga.Sval[(int64_t)es * bb + r * bs + cc];
+            }
+        }
+        if (poison && c == 0) vs[0] = -1.0;
+#pragma unroll
+        for (int r = 0; r < GATHER_BSMAX; ++r) {
+            if (r < bs) {
+                const int tr = (a * bs + r) >> 6;
+                const bool wk = !ga.k_upper || tc >= tr, ws_ = !ga.s_lower || tc <= tr;
+                if (wk) put_k((int64_t)(a * bs + r) * ldk + c, vk[r]);
+                if (ws_) put_s((int64_t)(a * bs + r) * lds + c, vs[r]);
+            }
         }
     }
     // E tile: columns np..np+63 of the K buffer; owned molecule o (block
