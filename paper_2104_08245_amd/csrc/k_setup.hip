@@ -1084,10 +1084,21 @@ __global__ __launch_bounds__(256) void k_convert(ChunkDev cd, char *ws, int use_
             return;
         }
     }
-    for (int f = threadIdx.x; f < 4096; f += 256) {
+    // the 16 loads of a thread first (the stores into the workspace below
+    // may not move above them), then the conversions and stores
+    double a[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int f = threadIdx.x + 256 * k;
         const int r = ti * 64 + (f >> 6), q = tj * 64 + (f & 63);
         const int ra = (SYM && r > q) ? q : r, qa = (SYM && r > q) ? r : q;
-        const double v = (r < n && q < n) ? c * kbuf_get(M, ws, (int64_t)ra * ldk + qa) : (r == q ? 1.0 : 0.0);
+        a[k] = (r < n && q < n) ? kbuf_get(M, ws, (int64_t)ra * ldk + qa) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int f = threadIdx.x + 256 * k;
+        const int r = ti * 64 + (f >> 6), q = tj * 64 + (f & 63);
+        const double v = (r < n && q < n) ? c * a[k] : (r == q ? 1.0 : 0.0);
         const T x = cvt<T>(v);
         X[(int64_t)r * M.ldx + q] = x;
         if constexpr (SYM) tt[f & 63][f >> 6] = x;
