@@ -305,6 +305,9 @@ def main():
     ap.add_argument("--finish-rows", action="store_true",
                     help="FP16: the finishing products with the row-streaming vector kernel (one "
                          "launch per product) instead of the fused matrix-core kernel")
+    ap.add_argument("--subst-fp32", action="store_true",
+                    help="symmetric route with FP32 substitutions: their tile products on the FP32 "
+                         "matrix cores instead of the default split FP16 (hi/lo) products")
     ap.add_argument("--tiles", default="cache", choices=["cache", "tune", "default"],
                     help="16-bit NS tile per size bucket: the autotuned choices of the tile cache "
                          "(buckets it lacks keep the default), tune them now before the warm-up "
@@ -391,7 +394,7 @@ def main():
     tile_kw = {"ns_small_tile_mask": masks[bool(sym)][0]} if lowp else {}
     sv = Solver(system, prec=args.prec, device=dev, ws_budget=int(args.ws_gb * (1 << 30)), sched=sched,
                 inverse=inv, combine=args.combine, sym_sign=sym, finish_rows=1 if args.finish_rows else 0,
-                **tile_kw)
+                subst_fp32=1 if args.subst_fp32 else 0, **tile_kw)
     if args.want_w:
         sv.want_w()
     info = sv.plan.info()
@@ -489,6 +492,8 @@ def main():
                    "combined": bool(args.combine), "symmetric_sign": bool(sym), "submatrices": int(len(n)),
                    "finishing": "row kernel" if (args.finish_rows or args.prec == "bf16") else
                    ("fused matrix-core kernel" if args.prec == "fp16" else "none"),
+                   **({"substitution_products": "FP32 matrix cores" if args.subst_fp32 else
+                       "split FP16 (hi/lo) matrix cores"} if (sym and inv in (L.INV_CHOLESKY_APPLY_FP32, L.INV_CHOLESKY_FP32)) else {}),
                    **({"ns_tiles": tiles} if tiles else {}),
                    "parallelism": "single GPU"},
         "submatrices_per_s": round(system.nmol / (ms / 1e3), 1),

@@ -214,7 +214,16 @@ typedef struct {
                                 diverged after its residual at iteration 2, so
                                 the guard restarts it from the Gershgorin scale
                                 (fallback = 1, same result); -1: none        */
-    int32_t reserved_;       /* 0                                                */
+    int32_t subst_fp32;      /* sym_sign with FP32 substitutions (the FP32
+                                factor, or the FP64 factor applied in FP32):
+                                != 0 forms their tile products on the FP32
+                                matrix cores. The default 0 forms them on the
+                                FP16 matrix cores from operands split into
+                                FP16 high and low parts, hi*hi + hi*lo + lo*hi
+                                with FP32 accumulation (about 2^-22 relative
+                                per operand, K scaled by a power of two into
+                                FP16 range), far below the FP16 rounding of
+                                the iterate that follows.                      */
 } nolsm_solve_opts;
 
 /* Fills *o with the defaults above for precision `prec`. */

@@ -48,7 +48,7 @@ class SolveOpts(C.Structure):
                 ("ns_small_tile_mask", C.c_uint64), ("d_wcols", C.c_void_p),
                 ("inverse", C.c_int32), ("inv_max_iter", C.c_int32),
                 ("sym_sign", C.c_int32), ("finish_rows", C.c_int32),
-                ("debug_force_stall", C.c_int32), ("reserved_", C.c_int32)]
+                ("debug_force_stall", C.c_int32), ("subst_fp32", C.c_int32)]
 
 
 class MolStats(C.Structure):

@@ -216,7 +216,8 @@ static int enqueue_setup(const nolsm_plan *pl, const BatchArgs &b, const LaunchA
         if (prof) prof->mark(PH_CHOL);
         if ((e = launch_chol(cd, ws, fp32, st)) != hipSuccess) return hip_fail(e, "Cholesky launch");
         if (prof) prof->mark(PH_SUBST);
-        e = o.sym_sign ? launch_subst_sym(cd, ws, apply32, st) : launch_subst(cd, ws, apply32, st);
+        e = o.sym_sign ? launch_subst_sym(cd, ws, apply32, o.subst_fp32 == 0, st)
+                       : launch_subst(cd, ws, apply32, st);
         if (e != hipSuccess) return hip_fail(e, "substitution launch");
     }
     if (prof) prof->mark(PH_BOUNDS);

@@ -6,11 +6,13 @@
 // T_J(D) need Y_J = T_J(S)^-1 E_cJ. Here T_J(S)^-1 is applied through an FP64
 // Cholesky factor (the paper's inverse is iterative; the FP64 factorisation
 // is this library's choice, for accuracy at these sizes), with FP64 or, on
-// the 16-bit routes that ask for it, FP32 arithmetic in the substitutions;
+// the 16-bit routes that ask for it, FP32 arithmetic in the substitutions
+// (on the symmetric route by default as split FP16 products, split16.h);
 // the K buffer (K, then W, then A or A~ and Y) is stored in the type of that
 // arithmetic.
 #include "dev_common.h"
 #include "kernels.h"
+#include "split16.h"
 
 // ---------------------------------------------------------------------------
 // Gather (Sec. III-B.2, submatrix construction): block row a of T_J(K) and
@@ -80,6 +82,7 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
         poison |= (a == 0 && ga.own_J[M.own_off + o] == ga.poison_J);
     // thread t takes columns t, t + 256, ..: the block column and the CSR
     // entries are found once per column, then its bs rows follow
+    double kmx = 0.0;   // largest |K| entry this thread stores
     for (int c = t; c < np; c += 256) {
         int ek = -1, es = -1, cc = 0;
         if (c < n) {
@@ -105,6 +108,8 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
         }
         if (poison && c == 0) vs[0] = -1.0;
 #pragma unroll
+        for (int r = 0; r < GATHER_BSMAX; ++r) kmx = fmax(kmx, fabs(vk[r]));
+#pragma unroll
         for (int r = 0; r < GATHER_BSMAX; ++r) {
             if (r < bs) {
                 const int tr = (a * bs + r) >> 6;
@@ -113,6 +118,13 @@ __global__ __launch_bounds__(256) void k_gather(ChunkDev cd, char *ws, GatherArg
                 if (ws_) put_s((int64_t)(a * bs + r) * lds + c, vs[r]);
             }
         }
+    }
+    // max |T_J(K)| over the submatrix, as FP32 bits (non-negative floats
+    // order like their bit patterns): one atomic per wave
+    {
+        float v = (float)kmx;
+        for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+        if ((t & 63) == 0) atomicMax(&cd.ctl[s].kmax, __float_as_uint(v));
     }
     // E tile: columns np..np+63 of the K buffer; owned molecule o (block
     // position q_o in the rows) has its unit columns at o bs .. o bs + bs - 1
@@ -907,6 +919,233 @@ __global__ __launch_bounds__(256, OCC) void k_rsolve(ChunkDev cd, char *ws, int 
 }
 
 // ---------------------------------------------------------------------------
+// The two kernels above for the symmetric route with FP32 arithmetic, with
+// their tile products on the FP16 matrix cores as split hi + lo operands
+// (split16.h; about 2^-22 relative per operand, and the result feeds an FP16
+// iterate). Same task lists, loop order and in-place layout; the FP32
+// accumulators are written out through an FP32 LDS tile. The K columns are
+// operands scaled by the power of two sc of max |T_J(K)| (sc max |K| in
+// [1, 2)), which W = L^-1 K and A~ carry until they are stored; the E tile
+// (entries 0 and 1) is not scaled.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void acc_mul(AccT<float> &a, float f) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) a.c[i][j][e] *= f;
+}
+
+// [W | y] = L^-1 [K | E], column tile cc of one submatrix per task, the
+// column tiles of K to their diagonal row
+template <int SR, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_subst_hl(ChunkDev cd, char *ws) {
+    __shared__ __attribute__((aligned(16))) HLTile sA;   // L_ik (negated) or Dinv_i: A[m][k]
+    __shared__ __attribute__((aligned(16))) HLTile sB;   // W_k, k-major: B[k][n] = sB(n, k)
+    __shared__ float sF[64][LDP];
+    const uint32_t task = xcd_task(cd.t_subst);
+    if (task == NOLSM_TASK_NONE) return;
+    const int s = task_slot(task), cc = task_a(task);
+    const SubMeta M = cd.meta[s];
+    if (cd.ctl[s].status != NOLSM_MOL_OK) return;
+    const int P = M.P, np = M.np, n = M.n;
+    const int64_t ldl = np, ldk = np + 64;
+    const float *L = (const float *)(ws + (M.offL32 ? M.offL32 : M.offL));
+    const float *Dinv = (const float *)(ws + (M.offL32 ? M.offDinv32 : M.offDinv));
+    float *Kb = (float *)(ws + M.offK);
+    float sc = 1.0f, inv = 1.0f;
+    if (cc < P) hl_scale(__uint_as_float(cd.ctl[s].kmax), sc, inv);
+    auto Lt = [&](int r, int c) { return L + (int64_t)(r * 64) * ldl + c * 64; };
+    const int col0 = (cc < P) ? cc * 64 : np;
+    auto Bt = [&](int r) { return Kb + (int64_t)(r * 64) * ldk + col0; };
+    // a column tile of K stops at its diagonal row; the E tile starts at the
+    // row tile of its first owned block (the rows above stay zero)
+    const int Pr = (cc < P) ? cc + 1 : P;
+    const int i1 = (cc == P) ? (M.pmin * (n / M.m)) / 64 : 0;
+    for (int i0 = i1; i0 < Pr; i0 += SR) {
+        const int nr = min(SR, Pr - i0);
+        AccT<float> acc[SR];
+#pragma unroll
+        for (int r = 0; r < SR; ++r)
+            if (r < nr) {
+                g2acc(acc[r], Bt(i0 + r), ldk);
+                acc_mul(acc[r], sc);
+            }
+        if (i0 > i1) {
+            RegTile<float> pl;
+            g2r_tile(pl, Lt(i0, i1), ldl);
+            r2hl(sA, pl, -1.0f);
+            for (int k = i1; k < i0; ++k) {
+                g2hl_t(sB, Bt(k), ldk, sc);
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < SR; ++r) {
+                    if (r < nr) {
+                        const bool last_r = (r + 1 == nr);
+                        const int kn = last_r ? k + 1 : k, rn = last_r ? 0 : r + 1;
+                        const bool more = kn < i0;
+                        if (more) g2r_tile(pl, Lt(i0 + rn, kn), ldl);
+                        mma64_hl(acc[r], sA, sB);
+                        __syncthreads();
+                        if (more) r2hl(sA, pl, -1.0f);
+                        if (!last_r) __syncthreads();
+                    }
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < SR; ++r) {
+            if (r < nr) {
+                const int i = i0 + r;
+                g2hl(sA, Dinv + (int64_t)i * 4096, 64, 1.0f);
+                acc2hl_t(sB, acc[r], 1.0f);
+                __syncthreads();
+                AccT<float> o;
+                acc_zero(o);
+                mma64_hl(o, sA, sB);   // sc W_i
+                __syncthreads();
+                acc2hl_t(sB, o, 1.0f);   // kept for the rows below
+                acc_mul(o, inv);
+                acc2s(sF, o);
+                __syncthreads();
+                s2g_tile(Bt(i), ldk, sF);
+#pragma unroll
+                for (int r2 = r + 1; r2 < SR; ++r2) {
+                    if (r2 < nr) {
+                        g2hl(sA, Lt(i0 + r2, i), ldl, -1.0f);
+                        __syncthreads();
+                        mma64_hl(acc[r2], sA, sB);
+                        __syncthreads();
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
+// A~ = W L^-T, row block i per launch, the tiles j >= i (k_rsolve's scheme)
+template <int RR, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_rsolve_hl(ChunkDev cd, char *ws, int i) {
+    const double mu = ((const WsHeader *)ws)->mu;
+    __shared__ __attribute__((aligned(16))) HLTile sX;   // -sc X_ik, or sc times the tile before Dinv: A[m][k]
+    __shared__ __attribute__((aligned(16))) HLTile sL;   // L_jk or Dinv_j: B[k][n] = sL(n, k)
+    __shared__ float sF[64][LDP];
+    __shared__ double red[256];
+    const int s = blockIdx.x;
+    if (s >= cd.nsub) return;
+    const SubMeta M = cd.meta[s];
+    if (cd.ctl[s].status != NOLSM_MOL_OK) return;
+    const int P = M.P, np = M.np, n = M.n;
+    if (i >= P) return;
+    const int64_t ldl = np, ldk = np + 64;
+    const float *L = (const float *)(ws + (M.offL32 ? M.offL32 : M.offL));
+    const float *Dinv = (const float *)(ws + (M.offL32 ? M.offDinv32 : M.offDinv));
+    float *Kb = (float *)(ws + M.offK);
+    double *rowp = (double *)(ws + M.offRow);
+    float sc, inv;
+    hl_scale(__uint_as_float(cd.ctl[s].kmax), sc, inv);
+    auto Lt = [&](int r, int c) { return L + (int64_t)(r * 64) * ldl + c * 64; };
+    auto Xt = [&](int j) { return Kb + (int64_t)(i * 64) * ldk + j * 64; };   // tile (i, j), j >= i
+    auto Ut = [&](int k) { return Kb + (int64_t)(k * 64) * ldk + i * 64; };   // tile (k, i) = X_ik^T
+    auto load_x = [&](int k) {
+        if (k < i) g2hl_t(sX, Ut(k), ldk, -sc);
+        else g2hl(sX, Xt(k), ldk, -sc);
+    };
+    const int t = threadIdx.x;
+    double frob = 0.0;
+    for (int j0 = i; j0 < P; j0 += RR) {
+        const int nr = min(RR, P - j0);
+        AccT<float> acc[RR];
+#pragma unroll
+        for (int r = 0; r < RR; ++r)
+            if (r < nr) {
+                g2acc(acc[r], Xt(j0 + r), ldk);
+                acc_mul(acc[r], sc);
+            }
+        if (j0 > 0) {
+            RegTile<float> pl;
+            g2r_tile(pl, Lt(j0, 0), ldl);
+            r2hl(sL, pl, 1.0f);
+            for (int k = 0; k < j0; ++k) {
+                load_x(k);
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < RR; ++r) {
+                    if (r < nr) {
+                        const bool last_r = (r + 1 == nr);
+                        const int kn = last_r ? k + 1 : k, rn = last_r ? 0 : r + 1;
+                        const bool more = kn < j0;
+                        if (more) g2r_tile(pl, Lt(j0 + rn, kn), ldl);
+                        mma64_hl(acc[r], sX, sL);
+                        __syncthreads();
+                        if (more) r2hl(sL, pl, 1.0f);
+                        if (!last_r) __syncthreads();
+                    }
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+            if (r < nr) {
+                const int j = j0 + r;
+                g2hl(sL, Dinv + (int64_t)j * 4096, 64, 1.0f);
+                acc2hl(sX, acc[r], 1.0f);
+                __syncthreads();
+                AccT<float> o;
+                acc_zero(o);
+                mma64_hl(o, sX, sL);   // sc X_ij
+                __syncthreads();
+                acc2hl(sX, o, -1.0f);   // -sc X_ij for the tiles to its right
+                acc_mul(o, inv);
+                acc2s(sF, o);
+                __syncthreads();
+                {
+                    // bounds inputs of A~ - mu I, as in k_rsolve
+                    auto a = [&](int rr, int q) { return (double)sF[rr][q] - ((i == j && rr == q) ? mu : 0.0); };
+                    if (t < 64) {
+                        const int gr = i * 64 + t;
+                        double rs = 0.0;
+                        for (int q = 0; q < 64; ++q)
+                            if (j * 64 + q < n) rs += fabs(a(t, q));
+                        rowp[(int64_t)j * np + gr] = (gr < n) ? rs : 0.0;
+                    } else if (t < 128 && j > i) {
+                        const int gc = j * 64 + t - 64;
+                        double cs = 0.0;
+                        for (int rr = 0; rr < 64; ++rr)
+                            if (i * 64 + rr < n) cs += fabs(a(rr, t - 64));
+                        rowp[(int64_t)i * np + gc] = (gc < n) ? cs : 0.0;
+                    }
+                    double fs = 0.0;
+                    for (int f = t; f < 4096; f += 256) {
+                        const int rr = f >> 6, q = f & 63;
+                        if (i * 64 + rr < n && j * 64 + q < n) fs += a(rr, q) * a(rr, q);
+                    }
+                    frob += (j > i) ? 2.0 * fs : fs;
+                }
+                s2g_tile(Xt(j), ldk, sF);
+#pragma unroll
+                for (int r2 = r + 1; r2 < RR; ++r2) {
+                    if (r2 < nr) {
+                        g2hl(sL, Lt(j0 + r2, j), ldl, 1.0f);
+                        __syncthreads();
+                        mma64_hl(acc[r2], sX, sL);
+                        __syncthreads();
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if (t < 64) Kb[(int64_t)(i * 64 + t) * ldk + i * 64 + t] -= mu;
+    const double fsum = block_sum(frob, red);
+    if (t == 0) ((double *)(ws + M.offCol))[np + i] = fsum;
+}
+
+// ---------------------------------------------------------------------------
 // Bounds and scale (one workgroup per submatrix). Row and column Gershgorin
 // intervals of A_J; their intersection [G_lo, G_hi] encloses the (real)
 // spectrum, so c_G = 1/max(|G_lo|, |G_hi|) puts it inside [-1, 1], which
@@ -1118,7 +1357,7 @@ __global__ void k_init_ctl(ChunkDev cd) {
     SubCtl *c = cd.ctl + s;
     if (threadIdx.x == 0) {
         c->done = 0; c->iters = 0; c->status = NOLSM_MOL_OK; c->fallback = 0; c->restart_at = -1;
-        c->scale = 0; c->scale_g = 0; c->resid = 0;
+        c->scale = 0; c->scale_g = 0; c->resid = 0; c->kmax = 0;
     }
     for (int i = threadIdx.x; i < NOLSM_MAX_ITER_CAP; i += blockDim.x) c->rhist[i] = 0.0;
     if (s == 0)
@@ -1152,8 +1391,11 @@ hipError_t launch_chol(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st) 
     }
     return hipSuccess;
 }
-hipError_t launch_subst_sym(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st) {
-    if (fp32) {
+hipError_t launch_subst_sym(const ChunkDev &cd, char *ws, bool fp32, bool split16, hipStream_t st) {
+    const bool hl = fp32 && split16;
+    if (hl) {
+        hipLaunchKernelGGL((k_subst_hl<4, 2>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
+    } else if (fp32) {
         hipLaunchKernelGGL((k_subst<float, 4, 1, 3, true>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
     } else {
         hipLaunchKernelGGL((k_subst<double, 4, 1, 2, true>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
@@ -1162,7 +1404,8 @@ hipError_t launch_subst_sym(const ChunkDev &cd, char *ws, bool fp32, hipStream_t
     // row blocks in order: block i reads the finished blocks k < i
     const int pmax = cd.max_np / 64;
     for (int i = 0; i < pmax; ++i) {
-        if (fp32) hipLaunchKernelGGL((k_rsolve<float, 4, 3>), dim3(cd.nsub), dim3(256), 0, st, cd, ws, i);
+        if (hl) hipLaunchKernelGGL((k_rsolve_hl<4, 2>), dim3(cd.nsub), dim3(256), 0, st, cd, ws, i);
+        else if (fp32) hipLaunchKernelGGL((k_rsolve<float, 4, 3>), dim3(cd.nsub), dim3(256), 0, st, cd, ws, i);
         else hipLaunchKernelGGL((k_rsolve<double, 4, 2>), dim3(cd.nsub), dim3(256), 0, st, cd, ws, i);
         LAUNCH_CHECK();
     }

@@ -87,7 +87,7 @@ hipError_t launch_inverse(const ChunkDev &cd, char *ws, const InvArgs &ia, hipSt
 hipError_t launch_chol(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st);
 hipError_t launch_subst(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st);
 // symmetric sign iteration: [W | y] = L^-1 [K | E], then A~ = W L^-T - mu I in place
-hipError_t launch_subst_sym(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st);
+hipError_t launch_subst_sym(const ChunkDev &cd, char *ws, bool fp32, bool split16, hipStream_t st);
 hipError_t launch_set_header(char *ws, double mu, hipStream_t st);
 int finish_launches(const FinishArgs &fa);
 hipError_t launch_trace_sums(const void *stats, int32_t nb, char *ws, hipStream_t st);

@@ -57,7 +57,8 @@ struct SubCtl {
     int32_t status;     // NOLSM_MOL_*
     int32_t fallback;   // Gershgorin restart used
     int32_t restart_at; // iteration of the restart, -1 if none
-    int32_t pad_[3];
+    uint32_t kmax;      // bits of max |T_J(K)| (FP32, non-negative), from the gather
+    int32_t pad_[2];
     double scale;       // c_J actually used
     double scale_g;     // Gershgorin scale 1/rho_G
     double resid;       // residual of the returned iterate

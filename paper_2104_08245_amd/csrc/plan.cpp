@@ -340,7 +340,7 @@ extern "C" void nolsm_default_opts(nolsm_solve_opts *o, int32_t prec) {
     o->sym_sign = 0;
     o->finish_rows = 0;
     o->debug_force_stall = -1;
-    o->reserved_ = 0;
+    o->subst_fp32 = 0;
 }
 
 extern "C" int nolsm_plan_info(const nolsm_plan *p, nolsm_plan_sizes *o) {

@@ -80,34 +80,39 @@ def test_symmetric_within_stated_error(torch, box64, ref1, prec):
     assert np.all(np.abs(st["iters"] - on_a.host_stats()["iters"]) <= 2)
 
 
-def test_symmetric_on_fp32_factor(torch, box64, ref1):
+@pytest.mark.parametrize("subst_fp32", [0, 1])
+def test_symmetric_on_fp32_factor(torch, box64, ref1, subst_fp32):
     from paper_2104_08245_amd import _lib as L
-    check_mixed(solve(box64, "fp16", inverse=L.INV_CHOLESKY_FP32), ref1, box64.nmol, "fp16",
-                "fp16 symmetric, FP32 factor")
+    check_mixed(solve(box64, "fp16", inverse=L.INV_CHOLESKY_FP32, subst_fp32=subst_fp32), ref1, box64.nmol,
+                "fp16", f"fp16 symmetric, FP32 factor, subst_fp32={subst_fp32}")
 
 
-@pytest.mark.parametrize("prec", ["fp16", "bf16"])
-def test_symmetric_on_fp64_factor_applied_in_fp32(torch, box64, ref1, prec):
+@pytest.mark.parametrize("prec,subst_fp32", [("fp16", 0), ("bf16", 0), ("fp16", 1), ("bf16", 1)])
+def test_symmetric_on_fp64_factor_applied_in_fp32(torch, box64, ref1, prec, subst_fp32):
+    # the FP32 substitutions as split FP16 products (default) or on the FP32
+    # matrix cores (subst_fp32)
     from paper_2104_08245_amd import _lib as L
-    check_mixed(solve(box64, prec, inverse=L.INV_CHOLESKY_APPLY_FP32), ref1, box64.nmol, prec,
-                f"{prec} symmetric, FP64 factor applied in FP32")
+    check_mixed(solve(box64, prec, inverse=L.INV_CHOLESKY_APPLY_FP32, subst_fp32=subst_fp32), ref1, box64.nmol,
+                prec, f"{prec} symmetric, FP64 factor applied in FP32, subst_fp32={subst_fp32}")
 
 
 def test_fp64_factor_applied_in_fp32_outside_spectrum(torch, box64):
     # sign = -I above the spectrum: Dcols = S_J^-1 E_cJ, formed through the
     # FP32 copy of the factor (y = L^-1 E) and the FP64 factor (L^-T); the
-    # FP32 application costs about kappa(L) 2^-24 relative
+    # FP32 application costs about kappa(L) 2^-24 relative (split FP16
+    # products, the symmetric route's default: about kappa(L) 2^-22)
     from paper_2104_08245_amd import _lib as L
+    from paper_2104_08245_amd import Solver
     Js = list(range(0, box64.nmol, 7))
     hi = o.nolsm(box64, mu=50.0, molecules=Js)
-    for sym in (1, 0):
-        from paper_2104_08245_amd import Solver
-        sv = Solver(box64, prec="fp16", device="cuda:0", sym_sign=sym, inverse=L.INV_CHOLESKY_APPLY_FP32)
+    for sym, subst_fp32 in ((1, 0), (1, 1), (0, 0)):
+        sv = Solver(box64, prec="fp16", device="cuda:0", sym_sign=sym, inverse=L.INV_CHOLESKY_APPLY_FP32,
+                    subst_fp32=subst_fp32)
         sv.run(mu=50.0)
         torch.cuda.synchronize()
         dc = sv.host_dcols()
         worst = max(rel(dc[J], hi.Dcols[J]) for J in Js)
-        say(f"FP64 factor applied in FP32, sym={sym}, mu=50: worst rel-F {worst:.3e}")
+        say(f"FP64 factor applied in FP32, sym={sym}, subst_fp32={subst_fp32}, mu=50: worst rel-F {worst:.3e}")
         assert worst <= 1e-5
 
 
