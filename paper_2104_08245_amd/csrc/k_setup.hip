@@ -1393,8 +1393,11 @@ hipError_t launch_chol(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st) 
 }
 hipError_t launch_subst_sym(const ChunkDev &cd, char *ws, bool fp32, bool split16, hipStream_t st) {
     const bool hl = fp32 && split16;
+    // split products: two row tiles per pass fit three workgroups per CU
+    // without spills (faster than four at two per CU); the right solve keeps
+    // four column tiles at two per CU (three per CU spill, and ran 16% slower)
     if (hl) {
-        hipLaunchKernelGGL((k_subst_hl<4, 2>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
+        hipLaunchKernelGGL((k_subst_hl<2, 3>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
     } else if (fp32) {
         hipLaunchKernelGGL((k_subst<float, 4, 1, 3, true>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
     } else {
