@@ -919,14 +919,13 @@ __global__ __launch_bounds__(256, OCC) void k_rsolve(ChunkDev cd, char *ws, int 
 }
 
 // ---------------------------------------------------------------------------
-// The two kernels above for the symmetric route with FP32 arithmetic, with
-// their tile products on the FP16 matrix cores as split hi + lo operands
-// (split16.h; about 2^-22 relative per operand, and the result feeds an FP16
-// iterate). Same task lists, loop order and in-place layout; the FP32
-// accumulators are written out through an FP32 LDS tile. The K columns are
-// operands scaled by the power of two sc of max |T_J(K)| (sc max |K| in
-// [1, 2)), which W = L^-1 K and A~ carry until they are stored; the E tile
-// (entries 0 and 1) is not scaled.
+// k_subst's forward pass and k_rsolve for the symmetric route with FP32
+// arithmetic, with their tile products on the FP16 matrix cores as split
+// hi + lo operands (split16.h; about 2^-22 relative per operand, and the
+// result feeds an FP16 iterate). The FP32 accumulators are written out
+// through an FP32 LDS tile. The K columns are operands scaled by the power
+// of two sc of max |T_J(K)| (sc max |K| in [1, 2)), which W = L^-1 K and A~
+// carry until they are stored; the E tile (entries 0 and 1) is not scaled.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void acc_mul(AccT<float> &a, float f) {
 #pragma unroll
@@ -1026,12 +1025,18 @@ __global__ __launch_bounds__(256, OCC) void k_subst_hl(ChunkDev cd, char *ws) {
     }
 }
 
-// A~ = W L^-T, row block i per launch, the tiles j >= i (k_rsolve's scheme)
-template <int RR, int OCC>
-__global__ __launch_bounds__(256, OCC) void k_rsolve_hl(ChunkDev cd, char *ws, int i) {
+// A~ = W L^-T, two row blocks (i, i + 1) per launch: every tile of the factor
+// that the launch reads serves both rows, so the factor's lower triangle is
+// read half as often as with one row block per launch. First the three
+// tiles (i, i), (i, i + 1), (i + 1, i + 1), in that order (row i + 1 needs
+// X_{i+1,i} = X_{i,i+1}^T); then passes of RC column tiles j >= i + 2 with
+// both rows' accumulators in registers.
+template <int RC, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_rsolve2_hl(ChunkDev cd, char *ws, int i) {
     const double mu = ((const WsHeader *)ws)->mu;
-    __shared__ __attribute__((aligned(16))) HLTile sX;   // -sc X_ik, or sc times the tile before Dinv: A[m][k]
-    __shared__ __attribute__((aligned(16))) HLTile sL;   // L_jk or Dinv_j: B[k][n] = sL(n, k)
+    __shared__ __attribute__((aligned(16))) HLTile sXa;   // operands of row i
+    __shared__ __attribute__((aligned(16))) HLTile sXb;   // operands of row i + 1
+    __shared__ __attribute__((aligned(16))) HLTile sL;    // L_jk or Dinv_j: B[k][n] = sL(n, k)
     __shared__ float sF[64][LDP];
     __shared__ double red[256];
     const int s = blockIdx.x;
@@ -1040,6 +1045,7 @@ __global__ __launch_bounds__(256, OCC) void k_rsolve_hl(ChunkDev cd, char *ws, i
     if (cd.ctl[s].status != NOLSM_MOL_OK) return;
     const int P = M.P, np = M.np, n = M.n;
     if (i >= P) return;
+    const bool two = i + 1 < P;
     const int64_t ldl = np, ldk = np + 64;
     const float *L = (const float *)(ws + (M.offL32 ? M.offL32 : M.offL));
     const float *Dinv = (const float *)(ws + (M.offL32 ? M.offDinv32 : M.offDinv));
@@ -1048,101 +1054,185 @@ __global__ __launch_bounds__(256, OCC) void k_rsolve_hl(ChunkDev cd, char *ws, i
     float sc, inv;
     hl_scale(__uint_as_float(cd.ctl[s].kmax), sc, inv);
     auto Lt = [&](int r, int c) { return L + (int64_t)(r * 64) * ldl + c * 64; };
-    auto Xt = [&](int j) { return Kb + (int64_t)(i * 64) * ldk + j * 64; };   // tile (i, j), j >= i
-    auto Ut = [&](int k) { return Kb + (int64_t)(k * 64) * ldk + i * 64; };   // tile (k, i) = X_ik^T
-    auto load_x = [&](int k) {
-        if (k < i) g2hl_t(sX, Ut(k), ldk, -sc);
-        else g2hl(sX, Xt(k), ldk, -sc);
+    auto Dt = [&](int j) { return Dinv + (int64_t)j * 4096; };
+    auto Xt = [&](int r, int j) { return Kb + (int64_t)(r * 64) * ldk + j * 64; };   // stored for j >= r
+    // -sc X_{r,k} as an A operand: the stored tile, or for k < r the
+    // transpose of the stored tile (k, r)
+    auto load_x = [&](HLTile &dst, int r, int k) {
+        if (k < r) g2hl_t(dst, Xt(k, r), ldk, -sc);
+        else g2hl(dst, Xt(r, k), ldk, -sc);
     };
     const int t = threadIdx.x;
-    double frob = 0.0;
-    for (int j0 = i; j0 < P; j0 += RR) {
-        const int nr = min(RR, P - j0);
-        AccT<float> acc[RR];
+    double frob0 = 0.0, frob1 = 0.0;
+    // a final tile o = sc X_{r,j} (accumulator layout): the bounds inputs of
+    // A~ - mu I as in k_rsolve, and the FP32 store
+    auto emit = [&](const AccT<float> &o, int r, int j, double &frob) {
+        __syncthreads();
 #pragma unroll
-        for (int r = 0; r < RR; ++r)
-            if (r < nr) {
-                g2acc(acc[r], Xt(j0 + r), ldk);
-                acc_mul(acc[r], sc);
-            }
-        if (j0 > 0) {
-            RegTile<float> pl;
-            g2r_tile(pl, Lt(j0, 0), ldl);
-            r2hl(sL, pl, 1.0f);
-            for (int k = 0; k < j0; ++k) {
-                load_x(k);
-                __syncthreads();
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                for (int r = 0; r < RR; ++r) {
-                    if (r < nr) {
-                        const bool last_r = (r + 1 == nr);
-                        const int kn = last_r ? k + 1 : k, rn = last_r ? 0 : r + 1;
-                        const bool more = kn < j0;
-                        if (more) g2r_tile(pl, Lt(j0 + rn, kn), ldl);
-                        mma64_hl(acc[r], sX, sL);
-                        __syncthreads();
-                        if (more) r2hl(sL, pl, 1.0f);
-                        if (!last_r) __syncthreads();
-                    }
-                }
-            }
-            __syncthreads();
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) sF[acc_row<float>(bi, e)][acc_col(bj)] = o.c[bi][bj][e] * inv;
+        __syncthreads();
+        auto a = [&](int rr, int q) { return (double)sF[rr][q] - ((r == j && rr == q) ? mu : 0.0); };
+        if (t < 64) {
+            const int gr = r * 64 + t;
+            double rs = 0.0;
+            for (int q = 0; q < 64; ++q)
+                if (j * 64 + q < n) rs += fabs(a(t, q));
+            rowp[(int64_t)j * np + gr] = (gr < n) ? rs : 0.0;
+        } else if (t < 128 && j > r) {
+            const int gc = j * 64 + t - 64;
+            double cs = 0.0;
+            for (int rr = 0; rr < 64; ++rr)
+                if (r * 64 + rr < n) cs += fabs(a(rr, t - 64));
+            rowp[(int64_t)r * np + gc] = (gc < n) ? cs : 0.0;
         }
+        double fs = 0.0;
+        for (int f = t; f < 4096; f += 256) {
+            const int rr = f >> 6, q = f & 63;
+            if (r * 64 + rr < n && j * 64 + q < n) fs += a(rr, q) * a(rr, q);
+        }
+        frob += (j > r) ? 2.0 * fs : fs;
+        s2g_tile(Xt(r, j), ldk, sF);
+    };
+    // o = acc Dinv_j^T with acc staged in sXa
+    auto diag = [&](AccT<float> &o, const AccT<float> &acc, int j) {
+        g2hl(sL, Dt(j), 64, 1.0f);
+        acc2hl(sXa, acc, 1.0f);
+        __syncthreads();
+        acc_zero(o);
+        mma64_hl(o, sXa, sL);
+        __syncthreads();
+    };
+    {
+        AccT<float> a00, a01, a11, o;
+        g2acc(a00, Xt(i, i), ldk);
+        acc_mul(a00, sc);
+        if (two) {
+            g2acc(a01, Xt(i, i + 1), ldk);
+            acc_mul(a01, sc);
+            g2acc(a11, Xt(i + 1, i + 1), ldk);
+            acc_mul(a11, sc);
+        }
+        for (int k = 0; k < i; ++k) {
+            load_x(sXa, i, k);
+            if (two) load_x(sXb, i + 1, k);
+            g2hl(sL, Lt(i, k), ldl, 1.0f);
+            __syncthreads();
+            mma64_hl(a00, sXa, sL);
+            __syncthreads();
+            if (two) {
+                g2hl(sL, Lt(i + 1, k), ldl, 1.0f);
+                __syncthreads();
+                mma64_hl(a01, sXa, sL);
+                mma64_hl(a11, sXb, sL);
+                __syncthreads();
+            }
+        }
+        diag(o, a00, i);
+        emit(o, i, i, frob0);
+        if (two) {
+            acc2hl(sXa, o, -1.0f);
+            g2hl(sL, Lt(i + 1, i), ldl, 1.0f);
+            __syncthreads();
+            mma64_hl(a01, sXa, sL);   // - X_ii L_{i+1,i}^T
+            __syncthreads();
+            diag(o, a01, i + 1);
+            emit(o, i, i + 1, frob0);
+            acc2hl_t(sXb, o, -1.0f);   // -sc X_{i+1,i} = -sc X_{i,i+1}^T
+            g2hl(sL, Lt(i + 1, i), ldl, 1.0f);
+            __syncthreads();
+            mma64_hl(a11, sXb, sL);
+            __syncthreads();
+            diag(o, a11, i + 1);
+            emit(o, i + 1, i + 1, frob1);
+        }
+    }
+    if (two) {
+        for (int j0 = i + 2; j0 < P; j0 += RC) {
+            const int nr = min(RC, P - j0);
+            AccT<float> a0[RC], a1[RC];
 #pragma unroll
-        for (int r = 0; r < RR; ++r) {
-            if (r < nr) {
-                const int j = j0 + r;
-                g2hl(sL, Dinv + (int64_t)j * 4096, 64, 1.0f);
-                acc2hl(sX, acc[r], 1.0f);
-                __syncthreads();
-                AccT<float> o;
-                acc_zero(o);
-                mma64_hl(o, sX, sL);   // sc X_ij
-                __syncthreads();
-                acc2hl(sX, o, -1.0f);   // -sc X_ij for the tiles to its right
-                acc_mul(o, inv);
-                acc2s(sF, o);
-                __syncthreads();
-                {
-                    // bounds inputs of A~ - mu I, as in k_rsolve
-                    auto a = [&](int rr, int q) { return (double)sF[rr][q] - ((i == j && rr == q) ? mu : 0.0); };
-                    if (t < 64) {
-                        const int gr = i * 64 + t;
-                        double rs = 0.0;
-                        for (int q = 0; q < 64; ++q)
-                            if (j * 64 + q < n) rs += fabs(a(t, q));
-                        rowp[(int64_t)j * np + gr] = (gr < n) ? rs : 0.0;
-                    } else if (t < 128 && j > i) {
-                        const int gc = j * 64 + t - 64;
-                        double cs = 0.0;
-                        for (int rr = 0; rr < 64; ++rr)
-                            if (i * 64 + rr < n) cs += fabs(a(rr, t - 64));
-                        rowp[(int64_t)i * np + gc] = (gc < n) ? cs : 0.0;
-                    }
-                    double fs = 0.0;
-                    for (int f = t; f < 4096; f += 256) {
-                        const int rr = f >> 6, q = f & 63;
-                        if (i * 64 + rr < n && j * 64 + q < n) fs += a(rr, q) * a(rr, q);
-                    }
-                    frob += (j > i) ? 2.0 * fs : fs;
+            for (int r = 0; r < RC; ++r)
+                if (r < nr) {
+                    g2acc(a0[r], Xt(i, j0 + r), ldk);
+                    acc_mul(a0[r], sc);
+                    g2acc(a1[r], Xt(i + 1, j0 + r), ldk);
+                    acc_mul(a1[r], sc);
                 }
-                s2g_tile(Xt(j), ldk, sF);
+            {
+                __syncthreads();
+                RegTile<float> pl;
+                g2r_tile(pl, Lt(j0, 0), ldl);
+                r2hl(sL, pl, 1.0f);
+                for (int k = 0; k < j0; ++k) {
+                    load_x(sXa, i, k);
+                    load_x(sXb, i + 1, k);
+                    __syncthreads();
 #pragma unroll
-                for (int r2 = r + 1; r2 < RR; ++r2) {
-                    if (r2 < nr) {
-                        g2hl(sL, Lt(j0 + r2, j), ldl, 1.0f);
-                        __syncthreads();
-                        mma64_hl(acc[r2], sX, sL);
-                        __syncthreads();
+                    for (int r = 0; r < RC; ++r) {
+                        if (r < nr) {
+                            const bool last_r = (r + 1 == nr);
+                            const int kn = last_r ? k + 1 : k, rn = last_r ? 0 : r + 1;
+                            const bool more = kn < j0;
+                            if (more) g2r_tile(pl, Lt(j0 + rn, kn), ldl);
+                            mma64_hl(a0[r], sXa, sL);
+                            mma64_hl(a1[r], sXb, sL);
+                            __syncthreads();
+                            if (more) r2hl(sL, pl, 1.0f);
+                            if (!last_r) __syncthreads();
+                        }
                     }
                 }
                 __syncthreads();
+            }
+#pragma unroll
+            for (int r = 0; r < RC; ++r) {
+                if (r < nr) {
+                    const int j = j0 + r;
+                    AccT<float> o0, o1;
+                    g2hl(sL, Dt(j), 64, 1.0f);
+                    acc2hl(sXa, a0[r], 1.0f);
+                    acc2hl(sXb, a1[r], 1.0f);
+                    __syncthreads();
+                    acc_zero(o0);
+                    acc_zero(o1);
+                    mma64_hl(o0, sXa, sL);
+                    mma64_hl(o1, sXb, sL);
+                    __syncthreads();
+                    acc2hl(sXa, o0, -1.0f);   // read by the next products only after emit's barriers
+                    emit(o0, i, j, frob0);
+                    acc2hl(sXb, o1, -1.0f);
+                    emit(o1, i + 1, j, frob1);
+#pragma unroll
+                    for (int r2 = r + 1; r2 < RC; ++r2) {
+                        if (r2 < nr) {
+                            g2hl(sL, Lt(j0 + r2, j), ldl, 1.0f);
+                            __syncthreads();
+                            mma64_hl(a0[r2], sXa, sL);
+                            mma64_hl(a1[r2], sXb, sL);
+                            __syncthreads();
+                        }
+                    }
+                    __syncthreads();
+                }
             }
         }
     }
-    if (t < 64) Kb[(int64_t)(i * 64 + t) * ldk + i * 64 + t] -= mu;
-    const double fsum = block_sum(frob, red);
-    if (t == 0) ((double *)(ws + M.offCol))[np + i] = fsum;
+    // the row blocks are final: take mu off their diagonals
+    __syncthreads();
+    if (t < 64) {
+        Kb[(int64_t)(i * 64 + t) * ldk + i * 64 + t] -= mu;
+        if (two) Kb[(int64_t)((i + 1) * 64 + t) * ldk + (i + 1) * 64 + t] -= mu;
+    }
+    const double f0 = block_sum(frob0, red);
+    const double f1 = block_sum(frob1, red);
+    if (t == 0) {
+        ((double *)(ws + M.offCol))[np + i] = f0;
+        if (two) ((double *)(ws + M.offCol))[np + i + 1] = f1;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1394,8 +1484,11 @@ hipError_t launch_chol(const ChunkDev &cd, char *ws, bool fp32, hipStream_t st) 
 hipError_t launch_subst_sym(const ChunkDev &cd, char *ws, bool fp32, bool split16, hipStream_t st) {
     const bool hl = fp32 && split16;
     // split products: two row tiles per pass fit three workgroups per CU
-    // without spills (faster than four at two per CU); the right solve keeps
-    // four column tiles at two per CU (three per CU spill, and ran 16% slower)
+    // without spills (faster than four at two per CU). The right solve takes
+    // two row blocks per launch at two workgroups per CU (it spills a little
+    // there; at one per CU without spills the phase took 32% longer); with
+    // one row block per launch it read the factor twice as often and the
+    // phase took 9% longer.
     if (hl) {
         hipLaunchKernelGGL((k_subst_hl<2, 3>), dim3(cd.n_subst), dim3(256), 0, st, cd, ws);
     } else if (fp32) {
@@ -1406,9 +1499,15 @@ hipError_t launch_subst_sym(const ChunkDev &cd, char *ws, bool fp32, bool split1
     LAUNCH_CHECK();
     // row blocks in order: block i reads the finished blocks k < i
     const int pmax = cd.max_np / 64;
+    if (hl) {
+        for (int i = 0; i < pmax; i += 2) {
+            hipLaunchKernelGGL((k_rsolve2_hl<2, 2>), dim3(cd.nsub), dim3(256), 0, st, cd, ws, i);
+            LAUNCH_CHECK();
+        }
+        return hipSuccess;
+    }
     for (int i = 0; i < pmax; ++i) {
-        if (hl) hipLaunchKernelGGL((k_rsolve_hl<4, 2>), dim3(cd.nsub), dim3(256), 0, st, cd, ws, i);
-        else if (fp32) hipLaunchKernelGGL((k_rsolve<float, 4, 3>), dim3(cd.nsub), dim3(256), 0, st, cd, ws, i);
+        if (fp32) hipLaunchKernelGGL((k_rsolve<float, 4, 3>), dim3(cd.nsub), dim3(256), 0, st, cd, ws, i);
         else hipLaunchKernelGGL((k_rsolve<double, 4, 2>), dim3(cd.nsub), dim3(256), 0, st, cd, ws, i);
         LAUNCH_CHECK();
     }
