@@ -68,15 +68,20 @@ def test_isolated_molecules_fp64(isolated, isolated_ref):
     assert np.allclose(st["trace_SD"], isolated_ref.N, rtol=0, atol=1e-10)
 
 
-@pytest.mark.parametrize("prec,sym", [("fp16", 1), ("fp16", 0), ("bf16", 1)])
-def test_isolated_molecules_mixed(isolated, isolated_ref, prec, sym):
-    sv = solve(isolated, prec, sym_sign=sym)
+@pytest.mark.parametrize("prec,sym,apply32", [("fp16", 1, 0), ("fp16", 0, 0), ("bf16", 1, 0), ("fp16", 1, 1),
+                                              ("bf16", 1, 1)])
+def test_isolated_molecules_mixed(isolated, isolated_ref, prec, sym, apply32):
+    # one 64-row tile per submatrix; apply32: the FP64 factor applied in FP32
+    # (on the symmetric route as split FP16 products)
+    from paper_2104_08245_amd import _lib as L
+    kw = {"inverse": L.INV_CHOLESKY_APPLY_FP32} if apply32 else {}
+    sv = solve(isolated, prec, sym_sign=sym, **kw)
     st = sv.host_stats()
     assert np.all(st["status"] == 0)
     dc = sv.host_dcols()
     errs = np.array([rel(dc[J], isolated_ref.Dcols[J]) for J in range(isolated.nmol)])
     de = np.abs(st["energy_KD"] - isolated_ref.E)
-    say(f"isolated {prec} sym={sym}: Dcols max {errs.max():.3e}; |dE| max {de.max():.3e}")
+    say(f"isolated {prec} sym={sym} apply32={apply32}: Dcols max {errs.max():.3e}; |dE| max {de.max():.3e}")
     assert errs.max() <= MIXED[prec]["dcols"] and de.max() <= MIXED[prec]["energy"]
 
 

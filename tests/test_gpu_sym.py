@@ -136,10 +136,15 @@ def test_symmetric_outside_spectrum_is_exact(torch, box64):
     assert np.abs(sv.Dcols.cpu().numpy()).max() <= 1e-5 * max(np.abs(d).max() for d in dc)
 
 
-def test_symmetric_combined(torch, box64):
-    sv = solve(box64, "fp16", combine=True)
+@pytest.mark.parametrize("route", ["cholesky", "apply_fp32"])
+def test_symmetric_combined(torch, box64, route):
+    # combined submatrices (several owned molecules, larger n), with the FP64
+    # application and with the FP32 one as split FP16 products
+    from paper_2104_08245_amd import _lib as L
+    inv = {"cholesky": L.INV_CHOLESKY, "apply_fp32": L.INV_CHOLESKY_APPLY_FP32}[route]
+    sv = solve(box64, "fp16", combine=True, inverse=inv)
     ref = o.nolsm_groups(box64, sv.plan.groups())
-    check_mixed(sv, ref, box64.nmol, "fp16", "fp16 symmetric combined")
+    check_mixed(sv, ref, box64.nmol, "fp16", f"fp16 symmetric combined, {route}")
 
 
 @pytest.mark.parametrize("prec", ["fp16"])
