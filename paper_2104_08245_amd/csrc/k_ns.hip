@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void k_ns64_pq(ChunkDev cd, int ntask, int *q,
 // tile at row c, column r. Each lane holds 4 consecutive rows of one column
 // per group of 4 accumulator elements: one 8-byte store each.
 template <int BM> __device__ __forceinline__ int sym_idx(int row, int col) {
-    return row * BM + ((((col >> 3) ^ row) & (BM / 8 - 1)) << 3) + (col & 7);
+    return row * BM + ((((col >> 3) ^ row ^ (row >> 3)) & (BM / 8 - 1)) << 3) + (col & 7);
 }
 template <int BM, typename Val> __device__ __forceinline__ void sym_stage(Val val) {
     constexpr int WT = BM / 2, NB = WT / 32;
@@ -272,6 +272,55 @@ template <int BM> __device__ __forceinline__ void sym_store_mirror(uint16_t *X, 
     for (int f = threadIdx.x; f < BM * NCH; f += 256) {
         const int cl = f / NCH, ch = f % NCH;
         *(uint4 *)(X + (int64_t)(col0 + cl) * ldx + row0 + ch * 8) = *(const uint4 *)(st + sym_idx<BM>(cl, ch * 8));
+    }
+}
+// off-diagonal tile (ti, tj) itself from the staged copy of its transpose:
+// each thread reads an 8 x 8 block (eight 16-byte reads of copy rows),
+// transposes it in registers and writes eight 16-byte row segments, so the
+// 16 threads of a block row store 256 contiguous bytes of each tile row
+// (the row ^ (row >> 3) term of sym_idx spreads the eight copy rows a
+// block read touches, 8 apart, over all chunk positions)
+template <int BM> __device__ __forceinline__ void sym_store_direct(uint16_t *X, int ldx, int row0, int col0) {
+    constexpr int NB8 = BM / 8;
+    const uint16_t *st = lp_lds<BM>();
+    for (int b = threadIdx.x; b < NB8 * NB8; b += 256) {
+        const int r0 = (b / NB8) * 8, c0 = (b % NB8) * 8;
+        uint4 v[8];   // v[q] = T[r0 .. r0 + 7][c0 + q]
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = *(const uint4 *)(st + sym_idx<BM>(c0 + q, r0));
+        auto dw = [](const uint4 &x, int d) { return d == 0 ? x.x : d == 1 ? x.y : d == 2 ? x.z : x.w; };
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            uint32_t o[4];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const uint32_t a = dw(v[2 * d], p >> 1), c = dw(v[2 * d + 1], p >> 1);
+                o[d] = (p & 1) ? ((a >> 16) | (c & 0xFFFF0000u)) : ((a & 0xFFFFu) | (c << 16));
+            }
+            *(uint4 *)(X + (int64_t)(row0 + r0 + p) * ldx + col0 + c0) = make_uint4(o[0], o[1], o[2], o[3]);
+        }
+    }
+}
+// A BM x BM tile of X_k into LDS as it stands (16-byte row loads), the
+// 16-byte chunk c of row r at chunk position c ^ 4 ((r / 4) % (BM / 32)):
+// the accumulator-layout reads (32 consecutive columns of one row, and of
+// the row 4 below) then fall on distinct banks
+template <int BM> __device__ __forceinline__ int dir_idx(int r, int c) {
+    return r * BM + ((((c >> 3) ^ (((r >> 2) & (BM / 32 - 1)) << 2))) << 3) + (c & 7);
+}
+template <int BM> __device__ __forceinline__ void dir_load(const uint16_t *X, int ldx, int row0, int col0) {
+    constexpr int NCH = BM / 8, NQ = BM * NCH / 256;
+    uint16_t *st = lp_lds<BM>();
+    uint4 v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int f = threadIdx.x + q * 256, r = f / NCH, ch = f % NCH;
+        v[q] = *(const uint4 *)(X + (int64_t)(row0 + r) * ldx + col0 + ch * 8);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int f = threadIdx.x + q * 256, r = f / NCH, ch = f % NCH;
+        *(uint4 *)(st + dir_idx<BM>(r, ch * 8)) = v[q];
     }
 }
 // diagonal tile: X R (and X X^T up to rounding) is symmetric only in exact
@@ -377,31 +426,28 @@ __device__ __forceinline__ void ns_lp_tile(const ChunkDev &cd, uint32_t task, ch
             }
             Out = Bb;
         } else {
-            const __amdgpu_buffer_rsrc_t rsX = __builtin_amdgcn_make_buffer_rsrc((void *)Xc, (short)0, nrec, 0x00020000);
-#pragma unroll
-            for (int i = 0; i < NB; ++i)
-#pragma unroll
-                for (int j = 0; j < NB; ++j) {
-                    uint16_t xo[16];
-#pragma unroll
-                    for (int e = 0; e < 16; ++e)
-                        xo[e] = __builtin_amdgcn_raw_buffer_load_b16(rsX, eo, NS_EOFF(i, j, e), 0);
-#pragma unroll
-                    for (int e = 0; e < 16; ++e) acc[i][j][e] = Lp<T>::dec(xo[e]) + 0.5f * acc[i][j][e];
-                }
-            Out = Xn;
-        }
-        sym_stage<BM>([&](int i, int j, int e) { return Lp<T>::enc(acc[i][j][e]); });
-        __syncthreads();
-        if (ti != tj) {
-            const __amdgpu_buffer_rsrc_t rsO = __builtin_amdgcn_make_buffer_rsrc((void *)Out, (short)0, nrec, 0x00020000);
+            // X_k of the tile through LDS (the operand buffers are free
+            // again): 16-byte row loads, then each lane's elements
+            dir_load<BM>(Xc, ldx, row0, col0);
+            __syncthreads();
+            const uint16_t *xs = lp_lds<BM>();
 #pragma unroll
             for (int i = 0; i < NB; ++i)
 #pragma unroll
                 for (int j = 0; j < NB; ++j)
 #pragma unroll
-                    for (int e = 0; e < 16; ++e)
-                        __builtin_amdgcn_raw_buffer_store_b16(Lp<T>::enc(acc[i][j][e]), rsO, eo, NS_EOFF(i, j, e), 0);
+                    for (int e = 0; e < 16; ++e) {
+                        const int rl = wm * WT + i * 32 + (e >> 2) * 8 + (l >> 5) * 4 + (e & 3);
+                        const int cl = wn * WT + j * 32 + (l & 31);
+                        acc[i][j][e] = Lp<T>::dec(xs[dir_idx<BM>(rl, cl)]) + 0.5f * acc[i][j][e];
+                    }
+            __syncthreads();
+            Out = Xn;
+        }
+        sym_stage<BM>([&](int i, int j, int e) { return Lp<T>::enc(acc[i][j][e]); });
+        __syncthreads();
+        if (ti != tj) {
+            sym_store_direct<BM>(Out, ldx, row0, col0);
             sym_store_mirror<BM>(Out, ldx, row0, col0);
         } else {
             sym_store_diag<BM>(Out, ldx, row0);
