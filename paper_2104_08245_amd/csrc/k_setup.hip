@@ -1373,12 +1373,13 @@ __global__ __launch_bounds__(256) void k_convert(ChunkDev cd, char *ws, int use_
     if constexpr (SYM && sizeof(T) == 2) {
         if (ti < tj) {   // uniform per workgroup; every entry has r < q
             const int t = threadIdx.x;
+            // both halves' loads first (the stores below may not move above them)
+            double a2[2][8];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int rr = t >> 2, q0 = ((t & 3) + 4 * h) * 8;
-                const int r = ti * 64 + rr, qb = tj * 64 + q0;
-                const int64_t off = (int64_t)r * ldk + qb;
-                double a[8];
+                const int64_t off = (int64_t)(ti * 64 + rr) * ldk + tj * 64 + q0;
+                double *a = a2[h];
                 if (M.kf32) {
                     const float4 *p = (const float4 *)((const float *)(ws + M.offK) + off);
                     const float4 u = p[0], v = p[1];
@@ -1392,6 +1393,12 @@ __global__ __launch_bounds__(256) void k_convert(ChunkDev cd, char *ws, int use_
                         a[2 * k + 1] = u.y;
                     }
                 }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int rr = t >> 2, q0 = ((t & 3) + 4 * h) * 8;
+                const int r = ti * 64 + rr, qb = tj * 64 + q0;
+                const double *a = a2[h];
                 uint16_t o[8];
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
