@@ -454,9 +454,14 @@ __global__ __launch_bounds__(256, 4) void k_chol_diag(ChunkDev cd, char *ws, int
     if (threadIdx.x == 0) fail = 0;
     AccT<T> acc;
     g2acc(acc, Lt(j, j), ld);
+    // - L_jk L_jk^T over k < j, tile k + 1 loaded into registers while
+    // tile k is multiplied
+    RegTile<T> pl;
+    if (j > 0) g2r_tile(pl, Lt(j, 0), ld);
     for (int k = 0; k < j; ++k) {
-        g2s_tile(sA, Lt(j, k), ld);
+        r2s_tile(sA, pl);
         __syncthreads();
+        if (k + 1 < j) g2r_tile(pl, Lt(j, k + 1), ld);
         mma64<false, true>(acc, sA, sA, -1.0);
         __syncthreads();
     }
@@ -505,15 +510,26 @@ __global__ __launch_bounds__(256, OCC) void k_chol_panel(ChunkDev cd, char *ws, 
 #pragma unroll
     for (int r = 0; r < CHOL_PR; ++r)
         if (r < nr) g2acc(acc[r], Lt(i0 + r, j), ld);
+    // - L_ik L_jk^T over k < j: the row-j tile per k, and the row tiles one
+    // (k, r) step ahead in registers while the current one is multiplied
+    RegTile<T> pl;
+    if (j > 0) g2r_tile(pl, Lt(i0, 0), ld);
     for (int k = 0; k < j; ++k) {
         g2s_tile(sB, Lt(j, k), ld);
+        r2s_tile(sA, pl);
+        __syncthreads();
 #pragma unroll
         for (int r = 0; r < CHOL_PR; ++r) {
             if (r < nr) {
-                g2s_tile(sA, Lt(i0 + r, k), ld);
-                __syncthreads();
+                const bool last_r = (r + 1 == nr);
+                const int kn = last_r ? k + 1 : k, rn = last_r ? 0 : r + 1;
+                if (kn < j) g2r_tile(pl, Lt(i0 + rn, kn), ld);
                 mma64<false, true>(acc[r], sA, sB, -1.0);
                 __syncthreads();
+                if (!last_r) {
+                    r2s_tile(sA, pl);
+                    __syncthreads();
+                }
             }
         }
     }
