@@ -452,8 +452,9 @@ def main():
               and (k not in ("ms_chol", "ms_subst") or args.inverse != "coupled_ns")}
     # composite bound: each phase's algorithmic work at its own peak (NS GEMMs
     # on the MFMA peak of the precision, finishing products at the FP32 peak,
-    # the Cholesky + solves at the FP64 or FP32 peak of their route, the
-    # gather at 8 TB/s)
+    # the Cholesky + solves at the FP64 or FP32 peak of their route, FP32
+    # solves formed as split FP16 products (symmetric route) at a third of the
+    # FP16 peak, the gather at 8 TB/s)
     m = n / 6.0
     setup_flops = float((n ** 3 / 3.0 + 2.0 * n ** 3 + 12.0 * n ** 2).sum())
     gather_bytes = float((576.0 * m ** 2 + 288.0 * m).sum())
@@ -461,12 +462,15 @@ def main():
              "gather_scatter": gather_bytes / 8e12}
     if args.inverse == "coupled_ns":
         terms["inverse"] = inv_flops / (peak * 1e12)
-    elif args.inverse == "cholesky_fp32":
-        terms["setup_fp32"] = setup_flops / 157.3e12
-    elif args.inverse == "cholesky_apply_fp32":
+    elif args.inverse in ("cholesky_fp32", "cholesky_apply_fp32"):
         chol_flops = float((n ** 3 / 3.0).sum())
-        terms["setup_fp64_factor"] = chol_flops / 78.6e12
-        terms["setup_fp32_apply"] = (setup_flops - chol_flops) / 157.3e12
+        split = bool(sym) and not args.subst_fp32
+        apply_peak = 2500e12 / 3.0 if split else 157.3e12
+        if args.inverse == "cholesky_fp32":
+            terms["setup_fp32_factor"] = chol_flops / 157.3e12
+        else:
+            terms["setup_fp64_factor"] = chol_flops / 78.6e12
+        terms["setup_fp32_apply_split16" if split else "setup_fp32_apply"] = (setup_flops - chol_flops) / apply_peak
     else:
         terms["setup_fp64"] = setup_flops / 78.6e12
     t_bound = sum(terms.values())
