@@ -10,8 +10,7 @@
 // products at the FP16 rate (16x that of v_mfma_f32_16x16x4_f32). FP16 has
 // a narrow exponent range, so the caller scales an operand by a power of two
 // that brings its largest magnitude into [1, 2) (the pair then holds every
-// entry to 2^-25 absolute, 2^-22 relative for entries above 2^-3) and
-// divides the result by it.
+// entry x to within max(2^-22 |x|, 2^-25)) and divides the result by it.
 //
 // Tiles are 64 x 64 in LDS, row n holding 64 contraction values k, in hi
 // and lo planes: an MFMA operand (16 rows, 8 consecutive k per lane) is one

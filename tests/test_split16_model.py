@@ -4,10 +4,10 @@ FP32 substitutions use (a host model of the arithmetic, numpy only).
 Each FP32 operand x is held as hi = fp16(x) and lo = fp16(x - hi); a product
 is hi*hi + hi*lo + lo*hi with FP32 accumulation. With the operand scaled by
 a power of two so that its largest magnitude lies in [1, 2), the pair keeps
-x to 2^-25 absolute (half the FP16 subnormal spacing), which is 2^-22
-relative for |x| >= 2^-3, and a 64-deep tile product stays within a few
-2^-22 of the exact product, far below the FP16 rounding (2^-11) of the
-iterate that follows.
+x to within max(2^-22 |x|, 2^-25) (the second term is half the FP16
+subnormal spacing, reached by small entries), and a 64-deep tile product
+stays within a few 2^-22 of the exact product, far below the FP16 rounding
+(2^-11) of the iterate that follows.
 """
 import numpy as np
 
@@ -45,6 +45,11 @@ def test_pair_holds_22_bits_in_the_normal_range():
     hi, lo = split(x)
     err = np.abs(x.astype(np.float64) - hi.astype(np.float64) - lo.astype(np.float64))
     assert np.all(err <= 2.0 ** -22 * np.abs(x) * 1.0001)
+    # small entries: half the subnormal spacing
+    y = np.float32(2.0) ** rng.uniform(-20, -3, 20000).astype(np.float32)
+    yh, yl = split(y)
+    erry = np.abs(y.astype(np.float64) - yh.astype(np.float64) - yl.astype(np.float64))
+    assert np.all(erry <= np.maximum(2.0 ** -22 * y, 2.0 ** -25) * 1.0001)
     # hi alone would only hold 11 bits
     assert np.max(np.abs(x - hi.astype(np.float32)) / np.abs(x)) > 2.0 ** -13
 
